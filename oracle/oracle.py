@@ -1,0 +1,230 @@
+"""ctypes wrapper of the plain FP64 CPU oracle (exx_oracle.c).
+
+Test infrastructure only: imported by the tests, by the smoke check and by
+the benchmark's CPU-baseline leg.  The product path never imports it.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "exx_oracle.c")
+_LIB = os.path.join(_HERE, "libexx_oracle.so")
+NLM = 49
+
+_dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
+_ip = np.ctypeslib.ndpointer(dtype=np.int32, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (-O2, OpenMP)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=gnu11", "-fopenmp", "-fPIC", "-shared",
+                               _SRC, "-o", tmp, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = C.CDLL(_LIB)
+        L.o_pair_list.restype = C.c_int
+        L.o_pair_list.argtypes = [C.c_int, _dp, _dp, C.c_double, C.c_int, C.c_void_p, C.c_void_p]
+        L.o_pair_origin.restype = None
+        L.o_pair_origin.argtypes = [_dp, _dp, _dp, _ip, _ip]
+        L.o_sub_build.restype = C.c_int
+        L.o_sub_build.argtypes = [_ip, _dp, C.c_double, C.c_double, C.POINTER(C.c_void_p)]
+        L.o_sub_free.argtypes = [C.c_void_p]
+        L.o_sub_info.argtypes = [C.c_void_p, C.POINTER(C.c_int), C.POINTER(C.c_int), _ip, _ip]
+        L.o_sub_offsets.argtypes = [C.c_void_p, _ip]
+        L.o_apply_A.argtypes = [C.c_void_p, _dp, _dp]
+        L.o_rhs.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.o_moments.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.o_shell_potential.argtypes = [C.c_void_p, _dp, _dp, _dp]
+        L.o_cg.restype = C.c_int
+        L.o_cg.argtypes = [C.c_void_p, _dp, _dp, C.c_double, C.c_int, C.POINTER(C.c_int),
+                           C.POINTER(C.c_double)]
+        L.o_ylm_reim.argtypes = [C.c_int, C.c_int, C.c_double, C.c_double,
+                                 C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        L.o_fd_weight.restype = C.c_double
+        L.o_fd_weight.argtypes = [C.c_int]
+        L.o_solve_pair.restype = C.c_int
+        L.o_solve_pair.argtypes = [C.c_void_p, _dp, _dp, _ip, C.c_double, C.c_int] + [C.c_void_p] * 6 + [
+            C.POINTER(C.c_double), C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_double)]
+        L.o_exx.restype = C.c_long
+        L.o_exx.argtypes = [_ip, _dp, C.c_double, _dp, _dp, C.c_int, _dp, _dp, C.c_double, C.c_int,
+                            C.c_int, C.POINTER(C.c_double), C.c_void_p, C.c_long] + [C.c_void_p] * 6
+        L.o_solve_pairs.restype = C.c_int
+        L.o_solve_pairs.argtypes = [_ip, _dp, _dp, _dp, _dp, C.c_void_p, C.c_int, _ip, _ip, C.c_double,
+                                    C.c_int, C.c_int, _dp, _ip, _ip, _dp]
+        _lib = L
+    return _lib
+
+
+def _i3(v):
+    return np.ascontiguousarray(np.asarray(v, dtype=np.int32).reshape(3))
+
+
+def _d3(v):
+    return np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(3))
+
+
+def _ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def fd_weights():
+    return np.array([lib().o_fd_weight(s) for s in range(4)])
+
+
+def ylm(l: int, m: int, theta: float, phi: float) -> complex:
+    re, im = C.c_double(), C.c_double()
+    lib().o_ylm_reim(l, m, theta, phi, C.byref(re), C.byref(im))
+    return complex(re.value, im.value)
+
+
+def pair_list(centers, cell, r_pair):
+    L = lib()
+    Cc = np.ascontiguousarray(centers, dtype=np.float64)
+    n = Cc.shape[0]
+    np_ = L.o_pair_list(n, Cc.ravel(), _d3(cell), float(r_pair), 0, None, None)
+    pi = np.zeros(np_, np.int32)
+    pj = np.zeros(np_, np.int32)
+    L.o_pair_list(n, Cc.ravel(), _d3(cell), float(r_pair), np_, _ptr(pi), _ptr(pj))
+    return pi, pj
+
+
+def pair_origin(ci, cj, cell, n):
+    gc = np.zeros(3, np.int32)
+    lib().o_pair_origin(_d3(ci), _d3(cj), _d3(cell), _i3(n), gc)
+    return gc
+
+
+class Subdomain:
+    """One proto-subdomain class (PE sphere + ME shell), Alg. 2."""
+
+    def __init__(self, n, cell, r_pe, r_me):
+        self._h = C.c_void_p()
+        rc = lib().o_sub_build(_i3(n), _d3(cell), float(r_pe), float(r_me), C.byref(self._h))
+        if rc != 0:
+            raise ValueError(f"o_sub_build failed ({rc})")
+        npe, nme = C.c_int(), C.c_int()
+        blo, bhi = np.zeros(3, np.int32), np.zeros(3, np.int32)
+        lib().o_sub_info(self._h, C.byref(npe), C.byref(nme), blo, bhi)
+        self.n_pe, self.n_me = npe.value, nme.value
+        self.n_shell = self.n_me - self.n_pe
+        self.blo, self.bhi = blo, bhi
+        self.h = np.asarray(cell, np.float64) / np.asarray(n, np.float64)
+        self.n = np.asarray(n)
+
+    def __del__(self):
+        if getattr(self, "_h", None) and lib is not None:
+            try:
+                lib().o_sub_free(self._h)
+            except Exception:
+                pass
+
+    def offsets(self) -> np.ndarray:
+        off = np.zeros((self.n_me, 3), np.int32)
+        lib().o_sub_offsets(self._h, off.reshape(-1))
+        return off
+
+    def apply_A(self, x):
+        y = np.zeros(self.n_pe)
+        lib().o_apply_A(self._h, np.ascontiguousarray(x, np.float64), y)
+        return y
+
+    def rhs(self, rho, vsh):
+        b = np.zeros(self.n_pe)
+        lib().o_rhs(self._h, np.ascontiguousarray(rho, np.float64),
+                    np.ascontiguousarray(vsh, np.float64) if self.n_shell else np.zeros(1), b)
+        return b
+
+    def moments(self, rho):
+        re, im = np.zeros(NLM), np.zeros(NLM)
+        lib().o_moments(self._h, np.ascontiguousarray(rho, np.float64), re, im)
+        return re + 1j * im
+
+    def shell_potential(self, Q):
+        v = np.zeros(max(self.n_shell, 1))
+        lib().o_shell_potential(self._h, np.ascontiguousarray(Q.real), np.ascontiguousarray(Q.imag), v)
+        return v[: self.n_shell]
+
+    def cg(self, b, tol=1e-10, maxit=100000):
+        x = np.zeros(self.n_pe)
+        conv, rel = C.c_int(), C.c_double()
+        it = lib().o_cg(self._h, np.ascontiguousarray(b, np.float64), x, tol, maxit, C.byref(conv), C.byref(rel))
+        return x, it, bool(conv.value), rel.value
+
+    def solve_pair(self, phi_i, phi_j, gc, tol=1e-10, maxit=100000):
+        """Full pair pipeline; returns a dict of every intermediate."""
+        x = np.zeros(self.n_pe)
+        vsh = np.zeros(max(self.n_shell, 1))
+        Qre, Qim = np.zeros(NLM), np.zeros(NLM)
+        rho = np.zeros(self.n_pe)
+        b = np.zeros(self.n_pe)
+        e, it, conv, rel = C.c_double(), C.c_int(), C.c_int(), C.c_double()
+        lib().o_solve_pair(self._h, np.ascontiguousarray(phi_i, np.float64).reshape(-1),
+                           np.ascontiguousarray(phi_j, np.float64).reshape(-1), _i3(gc), tol, maxit,
+                           _ptr(x), _ptr(vsh), _ptr(Qre), _ptr(Qim), _ptr(rho), _ptr(b),
+                           C.byref(e), C.byref(it), C.byref(conv), C.byref(rel))
+        return dict(x=x, vsh=vsh[: self.n_shell], Q=Qre + 1j * Qim, rho=rho, b=b, e=e.value,
+                    iters=it.value, converged=bool(conv.value), relres=rel.value)
+
+
+def exx(n, cell, r_pair, r_pe, r_me, centers, phi, tol=1e-10, maxit=100000, nthreads=0, want_D=True):
+    """Whole step: returns (E, D or None, per-pair dict)."""
+    L = lib()
+    Cc = np.ascontiguousarray(centers, np.float64)
+    n_orb = Cc.shape[0]
+    phi = np.ascontiguousarray(phi, np.float64)
+    pi, pj = pair_list(Cc, cell, r_pair)
+    npairs = len(pi)
+    out = dict(i=np.zeros(npairs, np.int32), j=np.zeros(npairs, np.int32), e=np.zeros(npairs),
+               iters=np.zeros(npairs, np.int32), converged=np.zeros(npairs, np.int32),
+               relres=np.zeros(npairs))
+    D = np.zeros_like(phi) if want_D else None
+    E = C.c_double()
+    rpe = np.ascontiguousarray(np.broadcast_to(np.asarray(r_pe, np.float64), (2,)))
+    rme = np.ascontiguousarray(np.broadcast_to(np.asarray(r_me, np.float64), (2,)))
+    rc = L.o_exx(_i3(n), _d3(cell), float(r_pair), rpe, rme, n_orb, Cc.ravel(), phi.reshape(-1), tol,
+                 maxit, nthreads, C.byref(E), _ptr(D), npairs, _ptr(out["i"]), _ptr(out["j"]),
+                 _ptr(out["e"]), _ptr(out["iters"]), _ptr(out["converged"]), _ptr(out["relres"]))
+    if rc < 0:
+        raise ValueError(f"o_exx failed ({rc})")
+    return E.value, D, out
+
+
+def solve_pairs(n, cell, r_pe, r_me, centers, phi_by_orbital: dict, pi: Sequence[int], pj: Sequence[int],
+                tol=1e-10, maxit=100000, nthreads=0):
+    """Solve an explicit pair list; phi_by_orbital maps orbital -> grid array."""
+    L = lib()
+    Cc = np.ascontiguousarray(centers, np.float64)
+    n_orb = Cc.shape[0]
+    keep = {k: np.ascontiguousarray(v, np.float64) for k, v in phi_by_orbital.items()}
+    ptrs = (C.c_void_p * n_orb)()
+    for k, v in keep.items():
+        ptrs[k] = v.ctypes.data
+    pi = np.ascontiguousarray(pi, np.int32)
+    pj = np.ascontiguousarray(pj, np.int32)
+    m = len(pi)
+    e, it, cv, rr = np.zeros(m), np.zeros(m, np.int32), np.zeros(m, np.int32), np.zeros(m)
+    rpe = np.ascontiguousarray(np.broadcast_to(np.asarray(r_pe, np.float64), (2,)))
+    rme = np.ascontiguousarray(np.broadcast_to(np.asarray(r_me, np.float64), (2,)))
+    used = L.o_solve_pairs(_i3(n), _d3(cell), rpe, rme, Cc.ravel(), ptrs, m, pi, pj, tol, maxit, nthreads,
+                           e, it, cv, rr)
+    if used < 0:
+        raise ValueError("o_solve_pairs failed")
+    return dict(e=e, iters=it, converged=cv, relres=rr, threads=used)

@@ -1,0 +1,306 @@
+"""Pins of the CPU oracle against facts that do not come from the oracle.
+
+Each test ties one oracle step to mathematics or to a library routine:
+finite-difference moment conditions, exactness on polynomials, lattice-point
+counts, scipy's spherical harmonics, a dense direct solve, closed-form
+Coulomb energies of Gaussian densities, multipoles of displaced charges,
+translation and pair symmetry, and the energy/potential consistency that
+follows from the definition of D (Sec. II.C, Eq. Dxx_mlwf).
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy.special import erf, sph_harm_y
+
+from oracle import oracle as O
+from paper_1911_10630_amd import synth as S
+
+H_C1 = 10.0 * S.ANG / 48
+
+
+# ---------------------------------------------------------------------------
+# Finite-difference stencil (Eq. d2_1)
+# ---------------------------------------------------------------------------
+
+def test_fd_weights_moment_conditions():
+    w = O.fd_weights()
+    s = np.arange(1, 4)
+    assert abs(w[0] + 2 * w[1:].sum()) < 1e-15                    # constants
+    assert abs(2 * np.sum(w[1:] * s ** 2) - 2.0) < 1e-14          # d2/dx2 of x^2 / 2
+    assert abs(np.sum(w[1:] * s ** 4)) < 1e-14                    # no h^2 error term
+    assert abs(np.sum(w[1:] * s ** 6)) < 1e-14                    # no h^4 error term
+    assert abs(2 * np.sum(w[1:] * s ** 8)) > 1e-3                 # first surviving term: 6th order
+
+
+def _lattice_count(k):
+    r = np.arange(-k, k + 1)
+    X, Y, Z = np.meshgrid(r, r, r, indexing="ij")
+    return int(np.sum(X * X + Y * Y + Z * Z <= k * k))
+
+
+def test_subdomain_lattice_counts():
+    """Points of the PE sphere of radius k*h are the lattice points in a ball of
+    radius k: OEIS A000604 (1, 7, 33, 123, 257, 515, 925) and brute force."""
+    a000604 = [1, 7, 33, 123, 257, 515, 925]
+    h = 0.4
+    for k in range(1, 7):
+        s = O.Subdomain((40, 40, 40), (40 * h,) * 3, k * h, (k + 3) * h)
+        assert s.n_pe == a000604[k] == _lattice_count(k)
+        assert s.n_me == _lattice_count(k + 3)
+
+
+def test_subdomain_small_config_counts_and_order():
+    s = O.Subdomain((48, 48, 48), (10 * S.ANG,) * 3, 4 * S.ANG, 5 * S.ANG)
+    off = s.offsets()
+    d2 = np.sum((off * s.h) ** 2, axis=1)
+    pe, sh = off[: s.n_pe], off[s.n_pe:]
+    assert np.all(d2[: s.n_pe] <= (4 * S.ANG) ** 2 * (1 + 1e-12))
+    assert np.all(d2[s.n_pe:] > (4 * S.ANG) ** 2 * (1 + 1e-12))
+    assert np.all(d2[s.n_pe:] <= (5 * S.ANG) ** 2 * (1 + 1e-12))
+    # cell clipping: offsets span [-24, 23] on a 48-point axis, R_ME/h = 24
+    assert off.min() == -24 and off.max() == 23
+    # each block in z, y, x lexicographic order (Alg. 2 loops over the grid)
+    for blk in (pe, sh):
+        key = (blk[:, 2] * 1000 + blk[:, 1]) * 1000 + blk[:, 0]
+        assert np.all(np.diff(key) > 0)
+    # the PE sphere is not clipped: symmetric under x -> -x
+    assert set(map(tuple, pe)) == set(map(tuple, pe * np.array([-1, 1, 1])))
+
+
+# ---------------------------------------------------------------------------
+# Pair list and pair origin (Step II / Step III, Eq. l2g)
+# ---------------------------------------------------------------------------
+
+def test_pair_list_minimum_image_and_strict_cutoff():
+    L = 10.0
+    C = np.array([[0.5, 5, 5], [9.7, 5, 5], [5, 5, 5], [5, 5, 7.0]])
+    pi, pj = O.pair_list(C, (L, L, L), 2.0)
+    got = set(zip(pi.tolist(), pj.tolist()))
+    # 0-1 are 0.8 apart across the boundary; 2-3 exactly 2.0 apart (strict <)
+    assert got == {(0, 0), (0, 1), (1, 1), (2, 2), (3, 3)}
+    pi, pj = O.pair_list(C, (L, L, L), 2.0 + 1e-9)
+    assert (2, 3) in set(zip(pi.tolist(), pj.tolist()))
+    assert list(pi) == sorted(pi)
+
+
+def test_pair_origin_wraps_and_rounds():
+    L, N = 10.0, 20                                    # h = 0.5
+    # midpoint 0.1 -> grid 0
+    assert list(O.pair_origin([0.5, 5, 5], [9.7, 5, 5], (L,) * 3, (N,) * 3)) == [0, 10, 10]
+    # midpoint -0.2 wraps to 9.8 -> 19.6 -> 20 -> 0 (non-negative MOD)
+    assert list(O.pair_origin([0.1, 5, 5], [9.5, 5, 5], (L,) * 3, (N,) * 3)) == [0, 10, 10]
+    # half-way value 2.25/0.5 = 4.5 rounds away from zero -> 5
+    assert list(O.pair_origin([2.0, 5, 5], [2.5, 5, 5], (L,) * 3, (N,) * 3)) == [5, 10, 10]
+
+
+# ---------------------------------------------------------------------------
+# Operator and CG (Eqs. d2_1, pe_mat_red)
+# ---------------------------------------------------------------------------
+
+def test_operator_exact_on_degree7_polynomials():
+    """-A f + (shell part) f = full stencil Laplacian, exact for degree <= 7."""
+    h = 0.37
+    s = O.Subdomain((40, 40, 40), (40 * h,) * 3, 6 * h, 9 * h)
+    off = s.offsets().astype(np.float64) * h / 3.0      # keep values O(1)
+    x, y, z = off[:, 0], off[:, 1], off[:, 2]
+    f = 1 + x - 2 * y * z + x ** 2 * y + 0.5 * z ** 4 - 0.3 * x ** 3 * y ** 2 * z + 0.1 * x ** 7 - 0.2 * y ** 5 * z ** 2
+    # analytic Laplacian; the coordinates were scaled by 1/3, so divide by 9
+    f_xx = 2 * y - 1.8 * x * y ** 2 * z + 4.2 * x ** 5
+    f_yy = -0.6 * x ** 3 * z - 4.0 * y ** 3 * z ** 2
+    f_zz = 6.0 * z ** 2 - 0.4 * y ** 5
+    lap = (f_xx + f_yy + f_zz) / 9.0
+    lhs = -s.apply_A(f[: s.n_pe]) + s.rhs(np.zeros(s.n_pe), f[s.n_pe:])
+    assert np.max(np.abs(lhs - lap[: s.n_pe])) < 1e-9 * np.max(np.abs(lap))
+
+
+def test_cg_matches_dense_solve_on_tiny_sphere():
+    h = 0.5
+    s = O.Subdomain((32, 32, 32), (32 * h,) * 3, 6 * h, 9 * h)
+    n = s.n_pe
+    assert n == 925
+    A = np.zeros((n, n))
+    for k in range(n):
+        e = np.zeros(n); e[k] = 1.0
+        A[:, k] = s.apply_A(e)
+    assert np.array_equal(A, A.T)
+    np.linalg.cholesky(A)                                    # SPD
+    rng = np.random.default_rng(7)
+    b = rng.normal(size=n)
+    x_ref = np.linalg.solve(A, b)
+    x, it, conv, rel = s.cg(b, tol=1e-14)
+    assert conv and rel < 1e-13
+    assert np.max(np.abs(x - x_ref)) < 1e-11 * np.max(np.abs(x_ref))
+
+
+# ---------------------------------------------------------------------------
+# Spherical harmonics and multipoles (Eqs. mepole, me)
+# ---------------------------------------------------------------------------
+
+def test_ylm_matches_scipy():
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        th, ph = rng.uniform(0, np.pi), rng.uniform(-np.pi, np.pi)
+        for l in range(7):
+            for m in range(-l, l + 1):
+                ref = complex(sph_harm_y(l, m, th, ph))
+                assert abs(O.ylm(l, m, th, ph) - ref) < 1e-13
+
+
+def _gauss_on(off, h, d, p, q=1.0):
+    r = off * h - np.asarray(d)
+    return q * (p / np.pi) ** 1.5 * np.exp(-p * np.sum(r * r, axis=1))
+
+
+def test_moments_of_displaced_gaussian():
+    """A spherical charge q at d has Q_lm = q |d|^l conj(Y_lm(dhat))."""
+    s = O.Subdomain((48, 48, 48), (10 * S.ANG,) * 3, 4 * S.ANG, 5 * S.ANG)
+    off = s.offsets()[: s.n_pe].astype(np.float64)
+    d = np.array([0.31, -0.22, 0.17])
+    p, q = 1.1, 0.8
+    Q = s.moments(_gauss_on(off, s.h, d, p, q))
+    dn = np.linalg.norm(d)
+    th, ph = math.acos(d[2] / dn), math.atan2(d[1], d[0])
+    for l in range(7):
+        for m in range(-l, l + 1):
+            ref = q * dn ** l * np.conj(complex(sph_harm_y(l, m, th, ph)))
+            assert abs(Q[l * l + l + m] - ref) < 1e-12, (l, m)
+
+
+def test_shell_potential_matches_coulomb():
+    s = O.Subdomain((48, 48, 48), (10 * S.ANG,) * 3, 4 * S.ANG, 5 * S.ANG)
+    off = s.offsets().astype(np.float64)
+    d = np.array([0.3, -0.1, 0.2])
+    p, q = 1.3, 1.0
+    Q = s.moments(_gauss_on(off[: s.n_pe], s.h, d, p, q))
+    v = s.shell_potential(Q)
+    r = np.linalg.norm(off[s.n_pe:] * s.h - d, axis=1)
+    v_ref = q * erf(math.sqrt(p) * r) / r
+    # l <= 6 truncation error ~ (|d|/r)^7 ~ 1e-10
+    assert np.max(np.abs(v - v_ref) / v_ref) < 1e-8
+
+
+# ---------------------------------------------------------------------------
+# Whole pair solve against closed forms
+# ---------------------------------------------------------------------------
+
+def _s_orbital_grid(n, L, c, alpha):
+    h = L / n
+    ax = np.arange(n) * h
+    d = [ax - c[k] for k in range(3)]
+    d = [dd - L * np.round(dd / L) for dd in d]
+    g = np.exp(-alpha * d[2][:, None, None] ** 2) * np.exp(-alpha * d[1][None, :, None] ** 2) \
+        * np.exp(-alpha * d[0][None, None, :] ** 2)
+    return (2 * alpha / np.pi) ** 0.75 * g
+
+
+@pytest.mark.parametrize("n", [48, 96])
+def test_self_energy_of_s_gaussian(n):
+    """Self pair of a normalized s Gaussian: e = (rho|rho) = 2 sqrt(alpha/pi)."""
+    L, alpha = 10 * S.ANG, 0.8
+    c = np.array([L / 2, L / 2, L / 2])
+    phi = _s_orbital_grid(n, L, c, alpha)
+    s = O.Subdomain((n,) * 3, (L,) * 3, 4 * S.ANG, 5 * S.ANG)
+    gc = O.pair_origin(c, c, (L,) * 3, (n,) * 3)
+    r = s.solve_pair(phi, phi, gc, tol=1e-12)
+    exact = 2 * math.sqrt(alpha / math.pi)
+    err = abs(r["e"] - exact) / exact
+    # 6th-order FD error: 2x the level measured for p = 1.6 at these spacings
+    assert err < {48: 2.2e-4, 96: 4e-6}[n], err
+    test_self_energy_of_s_gaussian.errs = getattr(test_self_energy_of_s_gaussian, "errs", {})
+    test_self_energy_of_s_gaussian.errs[n] = err
+
+
+def test_self_energy_converges_at_sixth_order():
+    errs = getattr(test_self_energy_of_s_gaussian, "errs", {})
+    if len(errs) < 2:
+        pytest.skip("needs both spacings from the previous test")
+    assert errs[48] / errs[96] > 30.0                         # ~2^6 asymptotically
+
+
+def test_two_center_product_across_boundary():
+    """rho_ab = S_ab * normalized Gaussian of exponent a+b centred at
+    P = (aA + bB)/(a+b); (rho|rho) = S_ab^2 sqrt(2p/pi).  Centres straddle
+    the periodic boundary, so the gather wraps."""
+    n, L = 48, 10 * S.ANG
+    a, b = 0.7, 0.9
+    A = np.array([0.4, 9.0, 18.5])
+    B = np.array([18.2, 9.6, 0.3])
+    pa = _s_orbital_grid(n, L, A, a)
+    pb = _s_orbital_grid(n, L, B, b)
+    s = O.Subdomain((n,) * 3, (L,) * 3, 4 * S.ANG, 5 * S.ANG)
+    gc = O.pair_origin(A, B, (L,) * 3, (n,) * 3)
+    r = s.solve_pair(pa, pb, gc, tol=1e-12)
+    dAB = B - A
+    dAB -= L * np.round(dAB / L)
+    mu = a * b / (a + b)
+    Sab = (4 * a * b / (a + b) ** 2) ** 0.75 * math.exp(-mu * float(dAB @ dAB))
+    exact = Sab ** 2 * math.sqrt(2 * (a + b) / math.pi)
+    assert abs(r["e"] - exact) / exact < 3e-4
+    # the monopole of the pair density is the overlap
+    assert abs(r["Q"][0] * math.sqrt(4 * math.pi) - Sab) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# Invariants of the whole step
+# ---------------------------------------------------------------------------
+
+@pytest.fixture(scope="module")
+def c1_result():
+    wl = S.c1_small()
+    phi = S.orbitals_np(wl)
+    E, D, out = O.exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, wl.orbitals.centers, phi)
+    return wl, phi, E, D, out
+
+
+def test_c1_pairs_and_convergence(c1_result):
+    wl, phi, E, D, out = c1_result
+    assert len(out["e"]) == 60
+    assert np.all(out["converged"] == 1)
+    assert np.all(out["relres"] < 1e-9)
+    assert E < 0
+    # E is the weighted sum of the pair energies
+    w = np.where(out["i"] == out["j"], 1.0, 2.0)
+    assert abs(E + np.sum(w * out["e"])) < 1e-12 * abs(E)
+
+
+def test_translation_by_grid_vector(c1_result):
+    wl, phi, E, D, out = c1_result
+    k = np.array([3, -5, 7])
+    C = np.mod(wl.orbitals.centers + k * np.array(wl.h), wl.cell[0])
+    phis = np.roll(phi, shift=(k[2], k[1], k[0]), axis=(1, 2, 3))
+    E2, D2, _ = O.exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, C, phis)
+    assert abs(E2 - E) <= 1e-13 * abs(E)
+    Dr = np.roll(D, shift=(k[2], k[1], k[0]), axis=(1, 2, 3))
+    assert np.max(np.abs(D2 - Dr)) <= 1e-13 * np.max(np.abs(D))
+
+
+def test_pair_potential_symmetric(c1_result):
+    wl, phi, *_ = c1_result
+    s = O.Subdomain(wl.n_grid, wl.cell, wl.r_pe[1], wl.r_me[1])
+    C = wl.orbitals.centers
+    gc = O.pair_origin(C[2], C[5], wl.cell, wl.n_grid)
+    a = s.solve_pair(phi[2], phi[5], gc)
+    b = s.solve_pair(phi[5], phi[2], gc)
+    assert np.array_equal(a["x"], b["x"]) and np.array_equal(a["vsh"], b["vsh"])
+
+
+@pytest.mark.slow
+def test_energy_potential_consistency(c1_result):
+    """dE/d eps along phi_k + eps*eta equals -4 h^3 <eta, D^k> (real orbitals)."""
+    wl, phi, E, D, out = c1_result
+    h3 = float(np.prod(wl.h))
+    k = 3
+    c = wl.orbitals.centers[k]
+    eta = _s_orbital_grid(wl.n_grid[0], wl.cell[0], c, 1.5)
+    eps = 1e-3
+    Es = []
+    for sgn in (+1, -1):
+        p2 = phi.copy()
+        p2[k] += sgn * eps * eta
+        Es.append(O.exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, wl.orbitals.centers, p2,
+                        tol=1e-13, want_D=False)[0])
+    fd = (Es[0] - Es[1]) / (2 * eps)
+    _, D13, _ = O.exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, wl.orbitals.centers, phi, tol=1e-13)
+    an = -4 * h3 * float(np.sum(eta * D13[k]))
+    assert abs(fd - an) < 1e-5 * abs(an), (fd, an)
