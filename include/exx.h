@@ -1,0 +1,162 @@
+/*
+ * exx.h -- C ABI of the MI355X pair-Poisson exact-exchange library.
+ *
+ * The library evaluates, for a set of localized orbitals phi_i on a periodic
+ * orthorhombic grid, the exact-exchange energy and orbital potentials of
+ * Ko et al., arXiv:1911.10630:
+ *
+ *   E_xx = - sum_<ij> w_ij h^3 sum_{r in PE_ij} rho_ij(r) v_ij(r),
+ *          w_ii = 1, w_ij = 2 (i != j)                       (Eqs. exx, exx_omega)
+ *   D^i(r) = sum_j v_ij(r) phi_j(r)   on the ME sphere of each pair
+ *                                                            (Eqs. Dxx_mlwf, Dxx_mlwf_omega)
+ *
+ * where rho_ij = phi_i phi_j, and v_ij solves the Poisson equation
+ * del^2 v = -4 pi rho on the PE sphere of radius R_PE around the grid point
+ * nearest the pair midpoint (Eq. pe), with Dirichlet values on the shell
+ * R_PE < r <= R_ME from an l <= 6 multipole expansion (Eqs. me, mepole),
+ * using the 6th-order central-difference Laplacian (Eq. d2_1) and the
+ * boundary-charge form of the reduced system (Eq. pe_mat_red), solved by
+ * conjugate gradient (Sec. III.C, Step IV).
+ *
+ * Units: bohr and hartree.  Grids: [n_orb][Nz][Ny][Nx], x fastest, 0-based
+ * (the convention of Eq. l2g).  The caller applies the hybrid mixing
+ * fraction a_x (Eq. hyb); E_xx and D are returned unscaled.
+ *
+ * Call order: exx_setup -> exx_pairs -> exx_solve -> exx_energy_potential
+ * (then exx_pairs or exx_solve again for the next step).  Out-of-order calls
+ * return EXX_ESTATE.  No call throws or aborts; every failure returns a
+ * status and leaves a message for exx_last_error.  A context is not
+ * thread-safe: calls on one context must not overlap.
+ */
+#ifndef EXX_H
+#define EXX_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct exx_ctx exx_ctx;
+
+typedef enum {
+    EXX_OK = 0,
+    EXX_EINVAL = -1,   /* bad argument: null pointer, size, radii, dtype       */
+    EXX_ENOMEM = -2,   /* device or host allocation failed                     */
+    EXX_EDEVICE = -3,  /* HIP runtime error (message names the call)          */
+    EXX_ENOCONV = -4,  /* some pair CG did not reach cg_rtol in cg_max_iter;
+                          results are still written, flags in exx_pair_info   */
+    EXX_ESTATE = -5    /* call out of order                                    */
+} exx_status;
+
+enum { EXX_FP64 = 0, EXX_FP32_REFINE = 1 };                 /* CG arithmetic  */
+enum { EXX_F64 = 0, EXX_F32 = 1 };                          /* orbital dtype  */
+enum { EXX_GUESS_ZERO = 0, EXX_GUESS_PREVIOUS = 1, EXX_GUESS_EXTRAP = 2 };
+
+typedef struct {
+    int32_t n_grid[3];      /* Nx, Ny, Nz                                       */
+    double  cell[3];        /* orthorhombic cell lengths |L_a| (bohr)           */
+    double  r_pair;         /* pair iff minimum-image |C_i - C_j| < r_pair      */
+    double  r_pe[2];        /* PE radius: [0] self pairs, [1] non-self pairs    */
+    double  r_me[2];        /* ME radius: [0] self pairs, [1] non-self pairs    */
+    int32_t fd_half_width;  /* n of Eq. d2_1; only 3 is implemented             */
+    int32_t l_max;          /* multipole order; only 6 is implemented           */
+    double  cg_rtol;        /* stop when ||b - A x||_2 <= cg_rtol ||b||_2       */
+    int32_t cg_max_iter;    /* per pair (FP32_REFINE: total inner iterations)   */
+    int32_t precision;      /* EXX_FP64 | EXX_FP32_REFINE                       */
+    int32_t orbital_dtype;  /* EXX_F64 | EXX_F32 (phi storage; D uses the same) */
+    int32_t guess;          /* EXX_GUESS_*: initial CG guess                    */
+    double  inner_rtol;     /* FP32_REFINE: relative tolerance of each FP32 solve */
+    int32_t block_threads;  /* work-group size of the solve kernel; 0 = tuned   */
+    int64_t wave_pairs;     /* max pairs per launch wave; 0 = as many as fit    */
+    int32_t keep_intermediates; /* 1: keep rho, b per pair for exx_debug_pair   */
+} exx_params;
+
+typedef struct {
+    int64_t n_pairs;
+    int64_t n_self;
+    int64_t iters_total;     /* sum of CG iterations (FP32 inner + FP64 outer)  */
+    int32_t iters_min, iters_max;
+    int64_t n_not_converged;
+    double  relres_max;      /* max true relative residual over pairs          */
+    double  solve_ms;        /* last exx_solve: all its kernels, HIP events     */
+    double  prep_ms;         /* last exx_solve: pair-preparation kernel         */
+    double  cg_ms;           /* last exx_solve: persistent CG kernel            */
+    double  dxx_ms;          /* last exx_energy_potential: D kernel, HIP events */
+    double  energy_ms;       /* last exx_energy_potential: E reduction          */
+    int32_t solve_grid;      /* persistent work-groups launched                 */
+    int32_t solve_block;     /* threads per work-group                          */
+    int64_t n_pe[2], n_me[2];/* subdomain sizes per class                       */
+    int64_t cg_bytes;        /* algorithmic CG bytes of the last solve          */
+    int64_t solve_bytes;     /* algorithmic bytes of the whole solve kernel     */
+    int64_t dxx_bytes;       /* algorithmic bytes of the D kernel               */
+    int64_t device_bytes;    /* device memory held by the context              */
+    int32_t n_waves;         /* pair waves of the last solve (1 = one launch)   */
+} exx_stats_t;
+
+/* Fills *p with the paper's method defaults (n = 3, l_max = 6, FP64, zero
+ * guess, cg_rtol 1e-10, cg_max_iter 20000).  Grid, cell and radii are zeroed
+ * and must be set by the caller. */
+void exx_default_params(exx_params *p);
+
+/* Validates the parameters, builds the self and non-self proto-subdomains
+ * (Alg. 2) and uploads their tables to `device`.  EXX_EINVAL if any radius is
+ * non-positive, R_ME - R_PE < n * max(h) (the stencil would leave PE u shell,
+ * Sec. IV.A), or an unimplemented order is requested.  *out owns every
+ * device allocation; free with exx_destroy. */
+exx_status exx_setup(const exx_params *p, int device, exx_ctx **out);
+
+/* Builds the unique pair list {i <= j : i == j or |C_i - C_j| < r_pair}
+ * ordered by (i, j), the pair origins (grid point nearest the minimum-image
+ * midpoint, Step III) and per-orbital pair lists, and sizes the per-pair
+ * device buffers.  centers: host, [n_orb][3] bohr, copied.  *n_pairs
+ * receives the pair count.  EXX_ENOMEM if the per-pair potentials do not fit
+ * on the device. */
+exx_status exx_pairs(exx_ctx *ctx, int32_t n_orb, const double *centers, int64_t *n_pairs);
+
+/* Enqueues every pair solve on `stream` (a hipStream_t; NULL = default):
+ * gather and pair density, multipole moments, shell potential and
+ * right-hand side, conjugate gradient, pair energy.  phi: device,
+ * [n_orb][Nz][Ny][Nx] of orbital_dtype, read-only, must stay valid until
+ * the stream work completes.  Asynchronous. */
+exx_status exx_solve(exx_ctx *ctx, const void *phi, void *stream);
+
+/* Enqueues D accumulation and the E reduction on `stream`, then
+ * synchronizes it.  dxx: device, same shape and dtype as phi, fully
+ * overwritten (every point of every orbital).  *e_xx receives E_xx (host).
+ * Returns EXX_ENOCONV (with results written) if any pair failed to
+ * converge. */
+exx_status exx_energy_potential(exx_ctx *ctx, double *e_xx, void *dxx, void *stream);
+
+/* Counters and timings of the last solve (synchronizes nothing; call after
+ * exx_energy_potential). */
+exx_status exx_stats(exx_ctx *ctx, exx_stats_t *st);
+
+/* Per-pair results of the last solve, copied to host arrays of length
+ * n_pairs (any pointer may be NULL): orbital indices, pair origin grid
+ * point [n_pairs][3], pair energy e_ij = h^3 sum rho x, CG iterations,
+ * convergence flag, true relative residual. */
+exx_status exx_pair_info(exx_ctx *ctx, int32_t *pi, int32_t *pj, int32_t *origin, double *e,
+                         int32_t *iters, int32_t *converged, double *relres);
+
+/* Copies one pair's arrays to host buffers (any may be NULL), after a
+ * solve: v on PE in the proto-subdomain order of Eq. rbar (n_pe), v on the
+ * shell (n_me - n_pe), the 49 real multipole moments Q_lm (index l*l+l+m,
+ * real orthonormal harmonics), and, if keep_intermediates was set, the
+ * pair density and right-hand side on PE.  EXX_ESTATE if the intermediates
+ * were not kept.  Synchronizes the device. */
+exx_status exx_debug_pair(exx_ctx *ctx, int64_t pair, double *v_pe, double *v_shell, double *q_lm,
+                          double *rho, double *rhs);
+
+/* Message of the last failing call on ctx (or of the last failing
+ * exx_setup when ctx is NULL).  Never NULL. */
+const char *exx_last_error(const exx_ctx *ctx);
+
+/* Releases every allocation; NULL is ignored. */
+void exx_destroy(exx_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* EXX_H */

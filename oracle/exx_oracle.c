@@ -168,7 +168,9 @@ int o_sub_build(const int n[3], const double cell[3], double r_pe, double r_me, 
             if (o < s->blo[a]) s->blo[a] = o;
             if (o > s->bhi[a]) s->bhi[a] = o;
         }
-    size_t bx = s->bhi[0] - s->blo[0] + 1, by = s->bhi[1] - s->blo[1] + 1, bz = s->bhi[2] - s->blo[2] + 1;
+    int ibx = s->bhi[0] - s->blo[0] + 1, iby = s->bhi[1] - s->blo[1] + 1, ibz = s->bhi[2] - s->blo[2] + 1;
+    if (ibx < 1 || iby < 1 || ibz < 1 || ibx > 4096 || iby > 4096 || ibz > 4096) { o_sub_free(s); return -1; }
+    size_t bx = (size_t)ibx, by = (size_t)iby, bz = (size_t)ibz;
     s->box = (int *)malloc(sizeof(int) * bx * by * bz);
     for (size_t t = 0; t < bx * by * bz; ++t) s->box[t] = -1;
     for (int q = 0; q < s->n_me; ++q) {

@@ -1,0 +1,717 @@
+// exx_host.cpp -- host side of the MI355X pair-Poisson exact-exchange library:
+// parameter validation, proto-subdomain tables (Alg. 2), pair list and pair
+// origins (Sec. III.C Steps II-III), device memory, and the C ABI of exx.h.
+#include "exx.h"
+#include "exx_internal.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+using namespace exx;
+
+namespace {
+
+// Central-difference weights of the second derivative for n = 3 (Eq. d2_1).
+constexpr double kFD[4] = {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0};
+
+std::string g_setup_error = "no error";
+
+// Fortran NINT: nearest integer, halves away from zero.
+long nint_away(double v) { return (long)(v >= 0.0 ? std::floor(v + 0.5) : -std::floor(-v + 0.5)); }
+int mod_pos(long a, int n) { long r = a % n; return (int)(r < 0 ? r + n : r); }
+
+struct HostClass {
+    double r_pe = 0, r_me = 0;
+    int n_pe = 0, n_sh = 0;
+    int pxlo = 0, pxhi = -1, pylo = 0, pyhi = -1, pzlo = 0, pzhi = -1;
+    int mxlo = 0, mxhi = -1, mylo = 0, myhi = -1, mzlo = 0, mzhi = -1;
+    std::vector<int4> pe_rows, me_rows;
+    std::vector<int> pe_xyz, sh_xyz, cols;
+    int4 *d_pe_rows = nullptr, *d_me_rows = nullptr;
+    int *d_pe_xyz = nullptr, *d_sh_xyz = nullptr, *d_cols = nullptr;
+};
+
+template <typename T>
+struct DevBuf {
+    T *p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct exx_ctx {
+    exx_params prm{};
+    int device = 0;
+    int n_cu = 0;
+    double h[3] = {0, 0, 0};
+    int c0[3] = {0, 0, 0};
+    HostClass cls[2];
+    std::string err = "no error";
+    int state = 0;  // 1 set up, 2 pairs built, 3 solved
+
+    // pairs
+    int n_orb = 0;
+    int64_t n_pairs = 0, n_self = 0;
+    std::vector<int2> ij;
+    std::vector<int4> gc;
+    std::vector<long long> out_off;
+    std::vector<int> orb_ptr, orb_pairs;
+    long long vout_n = 0;
+
+    DevBuf<int2> d_ij;
+    DevBuf<int4> d_gc;
+    DevBuf<long long> d_off;
+    DevBuf<int> d_orb_ptr, d_orb_pairs;
+    DevBuf<double> d_vout, d_q, d_e, d_relres, d_scratch, d_E, d_rhs, d_rho_keep;
+    DevBuf<int> d_iters, d_conv, d_counter;
+    DevBuf<float> d_scratch32;
+
+    int block = 256, grid = 0, slots = 0, wave_n = 0, n_waves = 0;
+    long long slot_n = 0;
+    const void *phi = nullptr;
+    hipEvent_t ev[6] = {};
+    bool have_events = false;
+    bool solved_once = false;
+};
+
+namespace {
+
+exx_status fail(exx_ctx *c, exx_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (c)
+        c->err = buf;
+    else
+        g_setup_error = buf;
+    return st;
+}
+
+#define HIPCHK(ctx, call)                                                                            \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess)                                                                        \
+            return fail(ctx, e_ == hipErrorOutOfMemory ? EXX_ENOMEM : EXX_EDEVICE, "%s: %s (%s:%d)", \
+                        #call, hipGetErrorString(e_), __FILE__, __LINE__);                           \
+    } while (0)
+
+template <typename T>
+void dev_free(DevBuf<T> &b)
+{
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.n = 0;
+}
+
+template <typename T>
+exx_status dev_reserve(exx_ctx *c, DevBuf<T> &b, size_t n)
+{
+    if (n <= b.n && b.p) return EXX_OK;
+    dev_free(b);
+    size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    hipError_t e = hipMalloc(&b.p, bytes);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        return fail(c, EXX_ENOMEM, "hipMalloc of %zu bytes failed: %s", bytes, hipGetErrorString(e));
+    }
+    b.n = std::max<size_t>(n, 1);
+    return EXX_OK;
+}
+
+template <typename T>
+exx_status upload(exx_ctx *c, DevBuf<T> &b, const std::vector<T> &v)
+{
+    exx_status st = dev_reserve(c, b, v.size());
+    if (st != EXX_OK) return st;
+    if (!v.empty()) HIPCHK(c, hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return EXX_OK;
+}
+
+bool inside(const double h[3], int x, int y, int z, double R)
+{
+    const double dx = x * h[0], dy = y * h[1], dz = z * h[2];
+    return dx * dx + dy * dy + dz * dz <= R * R * (1.0 + 1e-12);
+}
+
+// Builds the tables of one class.  Offsets o_a range over the cell points,
+// [-c0_a, N_a - 1 - c0_a] (Alg. 2 loops over the grid, so a sphere wider than
+// the cell is clipped and no grid point appears twice).
+exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
+{
+    const int *N = c->prm.n_grid;
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+        const int ext = (int)std::ceil(r_me / c->h[a]) + 1;
+        lo[a] = std::max(-c->c0[a], -ext);
+        hi[a] = std::min(N[a] - 1 - c->c0[a], ext);
+    }
+    k.r_pe = r_pe;
+    k.r_me = r_me;
+    // ME and PE runs per (z, y)
+    struct Run { int mlo, mhi, plo, phi; };
+    const int ny = hi[1] - lo[1] + 1, nz = hi[2] - lo[2] + 1;
+    std::vector<Run> runs((size_t)ny * nz, Run{1, 0, 1, 0});
+    int mb[6] = {1 << 30, -(1 << 30), 1 << 30, -(1 << 30), 1 << 30, -(1 << 30)};
+    int pb[6] = {1 << 30, -(1 << 30), 1 << 30, -(1 << 30), 1 << 30, -(1 << 30)};
+    for (int z = lo[2]; z <= hi[2]; ++z)
+        for (int y = lo[1]; y <= hi[1]; ++y) {
+            Run &r = runs[(size_t)(z - lo[2]) * ny + (y - lo[1])];
+            for (int x = lo[0]; x <= hi[0]; ++x) {
+                if (inside(c->h, x, y, z, r_me)) {
+                    if (r.mlo > r.mhi) r.mlo = x;
+                    r.mhi = x;
+                }
+                if (inside(c->h, x, y, z, r_pe)) {
+                    if (r.plo > r.phi) r.plo = x;
+                    r.phi = x;
+                }
+            }
+            if (r.mlo <= r.mhi) {
+                mb[0] = std::min(mb[0], r.mlo); mb[1] = std::max(mb[1], r.mhi);
+                mb[2] = std::min(mb[2], y); mb[3] = std::max(mb[3], y);
+                mb[4] = std::min(mb[4], z); mb[5] = std::max(mb[5], z);
+            }
+            if (r.plo <= r.phi) {
+                pb[0] = std::min(pb[0], r.plo); pb[1] = std::max(pb[1], r.phi);
+                pb[2] = std::min(pb[2], y); pb[3] = std::max(pb[3], y);
+                pb[4] = std::min(pb[4], z); pb[5] = std::max(pb[5], z);
+            }
+        }
+    if (pb[0] > pb[1]) return fail(c, EXX_EINVAL, "PE sphere of radius %g holds no grid point", r_pe);
+    auto run_at = [&](int y, int z) -> const Run * {
+        if (y < lo[1] || y > hi[1] || z < lo[2] || z > hi[2]) return nullptr;
+        return &runs[(size_t)(z - lo[2]) * ny + (y - lo[1])];
+    };
+    // Every stencil neighbour of every PE point must lie in PE u shell.
+    for (int z = pb[4]; z <= pb[5]; ++z)
+        for (int y = pb[2]; y <= pb[3]; ++y) {
+            const Run *r = run_at(y, z);
+            if (!r || r->plo > r->phi) continue;
+            if (r->plo - FD_N < r->mlo || r->phi + FD_N > r->mhi)
+                return fail(c, EXX_EINVAL, "R_ME - R_PE (%g - %g) leaves the stencil outside the ME sphere", r_me, r_pe);
+            for (int s = -FD_N; s <= FD_N; ++s) {
+                if (!s) continue;
+                const Run *ry = run_at(y + s, z), *rz = run_at(y, z + s);
+                for (const Run *q : {ry, rz})
+                    if (!q || q->mlo > r->plo || q->mhi < r->phi)
+                        return fail(c, EXX_EINVAL,
+                                    "R_ME - R_PE (%g - %g) leaves the stencil outside the ME sphere (or the cell clips it)",
+                                    r_me, r_pe);
+            }
+        }
+    k.pxlo = pb[0]; k.pxhi = pb[1]; k.pylo = pb[2]; k.pyhi = pb[3]; k.pzlo = pb[4]; k.pzhi = pb[5];
+    k.mxlo = mb[0]; k.mxhi = mb[1]; k.mylo = mb[2]; k.myhi = mb[3]; k.mzlo = mb[4]; k.mzhi = mb[5];
+    const int pny = k.pyhi - k.pylo + 1, pnz = k.pzhi - k.pzlo + 1;
+    const int mny = k.myhi - k.mylo + 1, mnz = k.mzhi - k.mzlo + 1;
+    k.pe_rows.assign((size_t)pny * pnz, int4{0, 1, 0, 0});
+    k.me_rows.assign((size_t)2 * mny * mnz, int4{0, 1, 0, 0});
+    k.pe_xyz.clear();
+    k.sh_xyz.clear();
+    // PE packing, z-major / y / x (the order of Alg. 2)
+    int base = 0;
+    for (int z = k.pzlo; z <= k.pzhi; ++z)
+        for (int y = k.pylo; y <= k.pyhi; ++y) {
+            const Run *r = run_at(y, z);
+            if (!r || r->plo > r->phi) continue;
+            k.pe_rows[(size_t)(z - k.pzlo) * pny + (y - k.pylo)] = int4{base, r->plo, r->phi, 0};
+            for (int x = r->plo; x <= r->phi; ++x) k.pe_xyz.push_back(pack_xyz(x, y, z));
+            base += r->phi - r->plo + 1;
+        }
+    k.n_pe = base;
+    // Shell packing: same order, left run then right run of each row
+    int sbase = 0;
+    for (int z = k.mzlo; z <= k.mzhi; ++z)
+        for (int y = k.mylo; y <= k.myhi; ++y) {
+            const Run *r = run_at(y, z);
+            if (!r || r->mlo > r->mhi) continue;
+            int plo = r->plo, phi = r->phi, pe_base = 0;
+            if (plo > phi) { plo = r->mhi + 1; phi = r->mhi; }
+            else pe_base = k.pe_rows[(size_t)(z - k.pzlo) * pny + (y - k.pylo)].x;
+            const size_t row = (size_t)(z - k.mzlo) * mny + (y - k.mylo);
+            k.me_rows[2 * row] = int4{pe_base, plo, phi, sbase};
+            k.me_rows[2 * row + 1] = int4{r->mlo, r->mhi, 0, 0};
+            for (int x = r->mlo; x <= r->mhi; ++x)
+                if (x < plo || x > phi) {
+                    k.sh_xyz.push_back(pack_xyz(x, y, z));
+                    ++sbase;
+                }
+        }
+    k.n_sh = sbase;
+    // Projection columns of PE onto the xy plane, sorted (y, x)
+    k.cols.clear();
+    for (int y = k.pylo; y <= k.pyhi; ++y) {
+        int xl = 1 << 30, xh = -(1 << 30);
+        for (int z = k.pzlo; z <= k.pzhi; ++z) {
+            const Run *r = run_at(y, z);
+            if (!r || r->plo > r->phi) continue;
+            xl = std::min(xl, r->plo);
+            xh = std::max(xh, r->phi);
+        }
+        for (int x = xl; x <= xh; ++x) k.cols.push_back(pack_xyz(x, y, 0));
+    }
+    // upload
+    auto up = [&](auto **dst, const auto &v) -> exx_status {
+        using T = std::remove_reference_t<decltype(v[0])>;
+        size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+        HIPCHK(c, hipMalloc((void **)dst, bytes));
+        if (!v.empty()) HIPCHK(c, hipMemcpy(*dst, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+        return EXX_OK;
+    };
+    exx_status st;
+    if ((st = up(&k.d_pe_rows, k.pe_rows)) != EXX_OK) return st;
+    if ((st = up(&k.d_me_rows, k.me_rows)) != EXX_OK) return st;
+    if ((st = up(&k.d_pe_xyz, k.pe_xyz)) != EXX_OK) return st;
+    if ((st = up(&k.d_sh_xyz, k.sh_xyz)) != EXX_OK) return st;
+    if ((st = up(&k.d_cols, k.cols)) != EXX_OK) return st;
+    return EXX_OK;
+}
+
+ClassDev class_dev(const HostClass &k)
+{
+    ClassDev d{};
+    d.pe_rows = k.d_pe_rows;
+    d.me_rows = k.d_me_rows;
+    d.pe_xyz = k.d_pe_xyz;
+    d.sh_xyz = k.d_sh_xyz;
+    d.cols = k.d_cols;
+    d.n_cols = (int)k.cols.size();
+    d.pxlo = k.pxlo; d.pylo = k.pylo; d.pzlo = k.pzlo;
+    d.pnx = k.pxhi - k.pxlo + 1; d.pny = k.pyhi - k.pylo + 1; d.pnz = k.pzhi - k.pzlo + 1;
+    d.mxlo = k.mxlo; d.mylo = k.mylo; d.mzlo = k.mzlo;
+    d.mnx = k.mxhi - k.mxlo + 1; d.mny = k.myhi - k.mylo + 1; d.mnz = k.mzhi - k.mzlo + 1;
+    d.n_pe = k.n_pe;
+    d.n_sh = k.n_sh;
+    return d;
+}
+
+void free_class(HostClass &k)
+{
+    for (void *p : {(void *)k.d_pe_rows, (void *)k.d_me_rows, (void *)k.d_pe_xyz, (void *)k.d_sh_xyz, (void *)k.d_cols})
+        if (p) (void)hipFree(p);
+    k.d_pe_rows = k.d_me_rows = nullptr;
+    k.d_pe_xyz = k.d_sh_xyz = k.d_cols = nullptr;
+}
+
+double fact(int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
+
+void ylm_norms(double *out)
+{
+    for (int l = 0; l <= LMAX; ++l)
+        for (int m = -l; m <= l; ++m) {
+            const int am = m < 0 ? -m : m;
+            double v = (2 * l + 1) / (4.0 * M_PI) * fact(l - am) / fact(l + am);
+            if (am) v *= 2.0;
+            out[l * l + l + m] = std::sqrt(v);
+        }
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+void exx_default_params(exx_params *p)
+{
+    if (!p) return;
+    std::memset(p, 0, sizeof *p);
+    p->fd_half_width = 3;
+    p->l_max = 6;
+    p->cg_rtol = 1e-10;
+    p->cg_max_iter = 20000;
+    p->precision = EXX_FP64;
+    p->orbital_dtype = EXX_F64;
+    p->guess = EXX_GUESS_ZERO;
+    p->inner_rtol = 1e-5;
+}
+
+exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
+{
+    if (!out) return fail(nullptr, EXX_EINVAL, "exx_setup: out is NULL");
+    *out = nullptr;
+    if (!p) return fail(nullptr, EXX_EINVAL, "exx_setup: params is NULL");
+    for (int a = 0; a < 3; ++a) {
+        if (p->n_grid[a] < 8 || p->n_grid[a] > 1000)
+            return fail(nullptr, EXX_EINVAL, "n_grid[%d] = %d outside [8, 1000]", a, p->n_grid[a]);
+        if (!(p->cell[a] > 0.0)) return fail(nullptr, EXX_EINVAL, "cell[%d] must be positive", a);
+    }
+    if (p->fd_half_width != 3) return fail(nullptr, EXX_EINVAL, "only fd_half_width = 3 is implemented");
+    if (p->l_max != 6) return fail(nullptr, EXX_EINVAL, "only l_max = 6 is implemented");
+    if (!(p->r_pair > 0.0)) return fail(nullptr, EXX_EINVAL, "r_pair must be positive");
+    if (!(p->cg_rtol > 0.0) || p->cg_max_iter < 1) return fail(nullptr, EXX_EINVAL, "cg_rtol > 0 and cg_max_iter >= 1 required");
+    if (p->precision != EXX_FP64 && p->precision != EXX_FP32_REFINE)
+        return fail(nullptr, EXX_EINVAL, "unknown precision %d", p->precision);
+    if (p->orbital_dtype != EXX_F64 && p->orbital_dtype != EXX_F32)
+        return fail(nullptr, EXX_EINVAL, "unknown orbital_dtype %d", p->orbital_dtype);
+    if (p->guess < EXX_GUESS_ZERO || p->guess > EXX_GUESS_EXTRAP)
+        return fail(nullptr, EXX_EINVAL, "unknown guess %d", p->guess);
+    if (p->precision == EXX_FP32_REFINE && !(p->inner_rtol > 0.0 && p->inner_rtol < 1.0))
+        return fail(nullptr, EXX_EINVAL, "inner_rtol must lie in (0, 1)");
+    double hmax = 0.0;
+    for (int a = 0; a < 3; ++a) hmax = std::max(hmax, p->cell[a] / p->n_grid[a]);
+    for (int c = 0; c < 2; ++c) {
+        if (!(p->r_pe[c] > 0.0)) return fail(nullptr, EXX_EINVAL, "r_pe[%d] must be positive", c);
+        if (p->r_me[c] - p->r_pe[c] < 3 * hmax * (1.0 - 1e-12))
+            return fail(nullptr, EXX_EINVAL, "r_me[%d] - r_pe[%d] = %g < n max(h) = %g", c, c, p->r_me[c] - p->r_pe[c],
+                        3 * hmax);
+    }
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+        return fail(nullptr, EXX_EDEVICE, "no HIP device available");
+    if (device < 0 || device >= ndev) return fail(nullptr, EXX_EINVAL, "device %d out of range [0, %d)", device, ndev);
+    exx_ctx *c = new (std::nothrow) exx_ctx();
+    if (!c) return fail(nullptr, EXX_ENOMEM, "host allocation failed");
+    c->prm = *p;
+    c->device = device;
+    auto bail = [&](exx_status st) {
+        g_setup_error = c->err;
+        exx_destroy(c);
+        return st;
+    };
+    if (hipSetDevice(device) != hipSuccess) return bail(fail(c, EXX_EDEVICE, "hipSetDevice(%d) failed", device));
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return bail(fail(c, EXX_EDEVICE, "hipGetDeviceProperties failed"));
+    c->n_cu = prop.multiProcessorCount;
+    for (int a = 0; a < 3; ++a) {
+        c->h[a] = p->cell[a] / p->n_grid[a];
+        c->c0[a] = (int)nint_away(0.5 * p->n_grid[a]);
+    }
+    for (int k = 0; k < 2; ++k) {
+        exx_status st = build_class(c, c->cls[k], p->r_pe[k], p->r_me[k]);
+        if (st != EXX_OK) return bail(st);
+    }
+    c->block = p->block_threads ? p->block_threads : 256;
+    int bs[8];
+    int nb = solve_block_sizes(bs, 8);
+    if (std::find(bs, bs + nb, c->block) == bs + nb)
+        return bail(fail(c, EXX_EINVAL, "block_threads %d not available", c->block));
+    for (auto &e : c->ev)
+        if (hipEventCreate(&e) != hipSuccess) return bail(fail(c, EXX_EDEVICE, "hipEventCreate failed"));
+    c->have_events = true;
+    c->state = 1;
+    *out = c;
+    return EXX_OK;
+}
+
+exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pairs)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_pairs: ctx is NULL");
+    if (c->state < 1) return fail(c, EXX_ESTATE, "exx_pairs before exx_setup");
+    if (n_orb < 1 || !C) return fail(c, EXX_EINVAL, "exx_pairs: need n_orb >= 1 and centers");
+    if (hipSetDevice(c->device) != hipSuccess) return fail(c, EXX_EDEVICE, "hipSetDevice failed");
+    const double *L = c->prm.cell;
+    const int *N = c->prm.n_grid;
+    for (int i = 0; i < 3 * n_orb; ++i)
+        if (!std::isfinite(C[i])) return fail(c, EXX_EINVAL, "centre coordinate %d is not finite", i);
+    c->ij.clear();
+    c->gc.clear();
+    c->out_off.clear();
+    c->n_self = 0;
+    const double r2 = c->prm.r_pair * c->prm.r_pair;
+    long long off = 0;
+    for (int i = 0; i < n_orb; ++i)
+        for (int j = i; j < n_orb; ++j) {
+            double d[3], dd = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                d[a] = C[3 * j + a] - C[3 * i + a];
+                d[a] -= L[a] * (double)nint_away(d[a] / L[a]);
+                dd += d[a] * d[a];
+            }
+            if (i != j && !(dd < r2)) continue;
+            int g[3];
+            for (int a = 0; a < 3; ++a) {
+                double m = C[3 * i + a] + 0.5 * d[a];
+                m -= L[a] * std::floor(m / L[a]);
+                g[a] = mod_pos(nint_away(m / c->h[a]), N[a]);
+            }
+            const int cl = i == j ? 0 : 1;
+            c->ij.push_back(int2{i, j});
+            c->gc.push_back(int4{g[0], g[1], g[2], cl});
+            c->out_off.push_back(off);
+            off += c->cls[cl].n_pe + c->cls[cl].n_sh;
+            if (i == j) ++c->n_self;
+        }
+    c->n_pairs = (int64_t)c->ij.size();
+    c->vout_n = off;
+    c->n_orb = n_orb;
+    c->orb_ptr.assign(n_orb + 1, 0);
+    for (auto &q : c->ij) {
+        c->orb_ptr[q.x + 1]++;
+        if (q.y != q.x) c->orb_ptr[q.y + 1]++;
+    }
+    for (int i = 0; i < n_orb; ++i) c->orb_ptr[i + 1] += c->orb_ptr[i];
+    c->orb_pairs.assign(c->orb_ptr[n_orb], 0);
+    {
+        std::vector<int> fill(c->orb_ptr.begin(), c->orb_ptr.end() - 1);
+        for (int p = 0; p < (int)c->ij.size(); ++p) {
+            c->orb_pairs[fill[c->ij[p].x]++] = p;
+            if (c->ij[p].y != c->ij[p].x) c->orb_pairs[fill[c->ij[p].y]++] = p;
+        }
+    }
+    exx_status st;
+    if ((st = upload(c, c->d_ij, c->ij)) != EXX_OK) return st;
+    if ((st = upload(c, c->d_gc, c->gc)) != EXX_OK) return st;
+    if ((st = upload(c, c->d_off, c->out_off)) != EXX_OK) return st;
+    if ((st = upload(c, c->d_orb_ptr, c->orb_ptr)) != EXX_OK) return st;
+    if ((st = upload(c, c->d_orb_pairs, c->orb_pairs)) != EXX_OK) return st;
+    const size_t np = (size_t)c->n_pairs;
+    if ((st = dev_reserve(c, c->d_vout, (size_t)c->vout_n)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_q, np * NLM)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_e, np)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_relres, np)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_iters, np)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_conv, np)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_counter, 1)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_E, 1)) != EXX_OK) return st;
+    // persistent grid and per-slot scratch
+    int per_cu = 0;
+    HIPCHK(c, solve_occupancy(c->block, &per_cu));
+    per_cu = std::max(per_cu, 1);
+    c->grid = (int)std::min<int64_t>(c->n_pairs, (int64_t)per_cu * c->n_cu);
+    c->grid = std::max(c->grid, 1);
+    c->slots = c->grid;
+    c->slot_n = ((long long)std::max(c->cls[0].n_pe, c->cls[1].n_pe) + 63) / 64 * 64;
+    if ((st = dev_reserve(c, c->d_scratch, (size_t)c->slots * 3 * c->slot_n)) != EXX_OK) return st;
+    // right-hand sides of one wave of pairs; the wave is as large as the
+    // device allows (one launch of each kernel when everything fits)
+    {
+        size_t freeb = 0, totalb = 0;
+        HIPCHK(c, hipMemGetInfo(&freeb, &totalb));
+        const size_t per_pair = (size_t)c->slot_n * sizeof(double);
+        int64_t w = c->n_pairs;
+        if (c->prm.wave_pairs > 0) w = std::min<int64_t>(w, c->prm.wave_pairs);
+        const size_t have = c->d_rhs.n * sizeof(double);
+        const size_t budget = freeb + have > ((size_t)2 << 30) ? freeb + have - ((size_t)2 << 30) : 0;
+        w = std::min<int64_t>(w, (int64_t)(budget / per_pair));
+        if (c->prm.keep_intermediates) w = c->n_pairs;
+        if (w < 1) return fail(c, EXX_ENOMEM, "no device memory left for right-hand sides");
+        c->wave_n = (int)w;
+        if ((st = dev_reserve(c, c->d_rhs, (size_t)w * c->slot_n)) != EXX_OK) return st;
+        if (c->prm.keep_intermediates &&
+            (st = dev_reserve(c, c->d_rho_keep, (size_t)c->n_pairs * c->slot_n)) != EXX_OK)
+            return st;
+    }
+    c->state = 2;
+    if (n_pairs) *n_pairs = c->n_pairs;
+    return EXX_OK;
+}
+
+exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_solve: ctx is NULL");
+    if (c->state < 2) return fail(c, EXX_ESTATE, "exx_solve before exx_pairs");
+    if (!phi) return fail(c, EXX_EINVAL, "exx_solve: phi is NULL");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    SolveArgs a{};
+    a.cls[0] = class_dev(c->cls[0]);
+    a.cls[1] = class_dev(c->cls[1]);
+    a.pair_gc = c->d_gc.p;
+    a.pair_ij = c->d_ij.p;
+    a.out_off = c->d_off.p;
+    a.phi = phi;
+    a.phi_f32 = c->prm.orbital_dtype == EXX_F32;
+    a.nx = c->prm.n_grid[0];
+    a.ny = c->prm.n_grid[1];
+    a.nz = c->prm.n_grid[2];
+    a.ngrid = (long long)a.nx * a.ny * a.nz;
+    a.vout = c->d_vout.p;
+    a.scratch = c->d_scratch.p;
+    a.rhs = c->d_rhs.p;
+    a.rho_keep = c->prm.keep_intermediates ? c->d_rho_keep.p : nullptr;
+    a.slot_n = c->slot_n;
+    a.q_out = c->d_q.p;
+    a.e_out = c->d_e.p;
+    a.iters_out = c->d_iters.p;
+    a.conv_out = c->d_conv.p;
+    a.relres_out = c->d_relres.p;
+    a.counter = c->d_counter.p;
+    a.static_sched = 0;
+    a.guess = c->prm.guess;
+    a.precision = c->prm.precision;
+    for (int k = 0; k < 3; ++k) a.h[k] = c->h[k];
+    for (int k = 0; k < 4; ++k) a.wfd[k] = kFD[k];
+    a.tol = c->prm.cg_rtol;
+    a.inner_tol = c->prm.inner_rtol;
+    a.maxit = c->prm.cg_max_iter;
+    ylm_norms(a.ylm_norm);
+    c->n_waves = 0;
+    HIPCHK(c, hipEventRecord(c->ev[0], s));
+    for (int64_t w0 = 0; w0 < c->n_pairs; w0 += c->wave_n) {
+        a.wave_begin = (int)w0;
+        a.wave_n = (int)std::min<int64_t>(c->wave_n, c->n_pairs - w0);
+        HIPCHK(c, launch_prep(a, s));
+        HIPCHK(c, launch_zero_int(c->d_counter.p, 1, s));
+        if (w0 == 0) HIPCHK(c, hipEventRecord(c->ev[5], s));
+        HIPCHK(c, launch_solve(a, std::min(c->grid, a.wave_n), c->block, s));
+        ++c->n_waves;
+    }
+    HIPCHK(c, hipEventRecord(c->ev[1], s));
+    c->phi = phi;
+    c->state = 3;
+    c->solved_once = true;
+    return EXX_OK;
+}
+
+exx_status exx_energy_potential(exx_ctx *c, double *e_xx, void *dxx, void *stream)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_energy_potential: ctx is NULL");
+    if (c->state < 3) return fail(c, EXX_ESTATE, "exx_energy_potential before exx_solve");
+    if (!e_xx || !dxx) return fail(c, EXX_EINVAL, "exx_energy_potential: e_xx and dxx are required");
+    HIPCHK(c, hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    DxxArgs d{};
+    d.cls[0] = class_dev(c->cls[0]);
+    d.cls[1] = class_dev(c->cls[1]);
+    d.pair_gc = c->d_gc.p;
+    d.pair_ij = c->d_ij.p;
+    d.out_off = c->d_off.p;
+    d.orb_ptr = c->d_orb_ptr.p;
+    d.orb_pairs = c->d_orb_pairs.p;
+    d.phi = c->phi;
+    d.dxx = dxx;
+    d.f32 = c->prm.orbital_dtype == EXX_F32;
+    d.nx = c->prm.n_grid[0];
+    d.ny = c->prm.n_grid[1];
+    d.nz = c->prm.n_grid[2];
+    d.ngrid = (long long)d.nx * d.ny * d.nz;
+    d.vout = c->d_vout.p;
+    HIPCHK(c, hipEventRecord(c->ev[2], s));
+    HIPCHK(c, launch_dxx(d, c->n_orb, s));
+    HIPCHK(c, hipEventRecord(c->ev[3], s));
+    HIPCHK(c, launch_energy(c->d_e.p, c->d_ij.p, (int)c->n_pairs, c->d_E.p, s));
+    HIPCHK(c, hipEventRecord(c->ev[4], s));
+    HIPCHK(c, hipMemcpyAsync(e_xx, c->d_E.p, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    // convergence flags
+    std::vector<int> conv((size_t)c->n_pairs);
+    HIPCHK(c, hipMemcpy(conv.data(), c->d_conv.p, conv.size() * sizeof(int), hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < conv.size(); ++k)
+        if (!conv[k]) return fail(c, EXX_ENOCONV, "pair %zu did not converge in %d iterations", k, c->prm.cg_max_iter);
+    return EXX_OK;
+}
+
+exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
+{
+    if (!c || !st) return fail(c, EXX_EINVAL, "exx_stats: null argument");
+    std::memset(st, 0, sizeof *st);
+    st->n_pairs = c->n_pairs;
+    st->n_self = c->n_self;
+    st->solve_grid = c->grid;
+    st->solve_block = c->block;
+    for (int k = 0; k < 2; ++k) {
+        st->n_pe[k] = c->cls[k].n_pe;
+        st->n_me[k] = c->cls[k].n_pe + c->cls[k].n_sh;
+    }
+    st->device_bytes = (int64_t)(c->d_vout.n * 8 + c->d_scratch.n * 8 + c->d_scratch32.n * 4 + c->d_q.n * 8 +
+                                 c->d_rhs.n * 8 + c->d_rho_keep.n * 8);
+    if (c->state < 3) return EXX_OK;
+    HIPCHK(c, hipSetDevice(c->device));
+    const size_t np = (size_t)c->n_pairs;
+    std::vector<int> it(np), cv(np);
+    std::vector<double> rr(np);
+    HIPCHK(c, hipMemcpy(it.data(), c->d_iters.p, np * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(cv.data(), c->d_conv.p, np * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(rr.data(), c->d_relres.p, np * sizeof(double), hipMemcpyDeviceToHost));
+    st->iters_min = np ? it[0] : 0;
+    const int sphi = c->prm.orbital_dtype == EXX_F32 ? 4 : 8;
+    for (size_t p = 0; p < np; ++p) {
+        const HostClass &k = c->cls[c->gc[p].w];
+        st->iters_total += it[p];
+        st->iters_min = std::min(st->iters_min, it[p]);
+        st->iters_max = std::max(st->iters_max, it[p]);
+        st->n_not_converged += cv[p] ? 0 : 1;
+        st->relres_max = std::max(st->relres_max, rr[p]);
+        const int64_t cg = (int64_t)it[p] * 8 * 8 * k.n_pe;
+        st->cg_bytes += cg;
+        st->solve_bytes += cg + (int64_t)2 * k.n_pe * sphi + (int64_t)k.n_sh * 8;
+        const int m = c->ij[p].x == c->ij[p].y ? 1 : 2;
+        st->dxx_bytes += (int64_t)m * (k.n_pe + k.n_sh) * (8 + sphi);
+    }
+    st->dxx_bytes += (int64_t)c->n_orb * c->prm.n_grid[0] * c->prm.n_grid[1] * c->prm.n_grid[2] * sphi;
+    float ms = 0.f;
+    st->n_waves = c->n_waves;
+    if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) st->solve_ms = ms;
+    st->prep_ms = st->cg_ms = -1.0;
+    if (c->n_waves == 1) {
+        if (hipEventElapsedTime(&ms, c->ev[0], c->ev[5]) == hipSuccess) st->prep_ms = ms;
+        if (hipEventElapsedTime(&ms, c->ev[5], c->ev[1]) == hipSuccess) st->cg_ms = ms;
+    }
+    if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) st->dxx_ms = ms;
+    if (hipEventElapsedTime(&ms, c->ev[3], c->ev[4]) == hipSuccess) st->energy_ms = ms;
+    return EXX_OK;
+}
+
+exx_status exx_pair_info(exx_ctx *c, int32_t *pi, int32_t *pj, int32_t *origin, double *e, int32_t *iters,
+                         int32_t *converged, double *relres)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_pair_info: ctx is NULL");
+    if (c->state < 2) return fail(c, EXX_ESTATE, "exx_pair_info before exx_pairs");
+    const size_t np = (size_t)c->n_pairs;
+    for (size_t p = 0; p < np; ++p) {
+        if (pi) pi[p] = c->ij[p].x;
+        if (pj) pj[p] = c->ij[p].y;
+        if (origin) { origin[3 * p] = c->gc[p].x; origin[3 * p + 1] = c->gc[p].y; origin[3 * p + 2] = c->gc[p].z; }
+    }
+    if (e || iters || converged || relres) {
+        if (c->state < 3) return fail(c, EXX_ESTATE, "exx_pair_info: no solve yet");
+        HIPCHK(c, hipSetDevice(c->device));
+        HIPCHK(c, hipDeviceSynchronize());
+        if (e) HIPCHK(c, hipMemcpy(e, c->d_e.p, np * sizeof(double), hipMemcpyDeviceToHost));
+        if (iters) HIPCHK(c, hipMemcpy(iters, c->d_iters.p, np * sizeof(int), hipMemcpyDeviceToHost));
+        if (converged) HIPCHK(c, hipMemcpy(converged, c->d_conv.p, np * sizeof(int), hipMemcpyDeviceToHost));
+        if (relres) HIPCHK(c, hipMemcpy(relres, c->d_relres.p, np * sizeof(double), hipMemcpyDeviceToHost));
+    }
+    return EXX_OK;
+}
+
+exx_status exx_debug_pair(exx_ctx *c, int64_t pair, double *v_pe, double *v_shell, double *q_lm, double *rho,
+                          double *rhs)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_debug_pair: ctx is NULL");
+    if (c->state < 3) return fail(c, EXX_ESTATE, "exx_debug_pair: no solve yet");
+    if (pair < 0 || pair >= c->n_pairs) return fail(c, EXX_EINVAL, "pair %lld out of range", (long long)pair);
+    if ((rho || rhs) && !c->prm.keep_intermediates)
+        return fail(c, EXX_ESTATE, "exx_debug_pair: intermediates were not kept (keep_intermediates = 0)");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceSynchronize());
+    const HostClass &k = c->cls[c->gc[pair].w];
+    const double *v = c->d_vout.p + c->out_off[pair];
+    if (v_pe) HIPCHK(c, hipMemcpy(v_pe, v, (size_t)k.n_pe * 8, hipMemcpyDeviceToHost));
+    if (v_shell) HIPCHK(c, hipMemcpy(v_shell, v + k.n_pe, (size_t)k.n_sh * 8, hipMemcpyDeviceToHost));
+    if (q_lm) HIPCHK(c, hipMemcpy(q_lm, c->d_q.p + pair * NLM, NLM * 8, hipMemcpyDeviceToHost));
+    if (rho) HIPCHK(c, hipMemcpy(rho, c->d_rho_keep.p + (size_t)pair * c->slot_n, (size_t)k.n_pe * 8, hipMemcpyDeviceToHost));
+    if (rhs) HIPCHK(c, hipMemcpy(rhs, c->d_rhs.p + (size_t)pair * c->slot_n, (size_t)k.n_pe * 8, hipMemcpyDeviceToHost));
+    return EXX_OK;
+}
+
+const char *exx_last_error(const exx_ctx *c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+
+void exx_destroy(exx_ctx *c)
+{
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (auto &k : c->cls) free_class(k);
+    dev_free(c->d_ij); dev_free(c->d_gc); dev_free(c->d_off); dev_free(c->d_orb_ptr); dev_free(c->d_orb_pairs);
+    dev_free(c->d_vout); dev_free(c->d_q); dev_free(c->d_e); dev_free(c->d_relres); dev_free(c->d_scratch);
+    dev_free(c->d_rhs); dev_free(c->d_rho_keep);
+    dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
+    if (c->have_events)
+        for (auto &e : c->ev)
+            if (e) (void)hipEventDestroy(e);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+// exx_internal.h -- structures shared by the host code and the HIP kernels of
+// the pair-Poisson exact-exchange library (library-internal, not installed).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace exx {
+
+constexpr int LMAX = 6;                      // multipole order (Eq. me)
+constexpr int NLM = (LMAX + 1) * (LMAX + 1); // 49 real harmonics
+constexpr int FD_N = 3;                      // stencil half-width (Eq. d2_1)
+
+// Local offsets (grid units, |o| < 512) packed into one int: 10 bits per axis.
+__host__ __device__ inline int pack_xyz(int x, int y, int z)
+{
+    return (x + 512) | ((y + 512) << 10) | ((z + 512) << 20);
+}
+__host__ __device__ inline void unpack_xyz(int v, int &x, int &y, int &z)
+{
+    x = (v & 1023) - 512;
+    y = ((v >> 10) & 1023) - 512;
+    z = ((v >> 20) & 1023) - 512;
+}
+
+// Device view of one proto-subdomain class (PE sphere + ME shell).
+//
+// PE storage ("row-packed"): rows (z, y) of the sphere in z-major, y-minor
+// order, each row the contiguous x run [xlo, xhi]; element (x, y, z) lives
+// at base(z, y) + x - xlo(z, y).  This is exactly the z, y, x lexicographic
+// order of Alg. 2, so local index q of Eq. rbar equals the packed index.
+// Shell storage: the same lexicographic order over shell points; a shell
+// row (z, y) holds the run [mlo, plo-1] then [phi+1, mhi].
+struct ClassDev {
+    const int4 *pe_rows;   // [pnz][pny] {base, xlo, xhi, 0}; empty row: xlo > xhi
+    const int4 *me_rows;   // [mnz][mny][2] {pe_base, plo, phi, sh_base}, {mlo, mhi, 0, 0}
+    const int *pe_xyz;     // [n_pe] packed offsets
+    const int *sh_xyz;     // [n_sh] packed offsets
+    const int *cols;       // [n_cols] packed (x, y, 0) of the PE projection, sorted (y, x)
+    int n_cols;
+    int pxlo, pylo, pzlo, pnx, pny, pnz;   // PE bounding box
+    int mxlo, mylo, mzlo, mnx, mny, mnz;   // ME bounding box
+    int n_pe, n_sh;
+};
+
+struct SolveArgs {
+    ClassDev cls[2];
+    const int4 *pair_gc;        // [n_pairs] {gx, gy, gz, class}
+    const int2 *pair_ij;        // [n_pairs] {i, j}
+    const long long *out_off;   // [n_pairs] offset of the pair's v in vout
+    const void *phi;            // [n_orb][Nz][Ny][Nx]
+    int phi_f32;
+    int nx, ny, nz;
+    long long ngrid;
+    double *vout;               // per pair: v on PE (n_pe) then v on shell (n_sh)
+    double *rhs;                // per wave pair: right-hand side b (slot_n each)
+    double *rho_keep;           // optional per pair: pair density (slot_n each)
+    double *scratch;            // per CG slot: r, p, Ap (slot_n each)
+    long long slot_n;           // elements per array (max n_pe, padded)
+    float *scratch32;           // per CG slot: FP32 work vectors (refinement)
+    double *q_out;              // [n_pairs][NLM]
+    double *e_out;              // [n_pairs]
+    int *iters_out;             // [n_pairs]
+    int *conv_out;              // [n_pairs]
+    double *relres_out;         // [n_pairs]
+    int *counter;               // dynamic pair queue (wave-relative)
+    int wave_begin, wave_n;     // pairs [wave_begin, wave_begin + wave_n)
+    int static_sched;           // 1: pair = block + k*grid, slot = block
+    int guess;                  // 0 zero, 1 v already in vout (previous step)
+    int precision;              // 0 FP64, 1 FP32 inner + FP64 refinement
+    double h[3];
+    double wfd[4];              // central-difference weights w_0..w_3
+    double tol;                 // relative residual target
+    double inner_tol;           // FP32 inner solve target
+    int maxit;
+    double ylm_norm[NLM];       // normalization of the real solid harmonics
+};
+
+struct DxxArgs {
+    ClassDev cls[2];
+    const int4 *pair_gc;
+    const int2 *pair_ij;
+    const long long *out_off;
+    const int *orb_ptr;         // [n_orb + 1] CSR over orbitals
+    const int *orb_pairs;       // pair indices, ascending per orbital
+    const void *phi;
+    void *dxx;
+    int f32;
+    int nx, ny, nz;
+    long long ngrid;
+    const double *vout;
+};
+
+// Launchers (exx_kernels.hip).
+hipError_t launch_prep(const SolveArgs &a, hipStream_t s);
+hipError_t launch_solve(const SolveArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_dxx(const DxxArgs &a, int n_orb, hipStream_t s);
+hipError_t launch_energy(const double *e, const int2 *ij, int n_pairs, double *out, hipStream_t s);
+hipError_t launch_zero_int(int *p, int n, hipStream_t s);
+int solve_block_sizes(int *out, int max_n);
+hipError_t solve_occupancy(int block, int *blocks_per_cu);
+
+}  // namespace exx

@@ -1,0 +1,232 @@
+"""Thin ctypes binding of the C ABI in include/exx.h.
+
+Argument marshalling only: every step of the pair-Poisson path runs in the
+HIP kernels of libexx_mi355x.so.  There is no CPU fallback; if the library
+is missing the import fails.  PyTorch supplies device memory and streams.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libexx_mi355x.so")
+
+EXX_OK, EXX_EINVAL, EXX_ENOMEM, EXX_EDEVICE, EXX_ENOCONV, EXX_ESTATE = 0, -1, -2, -3, -4, -5
+_STATUS = {0: "EXX_OK", -1: "EXX_EINVAL", -2: "EXX_ENOMEM", -3: "EXX_EDEVICE", -4: "EXX_ENOCONV",
+           -5: "EXX_ESTATE"}
+PRECISION = {"fp64": 0, "fp32_refine": 1}
+ORBITAL_DTYPE = {"f64": 0, "f32": 1}
+GUESS = {"zero": 0, "previous": 1, "extrap": 2}
+NLM = 49
+
+EXPORTS = ["exx_default_params", "exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats",
+           "exx_pair_info", "exx_debug_pair", "exx_last_error", "exx_destroy"]
+
+
+class ExxParams(C.Structure):
+    _fields_ = [("n_grid", C.c_int32 * 3), ("cell", C.c_double * 3), ("r_pair", C.c_double),
+                ("r_pe", C.c_double * 2), ("r_me", C.c_double * 2), ("fd_half_width", C.c_int32),
+                ("l_max", C.c_int32), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
+                ("precision", C.c_int32), ("orbital_dtype", C.c_int32), ("guess", C.c_int32),
+                ("inner_rtol", C.c_double), ("block_threads", C.c_int32), ("wave_pairs", C.c_int64),
+                ("keep_intermediates", C.c_int32)]
+
+
+class ExxStats(C.Structure):
+    _fields_ = [("n_pairs", C.c_int64), ("n_self", C.c_int64), ("iters_total", C.c_int64),
+                ("iters_min", C.c_int32), ("iters_max", C.c_int32), ("n_not_converged", C.c_int64),
+                ("relres_max", C.c_double), ("solve_ms", C.c_double), ("prep_ms", C.c_double),
+                ("cg_ms", C.c_double), ("dxx_ms", C.c_double), ("energy_ms", C.c_double),
+                ("solve_grid", C.c_int32), ("solve_block", C.c_int32), ("n_pe", C.c_int64 * 2),
+                ("n_me", C.c_int64 * 2), ("cg_bytes", C.c_int64), ("solve_bytes", C.c_int64),
+                ("dxx_bytes", C.c_int64), ("device_bytes", C.c_int64), ("n_waves", C.c_int32)]
+
+
+class ExxError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load() -> C.CDLL:
+    """Loads the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with paper_1911_10630_amd/build.py "
+                          "(there is no CPU fallback)")
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dp = C.c_void_p, C.c_int32, C.c_int64, C.POINTER(C.c_double)
+    L.exx_default_params.argtypes = [C.POINTER(ExxParams)]
+    L.exx_default_params.restype = None
+    L.exx_setup.argtypes = [C.POINTER(ExxParams), C.c_int, C.POINTER(vp)]
+    L.exx_pairs.argtypes = [vp, i32, vp, C.POINTER(i64)]
+    L.exx_solve.argtypes = [vp, vp, vp]
+    L.exx_energy_potential.argtypes = [vp, dp, vp, vp]
+    L.exx_stats.argtypes = [vp, C.POINTER(ExxStats)]
+    L.exx_pair_info.argtypes = [vp] + [vp] * 7
+    L.exx_debug_pair.argtypes = [vp, i64] + [vp] * 5
+    L.exx_last_error.argtypes = [vp]
+    L.exx_last_error.restype = C.c_char_p
+    L.exx_destroy.argtypes = [vp]
+    L.exx_destroy.restype = None
+    for f in ["exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats", "exx_pair_info",
+              "exx_debug_pair"]:
+        getattr(L, f).restype = C.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data_as(C.c_void_p)
+    return C.c_void_p(a.data_ptr())
+
+
+def _stream_handle(stream, device):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(device)
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Exx:
+    """One exact-exchange context on one GPU (exx_setup ... exx_destroy)."""
+
+    def __init__(self, n_grid, cell, r_pair, r_pe, r_me, *, cg_rtol=1e-10, cg_max_iter=20000,
+                 precision="fp64", orbital_dtype="f64", guess="zero", inner_rtol=1e-5, block_threads=0,
+                 wave_pairs=0, keep_intermediates=False, device=0):
+        L = load()
+        p = ExxParams()
+        L.exx_default_params(C.byref(p))
+        for a in range(3):
+            p.n_grid[a] = int(n_grid[a])
+            p.cell[a] = float(cell[a])
+        rpe = r_pe if isinstance(r_pe, (tuple, list)) else (r_pe, r_pe)
+        rme = r_me if isinstance(r_me, (tuple, list)) else (r_me, r_me)
+        p.r_pair = float(r_pair)
+        p.r_pe[0], p.r_pe[1] = float(rpe[0]), float(rpe[1])
+        p.r_me[0], p.r_me[1] = float(rme[0]), float(rme[1])
+        p.cg_rtol = float(cg_rtol)
+        p.cg_max_iter = int(cg_max_iter)
+        p.precision = PRECISION[precision]
+        p.orbital_dtype = ORBITAL_DTYPE[orbital_dtype]
+        p.guess = GUESS[guess]
+        p.inner_rtol = float(inner_rtol)
+        p.block_threads = int(block_threads)
+        p.wave_pairs = int(wave_pairs)
+        p.keep_intermediates = 1 if keep_intermediates else 0
+        self.params = p
+        self.device = int(device)
+        self.n_grid = tuple(int(v) for v in n_grid)
+        self.orbital_dtype = orbital_dtype
+        h = C.c_void_p()
+        st = L.exx_setup(C.byref(p), self.device, C.byref(h))
+        if st != EXX_OK:
+            raise ExxError(st, L.exx_last_error(None).decode())
+        self._h = h
+        self.n_pairs = 0
+        self.n_orb = 0
+
+    @classmethod
+    def from_workload(cls, wl, **kw):
+        kw.setdefault("cg_rtol", wl.cg_rtol)
+        kw.setdefault("precision", wl.precision)
+        kw.setdefault("orbital_dtype", wl.orbital_dtype)
+        return cls(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, **kw)
+
+    def _check(self, st):
+        if st != EXX_OK:
+            raise ExxError(st, load().exx_last_error(self._h).decode())
+
+    def pairs(self, centers) -> int:
+        c = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, 3))
+        n = C.c_int64()
+        self._check(load().exx_pairs(self._h, c.shape[0], _ptr(c), C.byref(n)))
+        self.n_pairs = int(n.value)
+        self.n_orb = c.shape[0]
+        return self.n_pairs
+
+    def _check_grid(self, t, name):
+        import torch
+        want = torch.float64 if self.orbital_dtype == "f64" else torch.float32
+        Nx, Ny, Nz = self.n_grid
+        if not t.is_cuda or t.dtype != want or not t.is_contiguous() or tuple(t.shape) != (self.n_orb, Nz, Ny, Nx):
+            raise ValueError(f"{name} must be a contiguous {want} CUDA tensor of shape {(self.n_orb, Nz, Ny, Nx)}")
+
+    def solve(self, phi, stream=None):
+        self._check_grid(phi, "phi")
+        self._phi = phi
+        self._check(load().exx_solve(self._h, _ptr(phi), _stream_handle(stream, phi.device)))
+
+    def energy_potential(self, dxx, stream=None, allow_noconv=False) -> float:
+        self._check_grid(dxx, "dxx")
+        e = C.c_double()
+        st = load().exx_energy_potential(self._h, C.byref(e), _ptr(dxx), _stream_handle(stream, dxx.device))
+        if st == EXX_ENOCONV and allow_noconv:
+            return e.value
+        self._check(st)
+        return e.value
+
+    def step(self, phi, dxx=None, stream=None):
+        import torch
+        if dxx is None:
+            dxx = torch.empty_like(phi)
+        self.solve(phi, stream)
+        return self.energy_potential(dxx, stream), dxx
+
+    def stats(self) -> dict:
+        s = ExxStats()
+        self._check(load().exx_stats(self._h, C.byref(s)))
+        out = {}
+        for name, _ in ExxStats._fields_:
+            v = getattr(s, name)
+            out[name] = list(v) if hasattr(v, "__len__") else v
+        return out
+
+    def pair_info(self, results=True) -> dict:
+        n = self.n_pairs
+        d = dict(i=np.zeros(n, np.int32), j=np.zeros(n, np.int32), origin=np.zeros((n, 3), np.int32))
+        if results:
+            d.update(e=np.zeros(n), iters=np.zeros(n, np.int32), converged=np.zeros(n, np.int32),
+                     relres=np.zeros(n))
+        self._check(load().exx_pair_info(self._h, _ptr(d["i"]), _ptr(d["j"]), _ptr(d["origin"]),
+                                         _ptr(d.get("e")), _ptr(d.get("iters")), _ptr(d.get("converged")),
+                                         _ptr(d.get("relres"))))
+        return d
+
+    def debug_pair(self, pair: int, n_pe: int, n_shell: int, intermediates: bool = False) -> dict:
+        d = dict(x=np.zeros(n_pe), vsh=np.zeros(max(n_shell, 1)), Q=np.zeros(NLM))
+        if intermediates:
+            d.update(rho=np.zeros(n_pe), b=np.zeros(n_pe))
+        self._check(load().exx_debug_pair(self._h, int(pair), _ptr(d["x"]), _ptr(d["vsh"]), _ptr(d["Q"]),
+                                          _ptr(d.get("rho")), _ptr(d.get("b"))))
+        d["vsh"] = d["vsh"][:n_shell]
+        return d
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().exx_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

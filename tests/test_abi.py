@@ -1,0 +1,144 @@
+"""The C ABI on the host: the library loads, exports every declared symbol,
+the ctypes structs match the header's layout, and argument validation
+returns the documented status codes without touching a GPU."""
+import ctypes as C
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1911_10630_amd import exx as X
+from paper_1911_10630_amd import synth as S
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "exx.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(exx_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    lib = X.load()
+    names = _declared()
+    assert set(names) == set(X.EXPORTS)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", X.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}$", out, flags=re.M), n
+
+
+def _c_layout():
+    src = r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "exx.h"
+#define O(T, f) printf("%s %zu\n", #f, offsetof(T, f));
+int main(void) {
+  printf("params %zu\n", sizeof(exx_params));
+  O(exx_params, n_grid) O(exx_params, cell) O(exx_params, r_pair) O(exx_params, r_pe) O(exx_params, r_me)
+  O(exx_params, fd_half_width) O(exx_params, l_max) O(exx_params, cg_rtol) O(exx_params, cg_max_iter)
+  O(exx_params, precision) O(exx_params, orbital_dtype) O(exx_params, guess) O(exx_params, inner_rtol)
+  O(exx_params, block_threads) O(exx_params, wave_pairs) O(exx_params, keep_intermediates)
+  printf("stats %zu\n", sizeof(exx_stats_t));
+  O(exx_stats_t, relres_max) O(exx_stats_t, cg_ms) O(exx_stats_t, n_pe) O(exx_stats_t, n_me)
+  O(exx_stats_t, cg_bytes) O(exx_stats_t, n_waves)
+  return 0;
+}
+'''
+    with tempfile.TemporaryDirectory() as d:
+        c = os.path.join(d, "l.c")
+        open(c, "w").write(src)
+        exe = os.path.join(d, "l")
+        subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), c, "-o", exe])
+        out = subprocess.check_output([exe], text=True)
+    return {k: int(v) for k, v in (ln.split() for ln in out.strip().splitlines())}
+
+
+def test_struct_layout_matches_header():
+    lay = _c_layout()
+    assert lay["params"] == C.sizeof(X.ExxParams)
+    assert lay["stats"] == C.sizeof(X.ExxStats)
+    for f in ["n_grid", "cell", "r_pair", "r_pe", "r_me", "fd_half_width", "l_max", "cg_rtol", "cg_max_iter",
+              "precision", "orbital_dtype", "guess", "inner_rtol", "block_threads", "wave_pairs",
+              "keep_intermediates"]:
+        assert lay[f] == getattr(X.ExxParams, f).offset, f
+    for f in ["relres_max", "cg_ms", "n_pe", "n_me", "cg_bytes", "n_waves"]:
+        assert lay[f] == getattr(X.ExxStats, f).offset, f
+
+
+def test_default_params():
+    p = X.ExxParams()
+    X.load().exx_default_params(C.byref(p))
+    assert p.fd_half_width == 3 and p.l_max == 6 and p.cg_rtol == 1e-10 and p.precision == 0
+
+
+def _setup_status(**over):
+    L = X.load()
+    p = X.ExxParams()
+    L.exx_default_params(C.byref(p))
+    wl = S.c1_small()
+    for a in range(3):
+        p.n_grid[a] = wl.n_grid[a]
+        p.cell[a] = wl.cell[a]
+    p.r_pair = wl.r_pair
+    p.r_pe[0] = p.r_pe[1] = wl.r_pe[0]
+    p.r_me[0] = p.r_me[1] = wl.r_me[0]
+    for k, v in over.items():
+        if isinstance(v, tuple):
+            arr = getattr(p, k)
+            for i, vv in enumerate(v):
+                arr[i] = vv
+        else:
+            setattr(p, k, v)
+    h = C.c_void_p()
+    st = L.exx_setup(C.byref(p), 0, C.byref(h))
+    msg = L.exx_last_error(None).decode()
+    if st == 0:
+        L.exx_destroy(h)
+    return st, msg
+
+
+@pytest.mark.parametrize("over,needle", [
+    (dict(r_me=(4.0 * S.ANG + 0.5, 4.0 * S.ANG + 0.5)), "n max(h)"),   # shell thinner than the stencil
+    (dict(r_pe=(0.0, 1.0)), "r_pe[0]"),
+    (dict(fd_half_width=2), "fd_half_width"),
+    (dict(l_max=4), "l_max"),
+    (dict(precision=7), "precision"),
+    (dict(orbital_dtype=3), "orbital_dtype"),
+    (dict(cg_rtol=0.0), "cg_rtol"),
+    (dict(n_grid=(4, 48, 48)), "n_grid"),
+])
+def test_setup_rejects_bad_parameters(over, needle):
+    st, msg = _setup_status(**over)
+    assert st == X.EXX_EINVAL and needle in msg
+
+
+def test_setup_null_pointers():
+    L = X.load()
+    assert L.exx_setup(None, 0, None) == X.EXX_EINVAL
+    h = C.c_void_p()
+    assert L.exx_setup(None, 0, C.byref(h)) == X.EXX_EINVAL
+    assert "NULL" in L.exx_last_error(None).decode()
+
+
+def test_calls_on_null_context():
+    L = X.load()
+    assert L.exx_pairs(None, 1, None, None) == X.EXX_EINVAL
+    assert L.exx_solve(None, None, None) == X.EXX_EINVAL
+    e = C.c_double()
+    assert L.exx_energy_potential(None, C.byref(e), None, None) == X.EXX_EINVAL
+    L.exx_destroy(None)
+
+
+def test_setup_without_gpu_reports_device_error():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    st, msg = _setup_status()
+    assert st == X.EXX_EDEVICE and "device" in msg
