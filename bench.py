@@ -1,0 +1,160 @@
+"""Benchmark: pair Poisson solves/s and ms per E_xx + D_xx step on one MI355X.
+
+Workload (default): 64 water-like molecules, 256 localized orbitals in a
+12.4 A cube on a 128^3 grid, R_pair = 5 A, R_PE = 4 A, R_ME = 5 A, FP64,
+CG to 1e-10 relative residual (seeded synthetic orbitals; see synth.py).
+One step = exx_solve + exx_energy_potential over every pair of the step.
+
+Prints ONE JSON line.  `roofline` describes the dominant kernel (the
+persistent CG kernel): algorithmic bytes per launch (64 B per unknown per
+CG iteration in FP64) over its HIP-event duration on the launch stream.
+`cpu_baseline` times the FP64 CPU oracle on a bounded sample of the same
+workload's pairs on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "cg_traffic.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1911_10630_amd", "csrc", "exx_kernels.hip")
+
+
+def kernel_hash() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, pi, pj, n_sample, threads, seed=0):
+    """FP64 oracle on a stratified sample of the workload's pairs."""
+    from oracle import oracle as O
+    from paper_1911_10630_amd import synth as S
+    rng = np.random.default_rng(seed)
+    self_idx = np.nonzero(pi == pj)[0]
+    ns_idx = np.nonzero(pi != pj)[0]
+    n_self = max(1, int(round(n_sample * len(self_idx) / len(pi))))
+    pick = np.concatenate([rng.choice(self_idx, n_self, replace=False),
+                           rng.choice(ns_idx, n_sample - n_self, replace=False)])
+    orbs = sorted(set(pi[pick].tolist()) | set(pj[pick].tolist()))
+    phis = dict(zip(orbs, S.orbitals_np(wl, orbs)))
+    t0 = time.perf_counter()
+    res = O.solve_pairs(wl.n_grid, wl.cell, wl.r_pe, wl.r_me, wl.orbitals.centers, phis, pi[pick], pj[pick],
+                        tol=wl.cg_rtol, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return dict(value=len(pick) / dt, unit="pair Poisson solves/s", cores=int(res["threads"]),
+                kind="oracle",
+                sample=f"{len(pick)} of {len(pi)} pairs ({n_self} self), FP64, {dt:.1f} s wall, "
+                       f"mean {float(np.mean(res['iters'])):.0f} CG iterations"), pick, res
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32_refine"])
+    ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 2 per thread)")
+    ap.add_argument("--cpu-threads", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--max-pairs", type=int, default=0, help="(profiling) keep only the first pairs' orbitals")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
+              "not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1911_10630_amd import exx as X
+    from paper_1911_10630_amd import synth as S
+
+    wl = S.WORKLOADS[args.workload]()
+    if args.precision:
+        wl.precision = args.precision
+    dev = torch.device("cuda:0")
+    log(f"[bench] workload {wl.name}: generating {wl.orbitals.n} orbitals on {dev}")
+    phi = S.orbitals_torch(wl, device=dev)
+    ctx = X.Exx.from_workload(wl, block_threads=args.block)
+    n_pairs = ctx.pairs(wl.orbitals.centers)
+    info = ctx.pair_info(results=False)
+    dxx = torch.empty_like(phi)
+    stream = torch.cuda.current_stream(dev)
+    log(f"[bench] {n_pairs} pairs; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        ctx.solve(phi, stream)
+        E = ctx.energy_potential(dxx, stream)
+        log(f"[bench] warmup step done, E_xx = {E:.12f}")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        ctx.solve(phi, stream)
+        E = ctx.energy_potential(dxx, stream)
+        log(f"[bench] step {k + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = ctx.stats()
+    ms_per_step = 1e3 * dt / args.steps
+    value = n_pairs * args.steps / dt
+
+    # dominant kernel: persistent CG (one launch per step when one wave holds every pair)
+    cg_ms = st["cg_ms"] if st["cg_ms"] > 0 else st["solve_ms"]
+    achieved = st["cg_bytes"] / (cg_ms * 1e-3) / 1e9
+    traffic = None
+    if os.path.exists(PROFILE_TRAFFIC):
+        tr = json.load(open(PROFILE_TRAFFIC))
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name:
+            traffic = tr.get("bytes_per_launch")
+    roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                    frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
+
+    line = dict(metric="pair Poisson solves/s", value=round(value, 2), unit="pair Poisson solves/s",
+                n_gpus=1, steps=args.steps, warmup=args.warmup, ms_per_step=round(ms_per_step, 2),
+                higher_is_better=True, scaling="weak", vs_baseline=None,
+                dtype="f64" if wl.precision == "fp64" else "f32+f64",
+                data="synthetic",
+                config=dict(workload=wl.name, n_orbitals=wl.orbitals.n, n_pairs=n_pairs,
+                            grid=list(wl.n_grid), r_pair_bohr=round(wl.r_pair, 4),
+                            r_pe_bohr=[round(v, 4) for v in wl.r_pe], r_me_bohr=[round(v, 4) for v in wl.r_me],
+                            n_pe=st["n_pe"], n_me=st["n_me"], cg_rtol=wl.cg_rtol, precision=wl.precision,
+                            parallelism="1 GPU, persistent work-group per pair"),
+                roofline=roofline,
+                detail=dict(E_xx=E, iters_mean=st["iters_total"] / n_pairs, iters_min=st["iters_min"],
+                            iters_max=st["iters_max"], relres_max=st["relres_max"],
+                            solve_ms=round(st["solve_ms"], 2), prep_ms=round(st["prep_ms"], 2),
+                            cg_ms=round(st["cg_ms"], 2), dxx_ms=round(st["dxx_ms"], 2),
+                            energy_ms=round(st["energy_ms"], 3), cg_bytes=st["cg_bytes"],
+                            dxx_gbs=round(st["dxx_bytes"] / (st["dxx_ms"] * 1e-3) / 1e9, 1) if st["dxx_ms"] > 0 else None,
+                            grid=st["solve_grid"], block=st["solve_block"], waves=st["n_waves"],
+                            kernel_hash=kernel_hash()))
+
+    if not args.no_cpu_baseline:
+        threads = args.cpu_threads or min(16, os.cpu_count() or 1)
+        n_sample = args.cpu_sample or 2 * threads
+        n_sample = min(n_sample, n_pairs)
+        log(f"[bench] CPU oracle baseline: {n_sample} pairs on {threads} threads")
+        cb, pick, res = cpu_baseline(wl, info["i"], info["j"], n_sample, threads)
+        line["cpu_baseline"] = cb
+        pinfo = ctx.pair_info()
+        rel = np.abs(pinfo["e"][pick] - res["e"]) / np.abs(res["e"])
+        line["detail"]["sample_pair_energy_max_rel_vs_oracle"] = float(rel.max())
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()
