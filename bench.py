@@ -68,6 +68,7 @@ def main():
     ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c4", "c5"])
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32_refine"])
     ap.add_argument("--block", type=int, default=0)
+    ap.add_argument("--cols", type=int, default=0, help="CG columns per thread (-1: flat kernel)")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 2 per thread)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -89,7 +90,7 @@ def main():
     dev = torch.device("cuda:0")
     log(f"[bench] workload {wl.name}: generating {wl.orbitals.n} orbitals on {dev}")
     phi = S.orbitals_torch(wl, device=dev)
-    ctx = X.Exx.from_workload(wl, block_threads=args.block)
+    ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols)
     n_pairs = ctx.pairs(wl.orbitals.centers)
     info = ctx.pair_info(results=False)
     dxx = torch.empty_like(phi)
@@ -140,6 +141,7 @@ def main():
                             energy_ms=round(st["energy_ms"], 3), cg_bytes=st["cg_bytes"],
                             dxx_gbs=round(st["dxx_bytes"] / (st["dxx_ms"] * 1e-3) / 1e9, 1) if st["dxx_ms"] > 0 else None,
                             grid=st["solve_grid"], block=st["solve_block"], waves=st["n_waves"],
+                            cg_cols=st["cg_cols"], cg_bands=st["cg_bands"], outer_total=st["outer_total"],
                             kernel_hash=kernel_hash()))
 
     if not args.no_cpu_baseline:

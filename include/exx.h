@@ -68,7 +68,9 @@ typedef struct {
     int32_t orbital_dtype;  /* EXX_F64 | EXX_F32 (phi storage; D uses the same) */
     int32_t guess;          /* EXX_GUESS_*: initial CG guess                    */
     double  inner_rtol;     /* FP32_REFINE: relative tolerance of each FP32 solve */
-    int32_t block_threads;  /* work-group size of the solve kernel; 0 = tuned   */
+    int32_t block_threads;  /* CG work-group size; 0 = default choice           */
+    int32_t cg_cols;        /* CG columns per thread (z-march); 0 = default;
+                               -1 = the flat kernel (any sphere size)           */
     int64_t wave_pairs;     /* max pairs per launch wave; 0 = as many as fit    */
     int32_t keep_intermediates; /* 1: keep rho, b per pair for exx_debug_pair   */
 } exx_params;
@@ -87,6 +89,9 @@ typedef struct {
     double  energy_ms;       /* last exx_energy_potential: E reduction          */
     int32_t solve_grid;      /* persistent work-groups launched                 */
     int32_t solve_block;     /* threads per work-group                          */
+    int32_t cg_cols;         /* columns per thread (0: flat kernel)             */
+    int32_t cg_bands[2];     /* y bands per class                               */
+    int64_t outer_total;     /* FP32_REFINE: FP64 residual passes               */
     int64_t n_pe[2], n_me[2];/* subdomain sizes per class                       */
     int64_t cg_bytes;        /* algorithmic CG bytes of the last solve          */
     int64_t solve_bytes;     /* algorithmic bytes of the whole solve kernel     */

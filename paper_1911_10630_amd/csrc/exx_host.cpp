@@ -33,8 +33,9 @@ struct HostClass {
     int mxlo = 0, mxhi = -1, mylo = 0, myhi = -1, mzlo = 0, mzhi = -1;
     std::vector<int4> pe_rows, me_rows;
     std::vector<int> pe_xyz, sh_xyz, cols;
+    std::vector<int> bands;      // [n][8] for the selected CG variant
     int4 *d_pe_rows = nullptr, *d_me_rows = nullptr;
-    int *d_pe_xyz = nullptr, *d_sh_xyz = nullptr, *d_cols = nullptr;
+    int *d_pe_xyz = nullptr, *d_sh_xyz = nullptr, *d_cols = nullptr, *d_bands = nullptr;
 };
 
 template <typename T>
@@ -69,10 +70,12 @@ struct exx_ctx {
     DevBuf<long long> d_off;
     DevBuf<int> d_orb_ptr, d_orb_pairs;
     DevBuf<double> d_vout, d_q, d_e, d_relres, d_scratch, d_E, d_rhs, d_rho_keep;
-    DevBuf<int> d_iters, d_conv, d_counter;
+    DevBuf<int> d_iters, d_outer, d_conv, d_counter;
     DevBuf<float> d_scratch32;
 
     int block = 256, grid = 0, slots = 0, wave_n = 0, n_waves = 0;
+    CgVariant var{0, 256, 0, 0};
+    size_t lds_bytes = 0;
     long long slot_n = 0;
     const void *phi = nullptr;
     hipEvent_t ev[6] = {};
@@ -290,15 +293,58 @@ ClassDev class_dev(const HostClass &k)
     d.mnx = k.mxhi - k.mxlo + 1; d.mny = k.myhi - k.mylo + 1; d.mnz = k.mzhi - k.mzlo + 1;
     d.n_pe = k.n_pe;
     d.n_sh = k.n_sh;
+    d.bands = k.d_bands;
+    d.n_bands = (int)k.bands.size() / 8;
+    d.lds_w = d.pnx + 6;
+    d.lds_plane = (d.pny + 6) * (d.pnx + 6);
     return d;
+}
+
+// Splits the PE projection columns of one class into y bands of whole rows,
+// each with at most v.cols * v.block columns and at most v.halo * v.block
+// columns in its 3-row halos.  Returns false if the variant cannot hold it.
+bool make_bands(const HostClass &k, const CgVariant &v, std::vector<int> &out)
+{
+    out.clear();
+    const int ny = k.pyhi - k.pylo + 1;
+    std::vector<int> start(ny + 1, 0);
+    for (int c : k.cols) {
+        int x, y, z;
+        unpack_xyz(c, x, y, z);
+        start[y - k.pylo + 1]++;
+    }
+    for (int y = 0; y < ny; ++y) start[y + 1] += start[y];
+    const int ncols = start[ny];
+    const long cap = (long)v.cols * v.block;
+    const int nb = (int)((ncols + cap - 1) / cap);
+    const int target = (ncols + nb - 1) / nb;
+    int y0 = 0;
+    while (y0 < ny) {
+        int y1 = y0;
+        while (y1 < ny && (start[y1 + 1] - start[y0]) <= cap && (y1 == y0 || start[y1] - start[y0] < target)) ++y1;
+        if (y1 == y0) return false;                  // a single row exceeds the capacity
+        const int lo0 = std::max(0, y0 - 3), hi1 = std::min(ny, y1 + 3);
+        const int nh = (start[y0] - start[lo0]) + (start[hi1] - start[y1]);
+        if (nh > (long)v.halo * v.block) return false;
+        int zlo = 1 << 30, zhi = -(1 << 30);
+        for (int z = k.pzlo; z <= k.pzhi; ++z)
+            for (int y = y0; y < y1; ++y) {
+                const int4 r = k.pe_rows[(size_t)(z - k.pzlo) * ny + y];
+                if (r.y <= r.z) { zlo = std::min(zlo, z); zhi = std::max(zhi, z); }
+            }
+        out.insert(out.end(), {start[y0], start[y1], start[lo0], start[y0], start[y1], start[hi1], zlo, zhi});
+        y0 = y1;
+    }
+    return true;
 }
 
 void free_class(HostClass &k)
 {
-    for (void *p : {(void *)k.d_pe_rows, (void *)k.d_me_rows, (void *)k.d_pe_xyz, (void *)k.d_sh_xyz, (void *)k.d_cols})
+    for (void *p : {(void *)k.d_pe_rows, (void *)k.d_me_rows, (void *)k.d_pe_xyz, (void *)k.d_sh_xyz,
+                    (void *)k.d_cols, (void *)k.d_bands})
         if (p) (void)hipFree(p);
     k.d_pe_rows = k.d_me_rows = nullptr;
-    k.d_pe_xyz = k.d_sh_xyz = k.d_cols = nullptr;
+    k.d_pe_xyz = k.d_sh_xyz = k.d_cols = k.d_bands = nullptr;
 }
 
 double fact(int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
@@ -312,6 +358,52 @@ void ylm_norms(double *out)
             if (am) v *= 2.0;
             out[l * l + l + m] = std::sqrt(v);
         }
+}
+
+constexpr size_t kMaxLds = 160 * 1024 - 1024;   // gfx950 LDS per work-group, less static use
+
+// Chooses the CG kernel: the requested (block, cols) z-march variant, or by
+// default the z-march variant with the fewest bands (then the smallest
+// block) whose LDS planes fit; the flat kernel when none fits.
+exx_status select_variant(exx_ctx *c)
+{
+    CgVariant vs[32];
+    const int nv = cg_variants(vs, 32);
+    const size_t plane = (size_t)std::max((c->cls[0].pyhi - c->cls[0].pylo + 7) * (c->cls[0].pxhi - c->cls[0].pxlo + 7),
+                                          (c->cls[1].pyhi - c->cls[1].pylo + 7) * (c->cls[1].pxhi - c->cls[1].pxlo + 7));
+    const size_t lds = 2 * plane * sizeof(double);
+    int best = -1, best_bands = 1 << 30;
+    std::vector<int> b0, b1;
+    for (int i = 0; i < nv; ++i) {
+        const CgVariant &v = vs[i];
+        if (c->prm.cg_cols < 0) { if (!v.zmarch) { best = i; break; } continue; }
+        if (!v.zmarch) continue;
+        if (c->prm.block_threads && v.block != c->prm.block_threads) continue;
+        if (c->prm.cg_cols && v.cols != c->prm.cg_cols) continue;
+        if (lds > kMaxLds) continue;
+        if (!make_bands(c->cls[0], v, b0) || !make_bands(c->cls[1], v, b1)) continue;
+        const int nb = (int)(b0.size() + b1.size()) / 8;
+        if (nb < best_bands) { best = i; best_bands = nb; }
+    }
+    if (best < 0) {
+        if (c->prm.block_threads || c->prm.cg_cols)
+            return fail(c, EXX_EINVAL, "no CG kernel variant with block %d and %d columns fits this subdomain",
+                        c->prm.block_threads, c->prm.cg_cols);
+        for (int i = 0; i < nv; ++i) if (!vs[i].zmarch) best = i;
+    }
+    c->var = vs[best];
+    c->lds_bytes = c->var.zmarch ? lds : 0;
+    for (auto &k : c->cls) {
+        if (k.d_bands) { (void)hipFree(k.d_bands); k.d_bands = nullptr; }
+        k.bands.clear();
+        if (c->var.zmarch) {
+            make_bands(k, c->var, k.bands);
+            HIPCHK(c, hipMalloc((void **)&k.d_bands, k.bands.size() * sizeof(int)));
+            HIPCHK(c, hipMemcpy(k.d_bands, k.bands.data(), k.bands.size() * sizeof(int), hipMemcpyHostToDevice));
+        }
+    }
+    c->block = c->var.block;
+    return EXX_OK;
 }
 
 }  // namespace
@@ -391,11 +483,10 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         exx_status st = build_class(c, c->cls[k], p->r_pe[k], p->r_me[k]);
         if (st != EXX_OK) return bail(st);
     }
-    c->block = p->block_threads ? p->block_threads : 256;
-    int bs[8];
-    int nb = solve_block_sizes(bs, 8);
-    if (std::find(bs, bs + nb, c->block) == bs + nb)
-        return bail(fail(c, EXX_EINVAL, "block_threads %d not available", c->block));
+    {
+        exx_status st = select_variant(c);
+        if (st != EXX_OK) return bail(st);
+    }
     for (auto &e : c->ev)
         if (hipEventCreate(&e) != hipSuccess) return bail(fail(c, EXX_EDEVICE, "hipEventCreate failed"));
     c->have_events = true;
@@ -471,18 +562,24 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     if ((st = dev_reserve(c, c->d_e, np)) != EXX_OK) return st;
     if ((st = dev_reserve(c, c->d_relres, np)) != EXX_OK) return st;
     if ((st = dev_reserve(c, c->d_iters, np)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_outer, np)) != EXX_OK) return st;
     if ((st = dev_reserve(c, c->d_conv, np)) != EXX_OK) return st;
     if ((st = dev_reserve(c, c->d_counter, 1)) != EXX_OK) return st;
     if ((st = dev_reserve(c, c->d_E, 1)) != EXX_OK) return st;
     // persistent grid and per-slot scratch
     int per_cu = 0;
-    HIPCHK(c, solve_occupancy(c->block, &per_cu));
+    HIPCHK(c, cg_occupancy(c->var, c->lds_bytes, &per_cu));
     per_cu = std::max(per_cu, 1);
     c->grid = (int)std::min<int64_t>(c->n_pairs, (int64_t)per_cu * c->n_cu);
     c->grid = std::max(c->grid, 1);
     c->slots = c->grid;
     c->slot_n = ((long long)std::max(c->cls[0].n_pe, c->cls[1].n_pe) + 63) / 64 * 64;
-    if ((st = dev_reserve(c, c->d_scratch, (size_t)c->slots * 3 * c->slot_n)) != EXX_OK) return st;
+    if (c->prm.precision == EXX_FP32_REFINE) {
+        if (!c->var.zmarch) return fail(c, EXX_EINVAL, "FP32 refinement needs a z-march CG kernel");
+        if ((st = dev_reserve(c, c->d_scratch32, (size_t)c->slots * 4 * c->slot_n)) != EXX_OK) return st;
+    } else {
+        if ((st = dev_reserve(c, c->d_scratch, (size_t)c->slots * 3 * c->slot_n)) != EXX_OK) return st;
+    }
     // right-hand sides of one wave of pairs; the wave is as large as the
     // device allows (one launch of each kernel when everything fits)
     {
@@ -528,12 +625,14 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
     a.ngrid = (long long)a.nx * a.ny * a.nz;
     a.vout = c->d_vout.p;
     a.scratch = c->d_scratch.p;
+    a.scratch32 = c->d_scratch32.p;
     a.rhs = c->d_rhs.p;
     a.rho_keep = c->prm.keep_intermediates ? c->d_rho_keep.p : nullptr;
     a.slot_n = c->slot_n;
     a.q_out = c->d_q.p;
     a.e_out = c->d_e.p;
     a.iters_out = c->d_iters.p;
+    a.outer_out = c->d_outer.p;
     a.conv_out = c->d_conv.p;
     a.relres_out = c->d_relres.p;
     a.counter = c->d_counter.p;
@@ -554,7 +653,7 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
         HIPCHK(c, launch_prep(a, s));
         HIPCHK(c, launch_zero_int(c->d_counter.p, 1, s));
         if (w0 == 0) HIPCHK(c, hipEventRecord(c->ev[5], s));
-        HIPCHK(c, launch_solve(a, std::min(c->grid, a.wave_n), c->block, s));
+        HIPCHK(c, launch_cg(c->var, a, std::min(c->grid, a.wave_n), c->lds_bytes, s));
         ++c->n_waves;
     }
     HIPCHK(c, hipEventRecord(c->ev[1], s));
@@ -610,6 +709,9 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     st->n_self = c->n_self;
     st->solve_grid = c->grid;
     st->solve_block = c->block;
+    st->cg_cols = c->var.zmarch ? c->var.cols : 0;
+    st->cg_bands[0] = (int)c->cls[0].bands.size() / 8;
+    st->cg_bands[1] = (int)c->cls[1].bands.size() / 8;
     for (int k = 0; k < 2; ++k) {
         st->n_pe[k] = c->cls[k].n_pe;
         st->n_me[k] = c->cls[k].n_pe + c->cls[k].n_sh;
@@ -619,21 +721,27 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     if (c->state < 3) return EXX_OK;
     HIPCHK(c, hipSetDevice(c->device));
     const size_t np = (size_t)c->n_pairs;
-    std::vector<int> it(np), cv(np);
+    std::vector<int> it(np), cv(np), ou(np);
     std::vector<double> rr(np);
     HIPCHK(c, hipMemcpy(it.data(), c->d_iters.p, np * sizeof(int), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(ou.data(), c->d_outer.p, np * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(cv.data(), c->d_conv.p, np * sizeof(int), hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(rr.data(), c->d_relres.p, np * sizeof(double), hipMemcpyDeviceToHost));
     st->iters_min = np ? it[0] : 0;
     const int sphi = c->prm.orbital_dtype == EXX_F32 ? 4 : 8;
+    const int scg = c->prm.precision == EXX_FP32_REFINE ? 4 : 8;
     for (size_t p = 0; p < np; ++p) {
         const HostClass &k = c->cls[c->gc[p].w];
         st->iters_total += it[p];
+        st->outer_total += ou[p];
         st->iters_min = std::min(st->iters_min, it[p]);
         st->iters_max = std::max(st->iters_max, it[p]);
         st->n_not_converged += cv[p] ? 0 : 1;
         st->relres_max = std::max(st->relres_max, rr[p]);
-        const int64_t cg = (int64_t)it[p] * 8 * 8 * k.n_pe;
+        // algorithmic bytes per unknown: 8 vector passes per CG iteration,
+        // 32 B per FP64 residual pass (x, b, d in; x, r out) and 32 B for the
+        // closing pass (x, b and the two orbitals in)
+        const int64_t cg = (int64_t)k.n_pe * ((int64_t)it[p] * 8 * scg + (int64_t)ou[p] * 32 + 32);
         st->cg_bytes += cg;
         st->solve_bytes += cg + (int64_t)2 * k.n_pe * sphi + (int64_t)k.n_sh * 8;
         const int m = c->ij[p].x == c->ij[p].y ? 1 : 2;
@@ -707,7 +815,7 @@ void exx_destroy(exx_ctx *c)
     dev_free(c->d_ij); dev_free(c->d_gc); dev_free(c->d_off); dev_free(c->d_orb_ptr); dev_free(c->d_orb_pairs);
     dev_free(c->d_vout); dev_free(c->d_q); dev_free(c->d_e); dev_free(c->d_relres); dev_free(c->d_scratch);
     dev_free(c->d_rhs); dev_free(c->d_rho_keep);
-    dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
+    dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_outer); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
     if (c->have_events)
         for (auto &e : c->ev)
             if (e) (void)hipEventDestroy(e);

@@ -38,6 +38,10 @@ struct ClassDev {
     const int *sh_xyz;     // [n_sh] packed offsets
     const int *cols;       // [n_cols] packed (x, y, 0) of the PE projection, sorted (y, x)
     int n_cols;
+    const int *bands;      // [n_bands][8] z-march bands: own cols [c0,c1), halo cols
+                           // [h0,h1) u [h2,h3), planes [zlo, zhi]
+    int n_bands;
+    int lds_w, lds_plane;  // z-march LDS plane: row pitch pnx + 6, (pny + 6) rows
     int pxlo, pylo, pzlo, pnx, pny, pnz;   // PE bounding box
     int mxlo, mylo, mzlo, mnx, mny, mnz;   // ME bounding box
     int n_pe, n_sh;
@@ -60,7 +64,8 @@ struct SolveArgs {
     float *scratch32;           // per CG slot: FP32 work vectors (refinement)
     double *q_out;              // [n_pairs][NLM]
     double *e_out;              // [n_pairs]
-    int *iters_out;             // [n_pairs]
+    int *iters_out;             // [n_pairs] CG iterations (FP32 refinement: inner total)
+    int *outer_out;             // [n_pairs] FP64 residual passes (refinement)
     int *conv_out;              // [n_pairs]
     double *relres_out;         // [n_pairs]
     int *counter;               // dynamic pair queue (wave-relative)
@@ -93,11 +98,19 @@ struct DxxArgs {
 
 // Launchers (exx_kernels.hip).
 hipError_t launch_prep(const SolveArgs &a, hipStream_t s);
-hipError_t launch_solve(const SolveArgs &a, int grid, int block, hipStream_t s);
+// Persistent CG kernels: "flat" (any sphere) and "zmarch" (register queue,
+// needs the LDS plane to fit).  Variants are (block, columns per thread).
+struct CgVariant {
+    int zmarch;   // 0 flat, 1 z-march
+    int block;    // threads per work-group
+    int cols;     // columns per thread per band (z-march)
+    int halo;     // halo columns per thread (z-march)
+};
+int cg_variants(CgVariant *out, int max_n);
+hipError_t cg_occupancy(const CgVariant &v, size_t lds_bytes, int *blocks_per_cu);
+hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_dxx(const DxxArgs &a, int n_orb, hipStream_t s);
 hipError_t launch_energy(const double *e, const int2 *ij, int n_pairs, double *out, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
-int solve_block_sizes(int *out, int max_n);
-hipError_t solve_occupancy(int block, int *blocks_per_cu);
 
 }  // namespace exx

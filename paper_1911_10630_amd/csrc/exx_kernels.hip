@@ -323,6 +323,7 @@ __device__ void cg_one_pair(const SolveArgs &a, int pair, long long slot, double
     if (tid == 0) {
         a.e_out[pair] = e * (a.h[0] * a.h[1] * a.h[2]);
         a.iters_out[pair] = k;
+        a.outer_out[pair] = 0;
         a.conv_out[pair] = conv;
         a.relres_out[pair] = bb > 0.0 ? sqrt(res / bb) : 0.0;
     }
@@ -346,6 +347,489 @@ __global__ __launch_bounds__(BLOCK) void k_solve(SolveArgs a)
         }
         if (k >= a.wave_n) break;
         cg_one_pair<BLOCK>(a, a.wave_begin + k, blockIdx.x, red);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// z-marching CG: one work-group per pair, register queue along z
+// ---------------------------------------------------------------------------
+//
+// Each thread owns xy columns of the PE sphere (up to K per band) and marches
+// through the planes z.  For every owned column it keeps the seven planes
+// z-3..z+3 of the stencil operand in registers; the current plane is written
+// to an LDS plane (zero-padded by 3 on every side) so the x and y neighbours
+// come from LDS.  Every vector element is therefore read from memory once
+// per pass.  Columns are split into y bands when they do not fit K per
+// thread; a band also loads the current plane of its 3 halo rows on each
+// side.  Loads of the next plane are issued before the LDS barrier, which
+// waits on LDS traffic only, so they overlap the stencil arithmetic.
+//
+// A CG iteration is two passes:
+//   direction  u = r + beta p_old (p_old and p_new in two buffers, so a later
+//              band's halo still sees p_old), store p_new, accumulate p.Ap;
+//   update     u = p, x += alpha p at load time, r -= alpha Ap at output
+//              time, accumulate r.r.
+// The final pass recomputes b - A x and the pair energy with the density
+// re-gathered from the orbitals.
+
+__device__ __forceinline__ void lds_barrier()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+    __builtin_amdgcn_s_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
+// Packed index of PE element (x, pylo + ry, z), or -1 when outside PE.
+__device__ __forceinline__ int zaddr(const ClassDev &g, int z, int ry, int x)
+{
+    const int zz = z - g.pzlo;
+    if ((unsigned)zz >= (unsigned)g.pnz) return -1;
+    const int4 r = g.pe_rows[zz * g.pny + ry];
+    return (x >= r.y && x <= r.z) ? r.x + x - r.y : -1;
+}
+
+template <typename R>
+struct StencilW {
+    R c, x[4], y[4], z[4];
+};
+
+template <typename R>
+__device__ __forceinline__ StencilW<R> stencil_w(const SolveArgs &a)
+{
+    StencilW<R> w;
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+        w.x[s] = (R)(a.wfd[s] / (a.h[0] * a.h[0]));
+        w.y[s] = (R)(a.wfd[s] / (a.h[1] * a.h[1]));
+        w.z[s] = (R)(a.wfd[s] / (a.h[2] * a.h[2]));
+    }
+    w.c = (R)(a.wfd[0] / (a.h[0] * a.h[0]) + a.wfd[0] / (a.h[1] * a.h[1]) + a.wfd[0] / (a.h[2] * a.h[2]));
+    return w;
+}
+
+template <typename R, int T, int K, int KH, class P>
+__device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, R *lds, int &par, P &pol,
+                                            const StencilW<R> &w, const int4 &pg, int nx, int ny, int nz)
+{
+    const int tid = threadIdx.x;
+    const int *bd = g.bands + 8 * bi;
+    const int c0 = bd[0], c1 = bd[1], h0 = bd[2], h1 = bd[3], h2 = bd[4], h3 = bd[5], zlo = bd[6], zhi = bd[7];
+    const int W = g.lds_w;
+    int cx[K], cry[K], clo[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const int c = c0 + k * T + tid;
+        int x = g.pxlo, y = g.pylo, z;
+        if (c < c1) unpack_xyz(g.cols[c], x, y, z);
+        cx[k] = x;
+        cry[k] = y - g.pylo;
+        clo[k] = c < c1 ? (y - g.pylo + 3) * W + (x - g.pxlo + 3) : -1;
+    }
+    const int nh0 = h1 - h0, nh = nh0 + (h3 - h2);
+    int hx[KH], hry[KH], hlo[KH];
+#pragma unroll
+    for (int j = 0; j < KH; ++j) {
+        const int t = j * T + tid;
+        int x = g.pxlo, y = g.pylo, z;
+        if (t < nh) unpack_xyz(g.cols[t < nh0 ? h0 + t : h2 + (t - nh0)], x, y, z);
+        hx[j] = x;
+        hry[j] = y - g.pylo;
+        hlo[j] = t < nh ? (y - g.pylo + 3) * W + (x - g.pxlo + 3) : -1;
+    }
+    auto fetch_own = [&](int zl) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) pol.fetch_own(k, (clo[k] >= 0 && zl <= zhi) ? zaddr(g, zl, cry[k], cx[k]) : -1);
+    };
+    auto fetch_halo = [&](int z) {
+#pragma unroll
+        for (int j = 0; j < KH; ++j) pol.fetch_halo(j, (hlo[j] >= 0 && z <= zhi) ? zaddr(g, z, hry[j], hx[j]) : -1);
+    };
+    auto fetch_out = [&](int z) {
+        const int gz = wrap_n(pg.z + z, nz);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const int ad = (clo[k] >= 0 && z <= zhi) ? zaddr(g, z, cry[k], cx[k]) : -1;
+            pol.fetch_out(k, ad, wrap_n(pg.x + cx[k], nx), wrap_n(pg.y + g.pylo + cry[k], ny), gz);
+        }
+    };
+
+    R q[K][7];
+#pragma unroll
+    for (int k = 0; k < K; ++k)
+#pragma unroll
+        for (int j = 0; j < 7; ++j) q[k][j] = (R)0;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        fetch_own(zlo + j);
+#pragma unroll
+        for (int k = 0; k < K; ++k) q[k][4 + j] = pol.fin_own(k);
+    }
+    fetch_own(zlo + 3);
+    fetch_halo(zlo);
+    fetch_out(zlo);
+    for (int zo = zlo; zo <= zhi; ++zo) {
+        R un[K], uh[KH];
+#pragma unroll
+        for (int k = 0; k < K; ++k) un[k] = pol.fin_own(k);
+#pragma unroll
+        for (int j = 0; j < KH; ++j) uh[j] = pol.fin_halo(j);
+        fetch_own(zo + 4);
+        fetch_halo(zo + 1);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+#pragma unroll
+            for (int j = 0; j < 6; ++j) q[k][j] = q[k][j + 1];
+            q[k][6] = un[k];
+        }
+        R *buf = lds + (par & 1) * g.lds_plane;
+        ++par;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            if (clo[k] >= 0) buf[clo[k]] = q[k][3];
+#pragma unroll
+        for (int j = 0; j < KH; ++j)
+            if (hlo[j] >= 0) buf[hlo[j]] = uh[j];
+        lds_barrier();
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            if (clo[k] < 0) continue;
+            const R *c = buf + clo[k];
+            R s = w.c * q[k][3];
+            s += w.z[1] * (q[k][2] + q[k][4]) + w.z[2] * (q[k][1] + q[k][5]) + w.z[3] * (q[k][0] + q[k][6]);
+            s += w.x[1] * (c[-1] + c[1]) + w.x[2] * (c[-2] + c[2]) + w.x[3] * (c[-3] + c[3]);
+            s += w.y[1] * (c[-W] + c[W]) + w.y[2] * (c[-2 * W] + c[2 * W]) + w.y[3] * (c[-3 * W] + c[3 * W]);
+            pol.output(k, q[k][3], -s);
+        }
+        fetch_out(zo + 1);
+    }
+}
+
+template <typename R, int T, int K, int KH, class P>
+__device__ __forceinline__ void zmarch(const ClassDev &g, R *lds, int &par, P &pol, const StencilW<R> &w,
+                                       const int4 &pg, int nx, int ny, int nz)
+{
+    for (int bi = 0; bi < g.n_bands; ++bi) zmarch_band<R, T, K, KH>(g, bi, lds, par, pol, w, pg, nx, ny, nz);
+}
+
+// direction pass: u = r + beta p_old, p_new <- u; sum p.Ap (and b.b when r is b)
+template <typename R, int K, int KH>
+struct PDir {
+    const R *rsrc, *pold;
+    R *pnew;
+    R beta;
+    bool load_p, acc_bb;
+    double pap = 0.0, bb = 0.0;
+    R fr[K], fp[K];
+    int fa[K];
+    R hr[KH], hp[KH];
+    __device__ __forceinline__ void fetch_own(int k, int a)
+    {
+        fa[k] = a;
+        fr[k] = a >= 0 ? rsrc[a] : (R)0;
+        fp[k] = (a >= 0 && load_p) ? pold[a] : (R)0;
+    }
+    __device__ __forceinline__ R fin_own(int k)
+    {
+        const R u = fr[k] + beta * fp[k];
+        if (fa[k] >= 0) {
+            pnew[fa[k]] = u;
+            if (acc_bb) bb += (double)fr[k] * (double)fr[k];
+        }
+        return u;
+    }
+    __device__ __forceinline__ void fetch_halo(int j, int a)
+    {
+        hr[j] = a >= 0 ? rsrc[a] : (R)0;
+        hp[j] = (a >= 0 && load_p) ? pold[a] : (R)0;
+    }
+    __device__ __forceinline__ R fin_halo(int j) { return hr[j] + beta * hp[j]; }
+    __device__ __forceinline__ void fetch_out(int, int, int, int, int) {}
+    __device__ __forceinline__ void output(int, R u, R Au) { pap += (double)u * (double)Au; }
+};
+
+// update pass: u = p, x += alpha p (load time), r = rsrc - alpha Ap (output time); sum r.r
+template <typename R, int K, int KH>
+struct PUpd {
+    const R *p, *rsrc;
+    R *x, *r;
+    R alpha;
+    bool load_x;
+    double rr = 0.0;
+    R fp[K], fx[K];
+    int fa[K];
+    R hp[KH];
+    R orr[K];
+    int oa[K];
+    __device__ __forceinline__ void fetch_own(int k, int a)
+    {
+        fa[k] = a;
+        fp[k] = a >= 0 ? p[a] : (R)0;
+        fx[k] = (a >= 0 && load_x) ? x[a] : (R)0;
+    }
+    __device__ __forceinline__ R fin_own(int k)
+    {
+        if (fa[k] >= 0) x[fa[k]] = fx[k] + alpha * fp[k];
+        return fp[k];
+    }
+    __device__ __forceinline__ void fetch_halo(int j, int a) { hp[j] = a >= 0 ? p[a] : (R)0; }
+    __device__ __forceinline__ R fin_halo(int j) { return hp[j]; }
+    __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
+    {
+        oa[k] = a;
+        orr[k] = a >= 0 ? rsrc[a] : (R)0;
+    }
+    __device__ __forceinline__ void output(int k, R, R Au)
+    {
+        if (oa[k] >= 0) {
+            const R t = orr[k] - alpha * Au;
+            r[oa[k]] = t;
+            rr += (double)t * (double)t;
+        }
+    }
+};
+
+// FP64 residual pass: u = x (+ d), r = b - A u; sums r.r and b.b; the
+// residual is stored in RT (double, or float for refinement).  x is not
+// written here (a later band's halo still needs the old x); the caller adds
+// d to x afterwards.
+template <int K, int KH, typename DT, typename RT>
+struct PRes {
+    const double *x;
+    const DT *d;
+    const double *b;
+    RT *r;
+    bool add_d;
+    double rr = 0.0, bb = 0.0;
+    double fx[K];
+    double hx[KH];
+    double ob[K];
+    int oa[K];
+    __device__ __forceinline__ void fetch_own(int k, int a)
+    {
+        double v = a >= 0 ? x[a] : 0.0;
+        if (a >= 0 && add_d) v += (double)d[a];
+        fx[k] = v;
+    }
+    __device__ __forceinline__ double fin_own(int k) { return fx[k]; }
+    __device__ __forceinline__ void fetch_halo(int j, int a)
+    {
+        double v = a >= 0 ? x[a] : 0.0;
+        if (a >= 0 && add_d) v += (double)d[a];
+        hx[j] = v;
+    }
+    __device__ __forceinline__ double fin_halo(int j) { return hx[j]; }
+    __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
+    {
+        oa[k] = a;
+        ob[k] = a >= 0 ? b[a] : 0.0;
+    }
+    __device__ __forceinline__ void output(int k, double, double Au)
+    {
+        if (oa[k] >= 0) {
+            const double t = ob[k] - Au;
+            r[oa[k]] = (RT)t;
+            rr += t * t;
+            bb += ob[k] * ob[k];
+        }
+    }
+};
+
+// final pass: true residual b - A x and energy sum rho x with rho re-gathered
+template <int K, int KH>
+struct PFin {
+    const double *x, *b;
+    const void *phi;
+    long long oi, oj;
+    int f32, nx, ny;
+    double e = 0.0, res = 0.0;
+    double fx[K];
+    double hx[KH];
+    double ob[K], orho[K];
+    int oa[K];
+    __device__ __forceinline__ void fetch_own(int k, int a) { fx[k] = a >= 0 ? x[a] : 0.0; }
+    __device__ __forceinline__ double fin_own(int k) { return fx[k]; }
+    __device__ __forceinline__ void fetch_halo(int j, int a) { hx[j] = a >= 0 ? x[a] : 0.0; }
+    __device__ __forceinline__ double fin_halo(int j) { return hx[j]; }
+    __device__ __forceinline__ void fetch_out(int k, int a, int gx, int gy, int gz)
+    {
+        oa[k] = a;
+        ob[k] = 0.0;
+        orho[k] = 0.0;
+        if (a >= 0) {
+            const long long gi = ((long long)gz * ny + gy) * nx + gx;
+            ob[k] = b[a];
+            orho[k] = load_phi(phi, f32, oi + gi) * load_phi(phi, f32, oj + gi);
+        }
+    }
+    __device__ __forceinline__ void output(int k, double u, double Au)
+    {
+        if (oa[k] >= 0) {
+            const double t = ob[k] - Au;
+            res += t * t;
+            e += orho[k] * u;
+        }
+    }
+};
+
+// One pair: FP64 CG, or FP32 CG with FP64 iterative refinement.
+template <int T, int K, int KH>
+__device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, long long slot, double *lds, double *red, int &par)
+{
+    const int tid = threadIdx.x;
+    const int4 pg = a.pair_gc[pair];
+    const int2 ij = a.pair_ij[pair];
+    const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
+    double *x = a.vout + a.out_off[pair];
+    const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
+    const StencilW<double> w64 = stencil_w<double>(a);
+    const bool guess = a.guess != 0;
+    int it = 0, conv = 0, outer = 0;
+    double bb = 0.0;
+
+    if (a.precision == 0) {
+        double *r = a.scratch + slot * 3 * a.slot_n;
+        double *pold = r + a.slot_n, *pnew = pold + a.slot_n;
+        const double *rsrc = b;
+        double rr = 0.0, pap = 0.0;
+        if (guess) {
+            PRes<K, KH, double, double> pr{x, nullptr, b, r, false};
+            zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
+            ++outer;
+            rr = block_sum<T>(pr.rr, red);
+            bb = block_sum<T>(pr.bb, red);
+            rsrc = r;
+        }
+        {
+            PDir<double, K, KH> pd{rsrc, pold, pnew, 0.0, false, !guess};
+            zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
+            pap = block_sum<T>(pd.pap, red);
+            if (!guess) rr = bb = block_sum<T>(pd.bb, red);
+        }
+        const double stop = a.tol * a.tol * bb;
+        if (bb == 0.0) {
+            for (int q = tid; q < g.n_pe; q += T) x[q] = 0.0;
+            conv = 1;
+        } else if (rr <= stop) {
+            conv = 1;
+        } else {
+            for (;;) {
+                const double alpha = rr / pap;
+                PUpd<double, K, KH> pu{pnew, rsrc, x, r, alpha, guess || it > 0};
+                zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
+                const double rn = block_sum<T>(pu.rr, red);
+                ++it;
+                const double beta = rn / rr;
+                rr = rn;
+                rsrc = r;
+                if (rr <= stop) { conv = 1; break; }
+                if (it >= a.maxit) break;
+                double *t = pold; pold = pnew; pnew = t;
+                PDir<double, K, KH> pd{r, pold, pnew, beta, true, false};
+                zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
+                pap = block_sum<T>(pd.pap, red);
+            }
+        }
+    } else {
+        // FP32 inner CG on A d = r32 (zero guess), FP64 residual and x.
+        float *r32 = a.scratch32 + slot * 4 * a.slot_n;
+        float *d32 = r32 + a.slot_n;
+        float *pold = d32 + a.slot_n, *pnew = pold + a.slot_n;
+        const StencilW<float> w32 = stencil_w<float>(a);
+        float *lds32 = reinterpret_cast<float *>(lds);
+        bool have_d = false;
+        if (!guess) {
+            for (int q = tid; q < g.n_pe; q += T) x[q] = 0.0;
+            __syncthreads();
+        }
+        for (;;) {
+            PRes<K, KH, float, float> pr{x, d32, b, r32, have_d};
+            zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
+            ++outer;
+            const double rr0 = block_sum<T>(pr.rr, red);
+            if (!have_d) bb = block_sum<T>(pr.bb, red);
+            if (have_d) {
+                for (int q = tid; q < g.n_pe; q += T) x[q] += (double)d32[q];
+                __syncthreads();
+            }
+            if (bb == 0.0 || rr0 <= a.tol * a.tol * bb) {
+                if (bb == 0.0) {
+                    for (int q = tid; q < g.n_pe; q += T) x[q] = 0.0;
+                    __syncthreads();
+                }
+                conv = 1;
+                break;
+            }
+            if (it >= a.maxit) break;
+            // inner solve to inner_tol relative
+            const double istop = a.inner_tol * a.inner_tol * rr0;
+            double rr = rr0, pap;
+            {
+                PDir<float, K, KH> pd{r32, pold, pnew, 0.0f, false, false};
+                zmarch<float, T, K, KH>(g, lds32, par, pd, w32, pg, a.nx, a.ny, a.nz);
+                pap = block_sum<T>(pd.pap, red);
+            }
+            int inner = 0;
+            for (;;) {
+                const float alpha = (float)(rr / pap);
+                PUpd<float, K, KH> pu{pnew, r32, d32, r32, alpha, inner > 0};
+                zmarch<float, T, K, KH>(g, lds32, par, pu, w32, pg, a.nx, a.ny, a.nz);
+                const double rn = block_sum<T>(pu.rr, red);
+                ++inner;
+                ++it;
+                const float beta = (float)(rn / rr);
+                rr = rn;
+                if (rr <= istop || it >= a.maxit) break;
+                float *t = pold; pold = pnew; pnew = t;
+                PDir<float, K, KH> pd{r32, pold, pnew, beta, true, false};
+                zmarch<float, T, K, KH>(g, lds32, par, pd, w32, pg, a.nx, a.ny, a.nz);
+                pap = block_sum<T>(pd.pap, red);
+            }
+            have_d = true;
+        }
+    }
+
+    PFin<K, KH> pf{x, b, a.phi, (long long)ij.x * a.ngrid, (long long)ij.y * a.ngrid, a.phi_f32, a.nx, a.ny};
+    zmarch<double, T, K, KH>(g, lds, par, pf, w64, pg, a.nx, a.ny, a.nz);
+    const double e = block_sum<T>(pf.e, red);
+    const double res = block_sum<T>(pf.res, red);
+    if (tid == 0) {
+        a.e_out[pair] = e * (a.h[0] * a.h[1] * a.h[2]);
+        a.iters_out[pair] = it;
+        a.outer_out[pair] = outer;
+        a.conv_out[pair] = conv;
+        a.relres_out[pair] = bb > 0.0 ? sqrt(res / bb) : 0.0;
+    }
+    __syncthreads();
+}
+
+template <int T, int K, int KH>
+__global__ __launch_bounds__(T) void k_cg_zmarch(SolveArgs a)
+{
+    extern __shared__ double lds_dyn[];
+    __shared__ double red[T / 64];
+    __shared__ int s_pair;
+    // zero both plane buffers once: the 3-wide frame and the points outside
+    // the PE projection are never written afterwards
+    const ClassDev g0 = a.cls[0], g1 = a.cls[1];
+    const int nplane = 2 * (g0.lds_plane > g1.lds_plane ? g0.lds_plane : g1.lds_plane);
+    for (int t = threadIdx.x; t < nplane; t += T) lds_dyn[t] = 0.0;
+    __syncthreads();
+    int par = 0;
+    int last_cls = -1;
+    for (;;) {
+        if (threadIdx.x == 0) s_pair = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int k = s_pair;
+        __syncthreads();
+        if (k >= a.wave_n) break;
+        const int cls = a.pair_gc[a.wave_begin + k].w;
+        if (last_cls >= 0 && cls != last_cls) {
+            // a different class has a different plane pitch: clear again
+            for (int t = threadIdx.x; t < nplane; t += T) lds_dyn[t] = 0.0;
+            __syncthreads();
+        }
+        last_cls = cls;
+        cg_zmarch_pair<T, K, KH>(a, a.wave_begin + k, blockIdx.x, lds_dyn, red, par);
     }
 }
 
@@ -440,38 +924,63 @@ __global__ void k_zero_int(int *p, int n)
 // launchers
 // ---------------------------------------------------------------------------
 
-static const int kBlocks[] = {256, 512};
+#define EXX_ZM_VARIANTS(X) X(256, 4, 2) X(256, 8, 2) X(512, 4, 1) X(512, 6, 1)
 
-int solve_block_sizes(int *out, int max_n)
+static const CgVariant kVariants[] = {
+    {0, 256, 0, 0},
+#define EXX_V(T, K, KH) {1, T, K, KH},
+    EXX_ZM_VARIANTS(EXX_V)
+#undef EXX_V
+};
+
+int cg_variants(CgVariant *out, int max_n)
 {
     int n = 0;
-    for (int b : kBlocks)
-        if (n < max_n) out[n++] = b;
+    for (const CgVariant &v : kVariants)
+        if (n < max_n) out[n++] = v;
     return n;
 }
 
-hipError_t solve_occupancy(int block, int *blocks_per_cu)
+template <int T, int K, int KH>
+static hipError_t zm_prepare(size_t lds)
 {
-    switch (block) {
-    case 256: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_solve<256>, 256, 0);
-    case 512: return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_solve<512>, 512, 0);
-    default: return hipErrorInvalidValue;
+    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cg_zmarch<T, K, KH>),
+                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+
+hipError_t cg_occupancy(const CgVariant &v, size_t lds, int *blocks_per_cu)
+{
+    if (!v.zmarch) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_solve<256>, 256, 0);
+#define EXX_V(T, K, KH)                                                                                     \
+    if (v.block == T && v.cols == K && v.halo == KH) {                                                       \
+        hipError_t e = zm_prepare<T, K, KH>(lds);                                                            \
+        if (e != hipSuccess) return e;                                                                       \
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_cg_zmarch<T, K, KH>, T, lds);   \
     }
+    EXX_ZM_VARIANTS(EXX_V)
+#undef EXX_V
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t lds, hipStream_t s)
+{
+    if (!v.zmarch) {
+        hipLaunchKernelGGL(k_solve<256>, dim3(grid), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+#define EXX_V(T, K, KH)                                                                   \
+    if (v.block == T && v.cols == K && v.halo == KH) {                                     \
+        hipLaunchKernelGGL((k_cg_zmarch<T, K, KH>), dim3(grid), dim3(T), lds, s, a);        \
+        return hipGetLastError();                                                          \
+    }
+    EXX_ZM_VARIANTS(EXX_V)
+#undef EXX_V
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_prep(const SolveArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_prep, dim3(a.wave_n), dim3(PREP_BLOCK), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_solve(const SolveArgs &a, int grid, int block, hipStream_t s)
-{
-    switch (block) {
-    case 256: hipLaunchKernelGGL(k_solve<256>, dim3(grid), dim3(256), 0, s, a); break;
-    case 512: hipLaunchKernelGGL(k_solve<512>, dim3(grid), dim3(512), 0, s, a); break;
-    default: return hipErrorInvalidValue;
-    }
     return hipGetLastError();
 }
 

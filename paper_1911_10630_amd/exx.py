@@ -32,7 +32,8 @@ class ExxParams(C.Structure):
                 ("r_pe", C.c_double * 2), ("r_me", C.c_double * 2), ("fd_half_width", C.c_int32),
                 ("l_max", C.c_int32), ("cg_rtol", C.c_double), ("cg_max_iter", C.c_int32),
                 ("precision", C.c_int32), ("orbital_dtype", C.c_int32), ("guess", C.c_int32),
-                ("inner_rtol", C.c_double), ("block_threads", C.c_int32), ("wave_pairs", C.c_int64),
+                ("inner_rtol", C.c_double), ("block_threads", C.c_int32), ("cg_cols", C.c_int32),
+                ("wave_pairs", C.c_int64),
                 ("keep_intermediates", C.c_int32)]
 
 
@@ -41,7 +42,8 @@ class ExxStats(C.Structure):
                 ("iters_min", C.c_int32), ("iters_max", C.c_int32), ("n_not_converged", C.c_int64),
                 ("relres_max", C.c_double), ("solve_ms", C.c_double), ("prep_ms", C.c_double),
                 ("cg_ms", C.c_double), ("dxx_ms", C.c_double), ("energy_ms", C.c_double),
-                ("solve_grid", C.c_int32), ("solve_block", C.c_int32), ("n_pe", C.c_int64 * 2),
+                ("solve_grid", C.c_int32), ("solve_block", C.c_int32), ("cg_cols", C.c_int32),
+                ("cg_bands", C.c_int32 * 2), ("outer_total", C.c_int64), ("n_pe", C.c_int64 * 2),
                 ("n_me", C.c_int64 * 2), ("cg_bytes", C.c_int64), ("solve_bytes", C.c_int64),
                 ("dxx_bytes", C.c_int64), ("device_bytes", C.c_int64), ("n_waves", C.c_int32)]
 
@@ -105,7 +107,7 @@ class Exx:
 
     def __init__(self, n_grid, cell, r_pair, r_pe, r_me, *, cg_rtol=1e-10, cg_max_iter=20000,
                  precision="fp64", orbital_dtype="f64", guess="zero", inner_rtol=1e-5, block_threads=0,
-                 wave_pairs=0, keep_intermediates=False, device=0):
+                 cg_cols=0, wave_pairs=0, keep_intermediates=False, device=0):
         L = load()
         p = ExxParams()
         L.exx_default_params(C.byref(p))
@@ -124,6 +126,7 @@ class Exx:
         p.guess = GUESS[guess]
         p.inner_rtol = float(inner_rtol)
         p.block_threads = int(block_threads)
+        p.cg_cols = int(cg_cols)
         p.wave_pairs = int(wave_pairs)
         p.keep_intermediates = 1 if keep_intermediates else 0
         self.params = p

@@ -147,3 +147,50 @@ def test_c1_waves_match_single_launch(c1, c1_gpu):
     E2, D2 = ctx.step(phit)
     assert ctx.stats()["n_waves"] == 9
     assert E2 == Eg and np.array_equal(D2.cpu().numpy(), Dg)
+
+
+@pytest.mark.parametrize("block,cols", [(256, -1), (256, 4), (256, 8), (512, 4), (512, 6)])
+def test_c1_cg_kernel_variants(c1, block, cols):
+    """Every CG kernel variant (flat, and z-march tilings with 1-2 bands)."""
+    wl, phi, E, D, out = c1
+    _say(f"[gpu] variant block={block} cols={cols}")
+    ctx = X.Exx.from_workload(wl, block_threads=block, cg_cols=cols)
+    ctx.pairs(wl.orbitals.centers)
+    Eg, Dg = ctx.step(torch.from_numpy(phi).cuda())
+    st = ctx.stats()
+    assert st["cg_cols"] == max(cols, 0)
+    info = ctx.pair_info()
+    assert np.all(info["converged"] == 1) and np.all(info["relres"] <= 1e-9)
+    assert abs(Eg - E) <= 1e-8 * abs(E), (Eg, E)
+    assert gamma(D, Dg.cpu().numpy()).max() <= 1e-7
+    assert np.all(np.abs(info["iters"] - out["iters"]) <= 2)
+
+
+def test_c1_fp32_refinement(c1):
+    """FP32 inner CG with FP64 refinement reaches the FP64 residual target."""
+    wl, phi, E, D, out = c1
+    _say("[gpu] fp32 refinement")
+    ctx = X.Exx.from_workload(wl, precision="fp32_refine", inner_rtol=1e-4)
+    ctx.pairs(wl.orbitals.centers)
+    Eg, Dg = ctx.step(torch.from_numpy(phi).cuda())
+    info = ctx.pair_info()
+    st = ctx.stats()
+    assert np.all(info["converged"] == 1)
+    assert info["relres"].max() <= 1e-10
+    assert st["outer_total"] >= 3 * len(info["e"])          # at least three FP64 residual passes per pair
+    assert abs(Eg - E) <= 1e-8 * abs(E), (Eg, E)
+    assert gamma(D, Dg.cpu().numpy()).max() <= 1e-7
+
+
+def test_c1_fp32_orbitals(c1):
+    """Orbitals and D stored in FP32; arithmetic FP64.  The oracle sees the same
+    FP32-rounded orbitals; D differs by its final rounding to FP32."""
+    wl, phi, *_ = c1
+    phi32 = phi.astype(np.float32)
+    E, D, _ = O.exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, wl.orbitals.centers, phi32.astype(np.float64))
+    ctx = X.Exx.from_workload(wl, orbital_dtype="f32")
+    ctx.pairs(wl.orbitals.centers)
+    Eg, Dg = ctx.step(torch.from_numpy(phi32).cuda())
+    assert Dg.dtype == torch.float32
+    assert abs(Eg - E) <= 1e-8 * abs(E)
+    assert gamma(D, Dg.cpu().numpy().astype(np.float64)).max() <= 1e-6
