@@ -33,9 +33,12 @@ struct HostClass {
     int mxlo = 0, mxhi = -1, mylo = 0, myhi = -1, mzlo = 0, mzhi = -1;
     std::vector<int4> pe_rows, me_rows;
     std::vector<int> pe_xyz, sh_xyz, cols;
-    std::vector<int> bands;      // [n][8] for the selected CG variant
+    std::vector<int> colz, pe_off;
+    std::vector<int> bands;      // [n][12] for the selected CG variant
+    int plane_rows = 0;
     int4 *d_pe_rows = nullptr, *d_me_rows = nullptr;
     int *d_pe_xyz = nullptr, *d_sh_xyz = nullptr, *d_cols = nullptr, *d_bands = nullptr;
+    int *d_colz = nullptr, *d_pe_off = nullptr;
 };
 
 template <typename T>
@@ -74,7 +77,7 @@ struct exx_ctx {
     DevBuf<float> d_scratch32;
 
     int block = 256, grid = 0, slots = 0, wave_n = 0, n_waves = 0;
-    CgVariant var{0, 256, 0, 0};
+    CgVariant var{0, 256, 0, 0, 0};
     size_t lds_bytes = 0;
     long long slot_n = 0;
     const void *phi = nullptr;
@@ -251,6 +254,7 @@ exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
     k.n_sh = sbase;
     // Projection columns of PE onto the xy plane, sorted (y, x)
     k.cols.clear();
+    k.colz.clear();
     for (int y = k.pylo; y <= k.pyhi; ++y) {
         int xl = 1 << 30, xh = -(1 << 30);
         for (int z = k.pzlo; z <= k.pzhi; ++z) {
@@ -259,8 +263,25 @@ exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
             xl = std::min(xl, r->plo);
             xh = std::max(xh, r->phi);
         }
-        for (int x = xl; x <= xh; ++x) k.cols.push_back(pack_xyz(x, y, 0));
+        for (int x = xl; x <= xh; ++x) {
+            k.cols.push_back(pack_xyz(x, y, 0));
+            int zl = 1 << 30, zh = -(1 << 30);
+            for (int z = k.pzlo; z <= k.pzhi; ++z) {
+                const Run *r = run_at(y, z);
+                if (r && r->plo <= x && x <= r->phi) { zl = std::min(zl, z); zh = std::max(zh, z); }
+            }
+            // the z extent of a column of a convex set is one interval
+            for (int z = zl; z <= zh; ++z) {
+                const Run *r = run_at(y, z);
+                if (!r || r->plo > x || x > r->phi)
+                    return fail(c, EXX_EINVAL, "PE column (%d, %d) is not one z interval", x, y);
+            }
+            k.colz.push_back((zl + 512) | ((zh + 512) << 16));
+        }
     }
+    k.pe_off.assign((size_t)pny * pnz, 0);
+    for (size_t t = 0; t < k.pe_rows.size(); ++t)
+        if (k.pe_rows[t].y <= k.pe_rows[t].z) k.pe_off[t] = k.pe_rows[t].x - k.pe_rows[t].y;
     // upload
     auto up = [&](auto **dst, const auto &v) -> exx_status {
         using T = std::remove_reference_t<decltype(v[0])>;
@@ -275,6 +296,8 @@ exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
     if ((st = up(&k.d_pe_xyz, k.pe_xyz)) != EXX_OK) return st;
     if ((st = up(&k.d_sh_xyz, k.sh_xyz)) != EXX_OK) return st;
     if ((st = up(&k.d_cols, k.cols)) != EXX_OK) return st;
+    if ((st = up(&k.d_colz, k.colz)) != EXX_OK) return st;
+    if ((st = up(&k.d_pe_off, k.pe_off)) != EXX_OK) return st;
     return EXX_OK;
 }
 
@@ -293,19 +316,24 @@ ClassDev class_dev(const HostClass &k)
     d.mnx = k.mxhi - k.mxlo + 1; d.mny = k.myhi - k.mylo + 1; d.mnz = k.mzhi - k.mzlo + 1;
     d.n_pe = k.n_pe;
     d.n_sh = k.n_sh;
+    d.colz = k.d_colz;
+    d.pe_off = k.d_pe_off;
     d.bands = k.d_bands;
-    d.n_bands = (int)k.bands.size() / 8;
+    d.n_bands = (int)k.bands.size() / 12;
+    d.tbl_ints = (d.pny * d.pnz + 3) / 4 * 4;
     d.lds_w = d.pnx + 6;
-    d.lds_plane = (d.pny + 6) * (d.pnx + 6);
+    d.plane_rows = k.plane_rows;
+    d.lds_plane = k.plane_rows * (d.pnx + 6);
     return d;
 }
 
 // Splits the PE projection columns of one class into y bands of whole rows,
 // each with at most v.cols * v.block columns and at most v.halo * v.block
 // columns in its 3-row halos.  Returns false if the variant cannot hold it.
-bool make_bands(const HostClass &k, const CgVariant &v, std::vector<int> &out)
+bool make_bands(const HostClass &k, const CgVariant &v, std::vector<int> &out, int *plane_rows)
 {
     out.clear();
+    *plane_rows = 0;
     const int ny = k.pyhi - k.pylo + 1;
     std::vector<int> start(ny + 1, 0);
     for (int c : k.cols) {
@@ -332,7 +360,9 @@ bool make_bands(const HostClass &k, const CgVariant &v, std::vector<int> &out)
                 const int4 r = k.pe_rows[(size_t)(z - k.pzlo) * ny + y];
                 if (r.y <= r.z) { zlo = std::min(zlo, z); zhi = std::max(zhi, z); }
             }
-        out.insert(out.end(), {start[y0], start[y1], start[lo0], start[y0], start[y1], start[hi1], zlo, zhi});
+        out.insert(out.end(), {start[y0], start[y1], start[lo0], start[y0], start[y1], start[hi1], zlo, zhi,
+                               k.pylo + y0, k.pylo + y1 - 1, 0, 0});
+        *plane_rows = std::max(*plane_rows, y1 - y0 + 6);
         y0 = y1;
     }
     return true;
@@ -341,10 +371,10 @@ bool make_bands(const HostClass &k, const CgVariant &v, std::vector<int> &out)
 void free_class(HostClass &k)
 {
     for (void *p : {(void *)k.d_pe_rows, (void *)k.d_me_rows, (void *)k.d_pe_xyz, (void *)k.d_sh_xyz,
-                    (void *)k.d_cols, (void *)k.d_bands})
+                    (void *)k.d_cols, (void *)k.d_bands, (void *)k.d_colz, (void *)k.d_pe_off})
         if (p) (void)hipFree(p);
     k.d_pe_rows = k.d_me_rows = nullptr;
-    k.d_pe_xyz = k.d_sh_xyz = k.d_cols = k.d_bands = nullptr;
+    k.d_pe_xyz = k.d_sh_xyz = k.d_cols = k.d_bands = k.d_colz = k.d_pe_off = nullptr;
 }
 
 double fact(int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
@@ -362,17 +392,23 @@ void ylm_norms(double *out)
 
 constexpr size_t kMaxLds = 160 * 1024 - 1024;   // gfx950 LDS per work-group, less static use
 
-// Chooses the CG kernel: the requested (block, cols) z-march variant, or by
-// default the z-march variant with the fewest bands (then the smallest
-// block) whose LDS planes fit; the flat kernel when none fits.
+// LDS of the z-march kernel for one class: row-offset table + two planes.
+size_t zmarch_lds(const HostClass &k, int plane_rows)
+{
+    const size_t pny = k.pyhi - k.pylo + 1, pnz = k.pzhi - k.pzlo + 1, pnx = k.pxhi - k.pxlo + 1;
+    return (pny * pnz + 3) / 4 * 4 * sizeof(int) + (2 * (size_t)plane_rows * (pnx + 6) + 2) * sizeof(double);
+}
+
+// Chooses the CG kernel: among the z-march variants that fit (and match the
+// requested block / cols), the one with the most resident waves per CU,
+// then the fewest bands; the flat kernel when none fits.
 exx_status select_variant(exx_ctx *c)
 {
     CgVariant vs[32];
     const int nv = cg_variants(vs, 32);
-    const size_t plane = (size_t)std::max((c->cls[0].pyhi - c->cls[0].pylo + 7) * (c->cls[0].pxhi - c->cls[0].pxlo + 7),
-                                          (c->cls[1].pyhi - c->cls[1].pylo + 7) * (c->cls[1].pxhi - c->cls[1].pxlo + 7));
-    const size_t lds = 2 * plane * sizeof(double);
-    int best = -1, best_bands = 1 << 30;
+    int best = -1;
+    long best_score = -1;
+    size_t best_lds = 0;
     std::vector<int> b0, b1;
     for (int i = 0; i < nv; ++i) {
         const CgVariant &v = vs[i];
@@ -380,10 +416,15 @@ exx_status select_variant(exx_ctx *c)
         if (!v.zmarch) continue;
         if (c->prm.block_threads && v.block != c->prm.block_threads) continue;
         if (c->prm.cg_cols && v.cols != c->prm.cg_cols) continue;
+        int r0 = 0, r1 = 0;
+        if (!make_bands(c->cls[0], v, b0, &r0) || !make_bands(c->cls[1], v, b1, &r1)) continue;
+        const size_t lds = std::max(zmarch_lds(c->cls[0], r0), zmarch_lds(c->cls[1], r1));
         if (lds > kMaxLds) continue;
-        if (!make_bands(c->cls[0], v, b0) || !make_bands(c->cls[1], v, b1)) continue;
-        const int nb = (int)(b0.size() + b1.size()) / 8;
-        if (nb < best_bands) { best = i; best_bands = nb; }
+        int per_cu = 0;
+        if (cg_occupancy(v, c->prm.precision, lds, &per_cu) != hipSuccess || per_cu < 1) continue;
+        const int nb = (int)(b0.size() + b1.size()) / 12;
+        const long score = (long)per_cu * v.block / 64 * 1000 - nb;
+        if (score > best_score) { best = i; best_score = score; best_lds = lds; }
     }
     if (best < 0) {
         if (c->prm.block_threads || c->prm.cg_cols)
@@ -392,12 +433,13 @@ exx_status select_variant(exx_ctx *c)
         for (int i = 0; i < nv; ++i) if (!vs[i].zmarch) best = i;
     }
     c->var = vs[best];
-    c->lds_bytes = c->var.zmarch ? lds : 0;
+    c->lds_bytes = c->var.zmarch ? best_lds : 0;
     for (auto &k : c->cls) {
         if (k.d_bands) { (void)hipFree(k.d_bands); k.d_bands = nullptr; }
         k.bands.clear();
+        k.plane_rows = 0;
         if (c->var.zmarch) {
-            make_bands(k, c->var, k.bands);
+            make_bands(k, c->var, k.bands, &k.plane_rows);
             HIPCHK(c, hipMalloc((void **)&k.d_bands, k.bands.size() * sizeof(int)));
             HIPCHK(c, hipMemcpy(k.d_bands, k.bands.data(), k.bands.size() * sizeof(int), hipMemcpyHostToDevice));
         }
@@ -568,12 +610,14 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     if ((st = dev_reserve(c, c->d_E, 1)) != EXX_OK) return st;
     // persistent grid and per-slot scratch
     int per_cu = 0;
-    HIPCHK(c, cg_occupancy(c->var, c->lds_bytes, &per_cu));
+    HIPCHK(c, cg_occupancy(c->var, c->prm.precision, c->lds_bytes, &per_cu));
     per_cu = std::max(per_cu, 1);
     c->grid = (int)std::min<int64_t>(c->n_pairs, (int64_t)per_cu * c->n_cu);
     c->grid = std::max(c->grid, 1);
     c->slots = c->grid;
-    c->slot_n = ((long long)std::max(c->cls[0].n_pe, c->cls[1].n_pe) + 63) / 64 * 64;
+    // one spare element past the largest PE vector: the z-march kernels store
+    // the values of unused lanes there
+    c->slot_n = ((long long)std::max(c->cls[0].n_pe, c->cls[1].n_pe) + 1 + 63) / 64 * 64;
     if (c->prm.precision == EXX_FP32_REFINE) {
         if (!c->var.zmarch) return fail(c, EXX_EINVAL, "FP32 refinement needs a z-march CG kernel");
         if ((st = dev_reserve(c, c->d_scratch32, (size_t)c->slots * 4 * c->slot_n)) != EXX_OK) return st;
@@ -710,8 +754,8 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     st->solve_grid = c->grid;
     st->solve_block = c->block;
     st->cg_cols = c->var.zmarch ? c->var.cols : 0;
-    st->cg_bands[0] = (int)c->cls[0].bands.size() / 8;
-    st->cg_bands[1] = (int)c->cls[1].bands.size() / 8;
+    st->cg_bands[0] = (int)c->cls[0].bands.size() / 12;
+    st->cg_bands[1] = (int)c->cls[1].bands.size() / 12;
     for (int k = 0; k < 2; ++k) {
         st->n_pe[k] = c->cls[k].n_pe;
         st->n_me[k] = c->cls[k].n_pe + c->cls[k].n_sh;

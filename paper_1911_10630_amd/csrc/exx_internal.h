@@ -38,10 +38,14 @@ struct ClassDev {
     const int *sh_xyz;     // [n_sh] packed offsets
     const int *cols;       // [n_cols] packed (x, y, 0) of the PE projection, sorted (y, x)
     int n_cols;
-    const int *bands;      // [n_bands][8] z-march bands: own cols [c0,c1), halo cols
-                           // [h0,h1) u [h2,h3), planes [zlo, zhi]
+    const int *colz;       // [n_cols] z range of each column: (zlo + 512) | (zhi + 512) << 16
+    const int *pe_off;     // [pnz][pny] base(z, y) - xlo(z, y): packed index of (x, y, z) = pe_off + x
+    const int *bands;      // [n_bands][12] z-march bands: own cols [c0,c1), halo cols
+                           // [h0,h1) u [h2,h3), planes [zlo, zhi], first own row ya
     int n_bands;
-    int lds_w, lds_plane;  // z-march LDS plane: row pitch pnx + 6, (pny + 6) rows
+    int tbl_ints;          // LDS ints holding pe_off (pnz * pny rounded up to 4)
+    int lds_w, lds_plane;  // z-march LDS plane: row pitch pnx + 6, plane_rows * lds_w
+    int plane_rows;        // own rows of the widest band + 6
     int pxlo, pylo, pzlo, pnx, pny, pnz;   // PE bounding box
     int mxlo, mylo, mzlo, mnx, mny, mnz;   // ME bounding box
     int n_pe, n_sh;
@@ -105,9 +109,10 @@ struct CgVariant {
     int block;    // threads per work-group
     int cols;     // columns per thread per band (z-march)
     int halo;     // halo columns per thread (z-march)
+    int wpe;      // minimum resident waves per SIMD the kernel is compiled for
 };
 int cg_variants(CgVariant *out, int max_n);
-hipError_t cg_occupancy(const CgVariant &v, size_t lds_bytes, int *blocks_per_cu);
+hipError_t cg_occupancy(const CgVariant &v, int mixed, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_dxx(const DxxArgs &a, int n_orb, hipStream_t s);
 hipError_t launch_energy(const double *e, const int2 *ij, int n_pairs, double *out, hipStream_t s);

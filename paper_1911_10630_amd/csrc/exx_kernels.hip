@@ -407,50 +407,101 @@ __device__ __forceinline__ StencilW<R> stencil_w(const SolveArgs &a)
     return w;
 }
 
+// The march is written without divergent branches: invalid columns load from
+// index 0 and select zero, store through a pointer redirected to a sink, and
+// write their LDS value to a sink slot.  Divergent branches around loads make
+// the compiler wait for every outstanding load (the next plane's prefetch
+// included) at each join.
+// Load from a (or from index 0 when a < 0: always valid memory); the caller
+// discards the value of invalid lanes when it consumes it, one plane later,
+// so the load stays in flight until then.
+template <typename T>
+__device__ __forceinline__ T raw_load(const T *p, int a)
+{
+    return p[a >= 0 ? a : 0];
+}
+
+template <typename T>
+__device__ __forceinline__ T *sel_ptr(T *p, int a, T *sink)
+{
+    return a >= 0 ? p + a : sink;
+}
+
 template <typename R, int T, int K, int KH, class P>
-__device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, R *lds, int &par, P &pol,
+__device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, double *lds, int &par, P &pol,
                                             const StencilW<R> &w, const int4 &pg, int nx, int ny, int nz)
 {
     const int tid = threadIdx.x;
-    const int *bd = g.bands + 8 * bi;
+    const int *bd = g.bands + 12 * bi;
     const int c0 = bd[0], c1 = bd[1], h0 = bd[2], h1 = bd[3], h2 = bd[4], h3 = bd[5], zlo = bd[6], zhi = bd[7];
+    const int ya = bd[8];
     const int W = g.lds_w;
-    int cx[K], cry[K], clo[K];
+    const int *tbl = reinterpret_cast<const int *>(lds);
+    R *planes = reinterpret_cast<R *>(lds + g.tbl_ints / 2);
+    R *lsink = planes + 2 * g.lds_plane;
+    // the plane buffers are band-relative: clear them (positions outside this
+    // band's projection must read as zero)
+    __syncthreads();
+    for (int t = tid; t < 2 * g.lds_plane + 2; t += T) lds[g.tbl_ints / 2 + t] = 0.0;
+    __syncthreads();
+
+    // own columns: x, table row, LDS offset, z range (empty range when unused)
+    int cxr[K], clo[K], czr[K];
+    bool cok[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) {
         const int c = c0 + k * T + tid;
-        int x = g.pxlo, y = g.pylo, z;
-        if (c < c1) unpack_xyz(g.cols[c], x, y, z);
-        cx[k] = x;
-        cry[k] = y - g.pylo;
-        clo[k] = c < c1 ? (y - g.pylo + 3) * W + (x - g.pxlo + 3) : -1;
+        cok[k] = c < c1;
+        int x = g.pxlo, y = ya, z;
+        unpack_xyz(g.cols[cok[k] ? c : c0], x, y, z);
+        czr[k] = cok[k] ? g.colz[cok[k] ? c : c0] : 1023;
+        cxr[k] = (x + 512) | ((y - g.pylo) << 16);
+        clo[k] = (y - ya + 3) * W + (x - g.pxlo + 3);
     }
     const int nh0 = h1 - h0, nh = nh0 + (h3 - h2);
-    int hx[KH], hry[KH], hlo[KH];
+    int hxr[KH], hlo[KH], hzr[KH];
+    bool hok[KH];
 #pragma unroll
     for (int j = 0; j < KH; ++j) {
         const int t = j * T + tid;
-        int x = g.pxlo, y = g.pylo, z;
-        if (t < nh) unpack_xyz(g.cols[t < nh0 ? h0 + t : h2 + (t - nh0)], x, y, z);
-        hx[j] = x;
-        hry[j] = y - g.pylo;
-        hlo[j] = t < nh ? (y - g.pylo + 3) * W + (x - g.pxlo + 3) : -1;
+        hok[j] = t < nh;
+        const int c = hok[j] ? (t < nh0 ? h0 + t : h2 + (t - nh0)) : c0;
+        int x, y, z;
+        unpack_xyz(g.cols[c], x, y, z);
+        hzr[j] = hok[j] ? g.colz[c] : 1023;
+        hxr[j] = (x + 512) | ((y - g.pylo) << 16);
+        hlo[j] = (y - ya + 3) * W + (x - g.pxlo + 3);
     }
+    // packed index of a column at plane z, or -1 (branch-free)
+    auto addr = [&](int z, int xr, int zr) -> int {
+        const int zl = (zr & 0xffff) - 512, zh = (zr >> 16) - 512;
+        const int zc = min(max(z, g.pzlo), g.pzlo + g.pnz - 1);
+        const int idx = tbl[(zc - g.pzlo) * g.pny + (xr >> 16)] + (xr & 0xffff) - 512;
+        return (unsigned)(z - zl) <= (unsigned)(zh - zl) ? idx : -1;
+    };
     auto fetch_own = [&](int zl) {
+        int ad[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) pol.fetch_own(k, (clo[k] >= 0 && zl <= zhi) ? zaddr(g, zl, cry[k], cx[k]) : -1);
+        for (int k = 0; k < K; ++k) ad[k] = addr(zl, cxr[k], czr[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k) pol.fetch_own(k, ad[k]);
     };
     auto fetch_halo = [&](int z) {
+        int ad[KH];
 #pragma unroll
-        for (int j = 0; j < KH; ++j) pol.fetch_halo(j, (hlo[j] >= 0 && z <= zhi) ? zaddr(g, z, hry[j], hx[j]) : -1);
+        for (int j = 0; j < KH; ++j) ad[j] = addr(z, hxr[j], hzr[j]);
+#pragma unroll
+        for (int j = 0; j < KH; ++j) pol.fetch_halo(j, ad[j]);
     };
     auto fetch_out = [&](int z) {
         const int gz = wrap_n(pg.z + z, nz);
+        int ad[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            const int ad = (clo[k] >= 0 && z <= zhi) ? zaddr(g, z, cry[k], cx[k]) : -1;
-            pol.fetch_out(k, ad, wrap_n(pg.x + cx[k], nx), wrap_n(pg.y + g.pylo + cry[k], ny), gz);
-        }
+        for (int k = 0; k < K; ++k) ad[k] = addr(z, cxr[k], czr[k]);
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            pol.fetch_out(k, ad[k], wrap_n(pg.x + (cxr[k] & 0xffff) - 512, nx),
+                          wrap_n(pg.y + g.pylo + (cxr[k] >> 16), ny), gz);
     };
 
     R q[K][7];
@@ -481,18 +532,15 @@ __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, R *lds, i
             for (int j = 0; j < 6; ++j) q[k][j] = q[k][j + 1];
             q[k][6] = un[k];
         }
-        R *buf = lds + (par & 1) * g.lds_plane;
+        R *buf = planes + (par & 1) * g.lds_plane;
         ++par;
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            if (clo[k] >= 0) buf[clo[k]] = q[k][3];
+        for (int k = 0; k < K; ++k) *(cok[k] ? buf + clo[k] : lsink) = q[k][3];
 #pragma unroll
-        for (int j = 0; j < KH; ++j)
-            if (hlo[j] >= 0) buf[hlo[j]] = uh[j];
+        for (int j = 0; j < KH; ++j) *(hok[j] ? buf + hlo[j] : lsink) = uh[j];
         lds_barrier();
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            if (clo[k] < 0) continue;
             const R *c = buf + clo[k];
             R s = w.c * q[k][3];
             s += w.z[1] * (q[k][2] + q[k][4]) + w.z[2] * (q[k][1] + q[k][5]) + w.z[3] * (q[k][0] + q[k][6]);
@@ -505,7 +553,7 @@ __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, R *lds, i
 }
 
 template <typename R, int T, int K, int KH, class P>
-__device__ __forceinline__ void zmarch(const ClassDev &g, R *lds, int &par, P &pol, const StencilW<R> &w,
+__device__ __forceinline__ void zmarch(const ClassDev &g, double *lds, int &par, P &pol, const StencilW<R> &w,
                                        const int4 &pg, int nx, int ny, int nz)
 {
     for (int bi = 0; bi < g.n_bands; ++bi) zmarch_band<R, T, K, KH>(g, bi, lds, par, pol, w, pg, nx, ny, nz);
@@ -515,34 +563,36 @@ __device__ __forceinline__ void zmarch(const ClassDev &g, R *lds, int &par, P &p
 template <typename R, int K, int KH>
 struct PDir {
     const R *rsrc, *pold;
-    R *pnew;
+    R *pnew, *sink;
     R beta;
     bool load_p, acc_bb;
     double pap = 0.0, bb = 0.0;
     R fr[K], fp[K];
     int fa[K];
     R hr[KH], hp[KH];
+    int ha[KH];
     __device__ __forceinline__ void fetch_own(int k, int a)
     {
         fa[k] = a;
-        fr[k] = a >= 0 ? rsrc[a] : (R)0;
-        fp[k] = (a >= 0 && load_p) ? pold[a] : (R)0;
+        fr[k] = raw_load(rsrc, a);
+        fp[k] = load_p ? raw_load(pold, a) : (R)0;
     }
     __device__ __forceinline__ R fin_own(int k)
     {
-        const R u = fr[k] + beta * fp[k];
-        if (fa[k] >= 0) {
-            pnew[fa[k]] = u;
-            if (acc_bb) bb += (double)fr[k] * (double)fr[k];
-        }
+        const bool ok = fa[k] >= 0;
+        const R r = ok ? fr[k] : (R)0;
+        const R u = ok ? fr[k] + beta * fp[k] : (R)0;
+        *sel_ptr(pnew, fa[k], sink) = u;
+        if (acc_bb) bb += (double)r * (double)r;
         return u;
     }
     __device__ __forceinline__ void fetch_halo(int j, int a)
     {
-        hr[j] = a >= 0 ? rsrc[a] : (R)0;
-        hp[j] = (a >= 0 && load_p) ? pold[a] : (R)0;
+        ha[j] = a;
+        hr[j] = raw_load(rsrc, a);
+        hp[j] = load_p ? raw_load(pold, a) : (R)0;
     }
-    __device__ __forceinline__ R fin_halo(int j) { return hr[j] + beta * hp[j]; }
+    __device__ __forceinline__ R fin_halo(int j) { return ha[j] >= 0 ? hr[j] + beta * hp[j] : (R)0; }
     __device__ __forceinline__ void fetch_out(int, int, int, int, int) {}
     __device__ __forceinline__ void output(int, R u, R Au) { pap += (double)u * (double)Au; }
 };
@@ -551,40 +601,44 @@ struct PDir {
 template <typename R, int K, int KH>
 struct PUpd {
     const R *p, *rsrc;
-    R *x, *r;
+    R *x, *r, *sink;
     R alpha;
     bool load_x;
     double rr = 0.0;
     R fp[K], fx[K];
     int fa[K];
     R hp[KH];
+    int ha[KH];
     R orr[K];
     int oa[K];
     __device__ __forceinline__ void fetch_own(int k, int a)
     {
         fa[k] = a;
-        fp[k] = a >= 0 ? p[a] : (R)0;
-        fx[k] = (a >= 0 && load_x) ? x[a] : (R)0;
+        fp[k] = raw_load(p, a);
+        fx[k] = load_x ? raw_load(x, a) : (R)0;
     }
     __device__ __forceinline__ R fin_own(int k)
     {
-        if (fa[k] >= 0) x[fa[k]] = fx[k] + alpha * fp[k];
-        return fp[k];
+        const R pv = fa[k] >= 0 ? fp[k] : (R)0;
+        *sel_ptr(x, fa[k], sink) = fx[k] + alpha * pv;
+        return pv;
     }
-    __device__ __forceinline__ void fetch_halo(int j, int a) { hp[j] = a >= 0 ? p[a] : (R)0; }
-    __device__ __forceinline__ R fin_halo(int j) { return hp[j]; }
+    __device__ __forceinline__ void fetch_halo(int j, int a)
+    {
+        ha[j] = a;
+        hp[j] = raw_load(p, a);
+    }
+    __device__ __forceinline__ R fin_halo(int j) { return ha[j] >= 0 ? hp[j] : (R)0; }
     __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
     {
         oa[k] = a;
-        orr[k] = a >= 0 ? rsrc[a] : (R)0;
+        orr[k] = raw_load(rsrc, a);
     }
     __device__ __forceinline__ void output(int k, R, R Au)
     {
-        if (oa[k] >= 0) {
-            const R t = orr[k] - alpha * Au;
-            r[oa[k]] = t;
-            rr += (double)t * (double)t;
-        }
+        const R t = oa[k] >= 0 ? orr[k] - alpha * Au : (R)0;
+        *sel_ptr(r, oa[k], sink) = t;
+        rr += (double)t * (double)t;
     }
 };
 
@@ -597,40 +651,44 @@ struct PRes {
     const double *x;
     const DT *d;
     const double *b;
-    RT *r;
+    RT *r, *sink;
     bool add_d;
     double rr = 0.0, bb = 0.0;
     double fx[K];
+    DT fd[K];
+    int fa[K];
     double hx[KH];
+    DT hd[KH];
+    int ha[KH];
     double ob[K];
     int oa[K];
     __device__ __forceinline__ void fetch_own(int k, int a)
     {
-        double v = a >= 0 ? x[a] : 0.0;
-        if (a >= 0 && add_d) v += (double)d[a];
-        fx[k] = v;
+        fa[k] = a;
+        fx[k] = raw_load(x, a);
+        fd[k] = add_d ? raw_load(d, a) : (DT)0;
     }
-    __device__ __forceinline__ double fin_own(int k) { return fx[k]; }
+    __device__ __forceinline__ double fin_own(int k) { return fa[k] >= 0 ? fx[k] + (double)fd[k] : 0.0; }
     __device__ __forceinline__ void fetch_halo(int j, int a)
     {
-        double v = a >= 0 ? x[a] : 0.0;
-        if (a >= 0 && add_d) v += (double)d[a];
-        hx[j] = v;
+        ha[j] = a;
+        hx[j] = raw_load(x, a);
+        hd[j] = add_d ? raw_load(d, a) : (DT)0;
     }
-    __device__ __forceinline__ double fin_halo(int j) { return hx[j]; }
+    __device__ __forceinline__ double fin_halo(int j) { return ha[j] >= 0 ? hx[j] + (double)hd[j] : 0.0; }
     __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
     {
         oa[k] = a;
-        ob[k] = a >= 0 ? b[a] : 0.0;
+        ob[k] = raw_load(b, a);
     }
     __device__ __forceinline__ void output(int k, double, double Au)
     {
-        if (oa[k] >= 0) {
-            const double t = ob[k] - Au;
-            r[oa[k]] = (RT)t;
-            rr += t * t;
-            bb += ob[k] * ob[k];
-        }
+        const bool ok = oa[k] >= 0;
+        const double bv = ok ? ob[k] : 0.0;
+        const double t = ok ? bv - Au : 0.0;
+        *sel_ptr(r, oa[k], sink) = (RT)t;
+        rr += t * t;
+        bb += bv * bv;
     }
 };
 
@@ -643,37 +701,44 @@ struct PFin {
     int f32, nx, ny;
     double e = 0.0, res = 0.0;
     double fx[K];
+    int fa[K];
     double hx[KH];
-    double ob[K], orho[K];
+    int ha[KH];
+    double ob[K], opi[K], opj[K];
     int oa[K];
-    __device__ __forceinline__ void fetch_own(int k, int a) { fx[k] = a >= 0 ? x[a] : 0.0; }
-    __device__ __forceinline__ double fin_own(int k) { return fx[k]; }
-    __device__ __forceinline__ void fetch_halo(int j, int a) { hx[j] = a >= 0 ? x[a] : 0.0; }
-    __device__ __forceinline__ double fin_halo(int j) { return hx[j]; }
+    __device__ __forceinline__ void fetch_own(int k, int a)
+    {
+        fa[k] = a;
+        fx[k] = raw_load(x, a);
+    }
+    __device__ __forceinline__ double fin_own(int k) { return fa[k] >= 0 ? fx[k] : 0.0; }
+    __device__ __forceinline__ void fetch_halo(int j, int a)
+    {
+        ha[j] = a;
+        hx[j] = raw_load(x, a);
+    }
+    __device__ __forceinline__ double fin_halo(int j) { return ha[j] >= 0 ? hx[j] : 0.0; }
     __device__ __forceinline__ void fetch_out(int k, int a, int gx, int gy, int gz)
     {
         oa[k] = a;
-        ob[k] = 0.0;
-        orho[k] = 0.0;
-        if (a >= 0) {
-            const long long gi = ((long long)gz * ny + gy) * nx + gx;
-            ob[k] = b[a];
-            orho[k] = load_phi(phi, f32, oi + gi) * load_phi(phi, f32, oj + gi);
-        }
+        ob[k] = raw_load(b, a);
+        const long long gi = ((long long)gz * ny + gy) * nx + gx;
+        opi[k] = load_phi(phi, f32, oi + gi);
+        opj[k] = load_phi(phi, f32, oj + gi);
     }
     __device__ __forceinline__ void output(int k, double u, double Au)
     {
-        if (oa[k] >= 0) {
-            const double t = ob[k] - Au;
-            res += t * t;
-            e += orho[k] * u;
-        }
+        const bool ok = oa[k] >= 0;
+        const double t = ok ? ob[k] - Au : 0.0;
+        res += t * t;
+        e += ok ? opi[k] * opj[k] * u : 0.0;
     }
 };
 
 // One pair: FP64 CG, or FP32 CG with FP64 iterative refinement.
-template <int T, int K, int KH>
-__device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, long long slot, double *lds, double *red, int &par)
+template <int T, int K, int KH, bool MIXED>
+__device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, long long slot, double *lds, double *red,
+                                               int &par)
 {
     const int tid = threadIdx.x;
     const int4 pg = a.pair_gc[pair];
@@ -686,13 +751,13 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     int it = 0, conv = 0, outer = 0;
     double bb = 0.0;
 
-    if (a.precision == 0) {
+    if constexpr (!MIXED) {
         double *r = a.scratch + slot * 3 * a.slot_n;
         double *pold = r + a.slot_n, *pnew = pold + a.slot_n;
         const double *rsrc = b;
         double rr = 0.0, pap = 0.0;
         if (guess) {
-            PRes<K, KH, double, double> pr{x, nullptr, b, r, false};
+            PRes<K, KH, double, double> pr{x, x, b, r, r + a.slot_n - 1, false};
             zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
             ++outer;
             rr = block_sum<T>(pr.rr, red);
@@ -700,7 +765,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
             rsrc = r;
         }
         {
-            PDir<double, K, KH> pd{rsrc, pold, pnew, 0.0, false, !guess};
+            PDir<double, K, KH> pd{rsrc, pold, pnew, pnew + a.slot_n - 1, 0.0, false, !guess};
             zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
             pap = block_sum<T>(pd.pap, red);
             if (!guess) rr = bb = block_sum<T>(pd.bb, red);
@@ -714,7 +779,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         } else {
             for (;;) {
                 const double alpha = rr / pap;
-                PUpd<double, K, KH> pu{pnew, rsrc, x, r, alpha, guess || it > 0};
+                PUpd<double, K, KH> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, guess || it > 0};
                 zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
                 const double rn = block_sum<T>(pu.rr, red);
                 ++it;
@@ -724,7 +789,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 if (rr <= stop) { conv = 1; break; }
                 if (it >= a.maxit) break;
                 double *t = pold; pold = pnew; pnew = t;
-                PDir<double, K, KH> pd{r, pold, pnew, beta, true, false};
+                PDir<double, K, KH> pd{r, pold, pnew, pnew + a.slot_n - 1, beta, true, false};
                 zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
             }
@@ -735,14 +800,13 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         float *d32 = r32 + a.slot_n;
         float *pold = d32 + a.slot_n, *pnew = pold + a.slot_n;
         const StencilW<float> w32 = stencil_w<float>(a);
-        float *lds32 = reinterpret_cast<float *>(lds);
         bool have_d = false;
         if (!guess) {
             for (int q = tid; q < g.n_pe; q += T) x[q] = 0.0;
             __syncthreads();
         }
         for (;;) {
-            PRes<K, KH, float, float> pr{x, d32, b, r32, have_d};
+            PRes<K, KH, float, float> pr{x, d32, b, r32, r32 + a.slot_n - 1, have_d};
             zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
             ++outer;
             const double rr0 = block_sum<T>(pr.rr, red);
@@ -764,15 +828,15 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
             const double istop = a.inner_tol * a.inner_tol * rr0;
             double rr = rr0, pap;
             {
-                PDir<float, K, KH> pd{r32, pold, pnew, 0.0f, false, false};
-                zmarch<float, T, K, KH>(g, lds32, par, pd, w32, pg, a.nx, a.ny, a.nz);
+                PDir<float, K, KH> pd{r32, pold, pnew, pnew + a.slot_n - 1, 0.0f, false, false};
+                zmarch<float, T, K, KH>(g, lds, par, pd, w32, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
             }
             int inner = 0;
             for (;;) {
                 const float alpha = (float)(rr / pap);
-                PUpd<float, K, KH> pu{pnew, r32, d32, r32, alpha, inner > 0};
-                zmarch<float, T, K, KH>(g, lds32, par, pu, w32, pg, a.nx, a.ny, a.nz);
+                PUpd<float, K, KH> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, inner > 0};
+                zmarch<float, T, K, KH>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
                 const double rn = block_sum<T>(pu.rr, red);
                 ++inner;
                 ++it;
@@ -780,8 +844,8 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 rr = rn;
                 if (rr <= istop || it >= a.maxit) break;
                 float *t = pold; pold = pnew; pnew = t;
-                PDir<float, K, KH> pd{r32, pold, pnew, beta, true, false};
-                zmarch<float, T, K, KH>(g, lds32, par, pd, w32, pg, a.nx, a.ny, a.nz);
+                PDir<float, K, KH> pd{r32, pold, pnew, pnew + a.slot_n - 1, beta, true, false};
+                zmarch<float, T, K, KH>(g, lds, par, pd, w32, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
             }
             have_d = true;
@@ -802,18 +866,12 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     __syncthreads();
 }
 
-template <int T, int K, int KH>
-__global__ __launch_bounds__(T) void k_cg_zmarch(SolveArgs a)
+template <int T, int K, int KH, int WPE, bool MIXED>
+__global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
 {
     extern __shared__ double lds_dyn[];
     __shared__ double red[T / 64];
     __shared__ int s_pair;
-    // zero both plane buffers once: the 3-wide frame and the points outside
-    // the PE projection are never written afterwards
-    const ClassDev g0 = a.cls[0], g1 = a.cls[1];
-    const int nplane = 2 * (g0.lds_plane > g1.lds_plane ? g0.lds_plane : g1.lds_plane);
-    for (int t = threadIdx.x; t < nplane; t += T) lds_dyn[t] = 0.0;
-    __syncthreads();
     int par = 0;
     int last_cls = -1;
     for (;;) {
@@ -823,13 +881,15 @@ __global__ __launch_bounds__(T) void k_cg_zmarch(SolveArgs a)
         __syncthreads();
         if (k >= a.wave_n) break;
         const int cls = a.pair_gc[a.wave_begin + k].w;
-        if (last_cls >= 0 && cls != last_cls) {
-            // a different class has a different plane pitch: clear again
-            for (int t = threadIdx.x; t < nplane; t += T) lds_dyn[t] = 0.0;
+        if (cls != last_cls) {
+            // the row-offset table of the class lives at the start of LDS
+            const ClassDev g = cls ? a.cls[1] : a.cls[0];
+            int *tbl = reinterpret_cast<int *>(lds_dyn);
+            for (int t = threadIdx.x; t < g.pnz * g.pny; t += T) tbl[t] = g.pe_off[t];
             __syncthreads();
+            last_cls = cls;
         }
-        last_cls = cls;
-        cg_zmarch_pair<T, K, KH>(a, a.wave_begin + k, blockIdx.x, lds_dyn, red, par);
+        cg_zmarch_pair<T, K, KH, MIXED>(a, a.wave_begin + k, blockIdx.x, lds_dyn, red, par);
     }
 }
 
@@ -924,11 +984,12 @@ __global__ void k_zero_int(int *p, int n)
 // launchers
 // ---------------------------------------------------------------------------
 
-#define EXX_ZM_VARIANTS(X) X(256, 4, 2) X(256, 8, 2) X(512, 4, 1) X(512, 6, 1)
+// (threads, columns per thread, halo columns per thread, min waves per SIMD)
+#define EXX_ZM_VARIANTS(X) X(256, 4, 2, 2) X(512, 4, 1, 2) X(512, 6, 1, 2)
 
 static const CgVariant kVariants[] = {
-    {0, 256, 0, 0},
-#define EXX_V(T, K, KH) {1, T, K, KH},
+    {0, 256, 0, 0, 0},
+#define EXX_V(T, K, KH, W) {1, T, K, KH, W},
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V
 };
@@ -941,22 +1002,21 @@ int cg_variants(CgVariant *out, int max_n)
     return n;
 }
 
-template <int T, int K, int KH>
-static hipError_t zm_prepare(size_t lds)
+template <int T, int K, int KH, int W, bool M>
+static hipError_t zm_occ(size_t lds, int *per_cu)
 {
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cg_zmarch<T, K, KH>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cg_zmarch<T, K, KH, W, M>),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    if (e != hipSuccess) return e;
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_cg_zmarch<T, K, KH, W, M>, T, lds);
 }
 
-hipError_t cg_occupancy(const CgVariant &v, size_t lds, int *blocks_per_cu)
+hipError_t cg_occupancy(const CgVariant &v, int mixed, size_t lds, int *blocks_per_cu)
 {
     if (!v.zmarch) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_solve<256>, 256, 0);
-#define EXX_V(T, K, KH)                                                                                     \
-    if (v.block == T && v.cols == K && v.halo == KH) {                                                       \
-        hipError_t e = zm_prepare<T, K, KH>(lds);                                                            \
-        if (e != hipSuccess) return e;                                                                       \
-        return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_cg_zmarch<T, K, KH>, T, lds);   \
-    }
+#define EXX_V(T, K, KH, W)                                                                     \
+    if (v.block == T && v.cols == K && v.halo == KH && v.wpe == W)                              \
+        return mixed ? zm_occ<T, K, KH, W, true>(lds, blocks_per_cu) : zm_occ<T, K, KH, W, false>(lds, blocks_per_cu);
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V
     return hipErrorInvalidValue;
@@ -968,10 +1028,13 @@ hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t ld
         hipLaunchKernelGGL(k_solve<256>, dim3(grid), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-#define EXX_V(T, K, KH)                                                                   \
-    if (v.block == T && v.cols == K && v.halo == KH) {                                     \
-        hipLaunchKernelGGL((k_cg_zmarch<T, K, KH>), dim3(grid), dim3(T), lds, s, a);        \
-        return hipGetLastError();                                                          \
+#define EXX_V(T, K, KH, W)                                                                          \
+    if (v.block == T && v.cols == K && v.halo == KH && v.wpe == W) {                                 \
+        if (a.precision)                                                                             \
+            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, W, true>), dim3(grid), dim3(T), lds, s, a);    \
+        else                                                                                         \
+            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, W, false>), dim3(grid), dim3(T), lds, s, a);   \
+        return hipGetLastError();                                                                    \
     }
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V
