@@ -72,7 +72,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 2 per thread)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--max-pairs", type=int, default=0, help="(profiling) keep only the first pairs' orbitals")
+    ap.add_argument("--copy-probe-mb", type=int, default=0,
+                    help="(profiling) also run a plain device copy of this many MiB, 3 times, to calibrate "
+                         "the FETCH_SIZE / WRITE_SIZE counters")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -83,6 +85,16 @@ def main():
     import torch
     from paper_1911_10630_amd import exx as X
     from paper_1911_10630_amd import synth as S
+
+    if args.copy_probe_mb:
+        n = args.copy_probe_mb * (1 << 20) // 8
+        src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"[bench] copy probe: 3 x {args.copy_probe_mb} MiB device-to-device")
+        del src, dst
 
     wl = S.WORKLOADS[args.workload]()
     if args.precision:
@@ -118,7 +130,8 @@ def main():
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         tr = json.load(open(PROFILE_TRAFFIC))
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name:
+        if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name
+                and tr.get("variant") == [st["solve_block"], st["cg_cols"]]):
             traffic = tr.get("bytes_per_launch")
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
