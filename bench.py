@@ -69,6 +69,7 @@ def main():
     ap.add_argument("--precision", default=None, choices=["fp64", "fp32_refine"])
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cols", type=int, default=0, help="CG columns per thread (-1: flat kernel)")
+    ap.add_argument("--inner-rtol", type=float, default=1e-5, help="FP32 inner CG tolerance (refinement)")
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 2 per thread)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -102,7 +103,7 @@ def main():
     dev = torch.device("cuda:0")
     log(f"[bench] workload {wl.name}: generating {wl.orbitals.n} orbitals on {dev}")
     phi = S.orbitals_torch(wl, device=dev)
-    ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols)
+    ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols, inner_rtol=args.inner_rtol)
     n_pairs = ctx.pairs(wl.orbitals.centers)
     info = ctx.pair_info(results=False)
     dxx = torch.empty_like(phi)
@@ -155,6 +156,7 @@ def main():
                             dxx_gbs=round(st["dxx_bytes"] / (st["dxx_ms"] * 1e-3) / 1e9, 1) if st["dxx_ms"] > 0 else None,
                             grid=st["solve_grid"], block=st["solve_block"], waves=st["n_waves"],
                             cg_cols=st["cg_cols"], cg_bands=st["cg_bands"], outer_total=st["outer_total"],
+                            inner_rtol=args.inner_rtol if wl.precision != "fp64" else None,
                             kernel_hash=kernel_hash()))
 
     if not args.no_cpu_baseline:

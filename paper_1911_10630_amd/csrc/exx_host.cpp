@@ -34,11 +34,11 @@ struct HostClass {
     std::vector<int4> pe_rows, me_rows;
     std::vector<int> pe_xyz, sh_xyz, cols;
     std::vector<int> colz, pe_off;
-    std::vector<int> bands;      // [n][12] for the selected CG variant
-    int plane_rows = 0;
+    std::vector<int> bands, bands32;   // [n][12] for the selected CG variant
+    int plane_rows = 0, plane_rows32 = 0;
     int4 *d_pe_rows = nullptr, *d_me_rows = nullptr;
     int *d_pe_xyz = nullptr, *d_sh_xyz = nullptr, *d_cols = nullptr, *d_bands = nullptr;
-    int *d_colz = nullptr, *d_pe_off = nullptr;
+    int *d_colz = nullptr, *d_pe_off = nullptr, *d_bands32 = nullptr;
 };
 
 template <typename T>
@@ -77,7 +77,7 @@ struct exx_ctx {
     DevBuf<float> d_scratch32;
 
     int block = 256, grid = 0, slots = 0, wave_n = 0, n_waves = 0;
-    CgVariant var{0, 256, 0, 0, 0};
+    CgVariant var{0, 256, 0, 0, 0, 0, 0};
     size_t lds_bytes = 0;
     long long slot_n = 0;
     const void *phi = nullptr;
@@ -324,13 +324,17 @@ ClassDev class_dev(const HostClass &k)
     d.lds_w = d.pnx + 6;
     d.plane_rows = k.plane_rows;
     d.lds_plane = k.plane_rows * (d.pnx + 6);
+    d.bands32 = k.d_bands32;
+    d.n_bands32 = (int)k.bands32.size() / 12;
+    d.lds_plane32 = k.plane_rows32 * (d.pnx + 6);
     return d;
 }
 
 // Splits the PE projection columns of one class into y bands of whole rows,
 // each with at most v.cols * v.block columns and at most v.halo * v.block
 // columns in its 3-row halos.  Returns false if the variant cannot hold it.
-bool make_bands(const HostClass &k, const CgVariant &v, std::vector<int> &out, int *plane_rows)
+bool make_bands(const HostClass &k, int cols_per_thread, int halo_per_thread, int block, std::vector<int> &out,
+                int *plane_rows)
 {
     out.clear();
     *plane_rows = 0;
@@ -343,7 +347,7 @@ bool make_bands(const HostClass &k, const CgVariant &v, std::vector<int> &out, i
     }
     for (int y = 0; y < ny; ++y) start[y + 1] += start[y];
     const int ncols = start[ny];
-    const long cap = (long)v.cols * v.block;
+    const long cap = (long)cols_per_thread * block;
     const int nb = (int)((ncols + cap - 1) / cap);
     const int target = (ncols + nb - 1) / nb;
     int y0 = 0;
@@ -353,7 +357,7 @@ bool make_bands(const HostClass &k, const CgVariant &v, std::vector<int> &out, i
         if (y1 == y0) return false;                  // a single row exceeds the capacity
         const int lo0 = std::max(0, y0 - 3), hi1 = std::min(ny, y1 + 3);
         const int nh = (start[y0] - start[lo0]) + (start[hi1] - start[y1]);
-        if (nh > (long)v.halo * v.block) return false;
+        if (nh > (long)halo_per_thread * block) return false;
         int zlo = 1 << 30, zhi = -(1 << 30);
         for (int z = k.pzlo; z <= k.pzhi; ++z)
             for (int y = y0; y < y1; ++y) {
@@ -371,10 +375,10 @@ bool make_bands(const HostClass &k, const CgVariant &v, std::vector<int> &out, i
 void free_class(HostClass &k)
 {
     for (void *p : {(void *)k.d_pe_rows, (void *)k.d_me_rows, (void *)k.d_pe_xyz, (void *)k.d_sh_xyz,
-                    (void *)k.d_cols, (void *)k.d_bands, (void *)k.d_colz, (void *)k.d_pe_off})
+                    (void *)k.d_cols, (void *)k.d_bands, (void *)k.d_colz, (void *)k.d_pe_off, (void *)k.d_bands32})
         if (p) (void)hipFree(p);
     k.d_pe_rows = k.d_me_rows = nullptr;
-    k.d_pe_xyz = k.d_sh_xyz = k.d_cols = k.d_bands = k.d_colz = k.d_pe_off = nullptr;
+    k.d_pe_xyz = k.d_sh_xyz = k.d_cols = k.d_bands = k.d_colz = k.d_pe_off = k.d_bands32 = nullptr;
 }
 
 double fact(int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
@@ -393,10 +397,12 @@ void ylm_norms(double *out)
 constexpr size_t kMaxLds = 160 * 1024 - 1024;   // gfx950 LDS per work-group, less static use
 
 // LDS of the z-march kernel for one class: row-offset table + two planes.
-size_t zmarch_lds(const HostClass &k, int plane_rows)
+size_t zmarch_lds(const HostClass &k, int plane_rows, int plane_rows32)
 {
     const size_t pny = k.pyhi - k.pylo + 1, pnz = k.pzhi - k.pzlo + 1, pnx = k.pxhi - k.pxlo + 1;
-    return (pny * pnz + 3) / 4 * 4 * sizeof(int) + (2 * (size_t)plane_rows * (pnx + 6) + 2) * sizeof(double);
+    const size_t p64 = (2 * (size_t)plane_rows * (pnx + 6) + 2) * sizeof(double);
+    const size_t p32 = (2 * (size_t)plane_rows32 * (pnx + 6) + 2) * sizeof(float);
+    return (pny * pnz + 3) / 4 * 4 * sizeof(int) + std::max(p64, p32);
 }
 
 // Chooses the CG kernel: among the z-march variants that fit (and match the
@@ -416,14 +422,22 @@ exx_status select_variant(exx_ctx *c)
         if (!v.zmarch) continue;
         if (c->prm.block_threads && v.block != c->prm.block_threads) continue;
         if (c->prm.cg_cols && v.cols != c->prm.cg_cols) continue;
-        int r0 = 0, r1 = 0;
-        if (!make_bands(c->cls[0], v, b0, &r0) || !make_bands(c->cls[1], v, b1, &r1)) continue;
-        const size_t lds = std::max(zmarch_lds(c->cls[0], r0), zmarch_lds(c->cls[1], r1));
+        int r0 = 0, r1 = 0, s0 = 0, s1 = 0;
+        std::vector<int> f0, f1;
+        if (!make_bands(c->cls[0], v.cols, v.halo, v.block, b0, &r0) ||
+            !make_bands(c->cls[1], v.cols, v.halo, v.block, b1, &r1))
+            continue;
+        if (c->prm.precision == EXX_FP32_REFINE &&
+            (!make_bands(c->cls[0], v.cols32, v.halo32, v.block, f0, &s0) ||
+             !make_bands(c->cls[1], v.cols32, v.halo32, v.block, f1, &s1)))
+            continue;
+        const size_t lds = std::max(zmarch_lds(c->cls[0], r0, s0), zmarch_lds(c->cls[1], r1, s1));
         if (lds > kMaxLds) continue;
         int per_cu = 0;
         if (cg_occupancy(v, c->prm.precision, lds, &per_cu) != hipSuccess || per_cu < 1) continue;
         const int nb = (int)(b0.size() + b1.size()) / 12;
-        const long score = (long)per_cu * v.block / 64 * 1000 - nb;
+        // resident waves first, then independent work-groups, then fewer bands
+        const long score = (long)per_cu * v.block / 64 * 1000 + per_cu * 100 - nb;
         if (score > best_score) { best = i; best_score = score; best_lds = lds; }
     }
     if (best < 0) {
@@ -436,12 +450,20 @@ exx_status select_variant(exx_ctx *c)
     c->lds_bytes = c->var.zmarch ? best_lds : 0;
     for (auto &k : c->cls) {
         if (k.d_bands) { (void)hipFree(k.d_bands); k.d_bands = nullptr; }
+        if (k.d_bands32) { (void)hipFree(k.d_bands32); k.d_bands32 = nullptr; }
         k.bands.clear();
-        k.plane_rows = 0;
+        k.bands32.clear();
+        k.plane_rows = k.plane_rows32 = 0;
         if (c->var.zmarch) {
-            make_bands(k, c->var, k.bands, &k.plane_rows);
+            make_bands(k, c->var.cols, c->var.halo, c->var.block, k.bands, &k.plane_rows);
             HIPCHK(c, hipMalloc((void **)&k.d_bands, k.bands.size() * sizeof(int)));
             HIPCHK(c, hipMemcpy(k.d_bands, k.bands.data(), k.bands.size() * sizeof(int), hipMemcpyHostToDevice));
+            if (c->prm.precision == EXX_FP32_REFINE) {
+                make_bands(k, c->var.cols32, c->var.halo32, c->var.block, k.bands32, &k.plane_rows32);
+                HIPCHK(c, hipMalloc((void **)&k.d_bands32, k.bands32.size() * sizeof(int)));
+                HIPCHK(c, hipMemcpy(k.d_bands32, k.bands32.data(), k.bands32.size() * sizeof(int),
+                                    hipMemcpyHostToDevice));
+            }
         }
     }
     c->block = c->var.block;
@@ -621,9 +643,8 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     if (c->prm.precision == EXX_FP32_REFINE) {
         if (!c->var.zmarch) return fail(c, EXX_EINVAL, "FP32 refinement needs a z-march CG kernel");
         if ((st = dev_reserve(c, c->d_scratch32, (size_t)c->slots * 4 * c->slot_n)) != EXX_OK) return st;
-    } else {
-        if ((st = dev_reserve(c, c->d_scratch, (size_t)c->slots * 3 * c->slot_n)) != EXX_OK) return st;
     }
+    if ((st = dev_reserve(c, c->d_scratch, (size_t)c->slots * 3 * c->slot_n)) != EXX_OK) return st;
     // right-hand sides of one wave of pairs; the wave is as large as the
     // device allows (one launch of each kernel when everything fits)
     {

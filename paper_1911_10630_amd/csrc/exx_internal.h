@@ -43,9 +43,12 @@ struct ClassDev {
     const int *bands;      // [n_bands][12] z-march bands: own cols [c0,c1), halo cols
                            // [h0,h1) u [h2,h3), planes [zlo, zhi], first own row ya
     int n_bands;
+    const int *bands32;    // bands of the FP32 passes (more columns per thread)
+    int n_bands32;
     int tbl_ints;          // LDS ints holding pe_off (pnz * pny rounded up to 4)
     int lds_w, lds_plane;  // z-march LDS plane: row pitch pnx + 6, plane_rows * lds_w
     int plane_rows;        // own rows of the widest band + 6
+    int lds_plane32;       // plane size of the FP32 bands
     int pxlo, pylo, pzlo, pnx, pny, pnz;   // PE bounding box
     int mxlo, mylo, mzlo, mnx, mny, mnz;   // ME bounding box
     int n_pe, n_sh;
@@ -107,8 +110,10 @@ hipError_t launch_prep(const SolveArgs &a, hipStream_t s);
 struct CgVariant {
     int zmarch;   // 0 flat, 1 z-march
     int block;    // threads per work-group
-    int cols;     // columns per thread per band (z-march)
-    int halo;     // halo columns per thread (z-march)
+    int cols;     // FP64 columns per thread per band (z-march)
+    int halo;     // FP64 halo columns per thread (z-march)
+    int cols32;   // FP32 columns per thread (refinement passes)
+    int halo32;   // FP32 halo columns per thread
     int wpe;      // minimum resident waves per SIMD the kernel is compiled for
 };
 int cg_variants(CgVariant *out, int max_n);

@@ -432,17 +432,19 @@ __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, double *l
                                             const StencilW<R> &w, const int4 &pg, int nx, int ny, int nz)
 {
     const int tid = threadIdx.x;
-    const int *bd = g.bands + 12 * bi;
+    constexpr bool F32 = sizeof(R) == 4;
+    const int *bd = (F32 ? g.bands32 : g.bands) + 12 * bi;
+    const int plane = F32 ? g.lds_plane32 : g.lds_plane;
     const int c0 = bd[0], c1 = bd[1], h0 = bd[2], h1 = bd[3], h2 = bd[4], h3 = bd[5], zlo = bd[6], zhi = bd[7];
     const int ya = bd[8];
     const int W = g.lds_w;
     const int *tbl = reinterpret_cast<const int *>(lds);
     R *planes = reinterpret_cast<R *>(lds + g.tbl_ints / 2);
-    R *lsink = planes + 2 * g.lds_plane;
+    R *lsink = planes + 2 * plane;
     // the plane buffers are band-relative: clear them (positions outside this
     // band's projection must read as zero)
     __syncthreads();
-    for (int t = tid; t < 2 * g.lds_plane + 2; t += T) lds[g.tbl_ints / 2 + t] = 0.0;
+    for (int t = tid; t < 2 * plane + 2; t += T) planes[t] = (R)0;
     __syncthreads();
 
     // own columns: x, table row, LDS offset, z range (empty range when unused)
@@ -532,7 +534,7 @@ __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, double *l
             for (int j = 0; j < 6; ++j) q[k][j] = q[k][j + 1];
             q[k][6] = un[k];
         }
-        R *buf = planes + (par & 1) * g.lds_plane;
+        R *buf = planes + (par & 1) * plane;
         ++par;
 #pragma unroll
         for (int k = 0; k < K; ++k) *(cok[k] ? buf + clo[k] : lsink) = q[k][3];
@@ -556,7 +558,8 @@ template <typename R, int T, int K, int KH, class P>
 __device__ __forceinline__ void zmarch(const ClassDev &g, double *lds, int &par, P &pol, const StencilW<R> &w,
                                        const int4 &pg, int nx, int ny, int nz)
 {
-    for (int bi = 0; bi < g.n_bands; ++bi) zmarch_band<R, T, K, KH>(g, bi, lds, par, pol, w, pg, nx, ny, nz);
+    const int nb = sizeof(R) == 4 ? g.n_bands32 : g.n_bands;
+    for (int bi = 0; bi < nb; ++bi) zmarch_band<R, T, K, KH>(g, bi, lds, par, pol, w, pg, nx, ny, nz);
 }
 
 // direction pass: u = r + beta p_old, p_new <- u; sum p.Ap (and b.b when r is b)
@@ -653,6 +656,7 @@ struct PRes {
     const double *b;
     RT *r, *sink;
     bool add_d;
+    double dscale;              // u = x + dscale * d
     double rr = 0.0, bb = 0.0;
     double fx[K];
     DT fd[K];
@@ -668,14 +672,14 @@ struct PRes {
         fx[k] = raw_load(x, a);
         fd[k] = add_d ? raw_load(d, a) : (DT)0;
     }
-    __device__ __forceinline__ double fin_own(int k) { return fa[k] >= 0 ? fx[k] + (double)fd[k] : 0.0; }
+    __device__ __forceinline__ double fin_own(int k) { return fa[k] >= 0 ? fx[k] + dscale * (double)fd[k] : 0.0; }
     __device__ __forceinline__ void fetch_halo(int j, int a)
     {
         ha[j] = a;
         hx[j] = raw_load(x, a);
         hd[j] = add_d ? raw_load(d, a) : (DT)0;
     }
-    __device__ __forceinline__ double fin_halo(int j) { return ha[j] >= 0 ? hx[j] + (double)hd[j] : 0.0; }
+    __device__ __forceinline__ double fin_halo(int j) { return ha[j] >= 0 ? hx[j] + dscale * (double)hd[j] : 0.0; }
     __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
     {
         oa[k] = a;
@@ -736,7 +740,7 @@ struct PFin {
 };
 
 // One pair: FP64 CG, or FP32 CG with FP64 iterative refinement.
-template <int T, int K, int KH, bool MIXED>
+template <int T, int K, int KH, int K32, int KH32, bool MIXED>
 __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, long long slot, double *lds, double *red,
                                                int &par)
 {
@@ -757,7 +761,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         const double *rsrc = b;
         double rr = 0.0, pap = 0.0;
         if (guess) {
-            PRes<K, KH, double, double> pr{x, x, b, r, r + a.slot_n - 1, false};
+            PRes<K, KH, double, double> pr{x, x, b, r, r + a.slot_n - 1, false, 0.0};
             zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
             ++outer;
             rr = block_sum<T>(pr.rr, red);
@@ -795,27 +799,38 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
             }
         }
     } else {
-        // FP32 inner CG on A d = r32 (zero guess), FP64 residual and x.
+        // FP32 CG with reliable updates.  The FP32 system is scaled so its
+        // residual has unit RMS (pair densities of distant orbitals are far
+        // below the FP32 range); the FP32 solution increment d is folded into
+        // the FP64 x, and the residual replaced by the true FP64 b - A x,
+        // whenever the recursive residual has dropped by a factor 10 since the
+        // last replacement or claims convergence.  The search direction is
+        // kept across replacements.
+        double *r64 = a.scratch + slot * 3 * a.slot_n;
         float *r32 = a.scratch32 + slot * 4 * a.slot_n;
         float *d32 = r32 + a.slot_n;
         float *pold = d32 + a.slot_n, *pnew = pold + a.slot_n;
         const StencilW<float> w32 = stencil_w<float>(a);
-        bool have_d = false;
+        const double n_el = (double)g.n_pe;
+        const double stop_rel2 = a.tol * a.tol;
         if (!guess) {
             for (int q = tid; q < g.n_pe; q += T) x[q] = 0.0;
             __syncthreads();
         }
+        double sigma = 1.0, rr_s = 0.0, rmax = 0.0, beta = 0.0;
+        bool have_d = false, first = true;
         for (;;) {
-            PRes<K, KH, float, float> pr{x, d32, b, r32, r32 + a.slot_n - 1, have_d};
+            // true residual of x (+ sigma d), in FP64
+            PRes<K, KH, float, double> pr{x, d32, b, r64, r64 + a.slot_n - 1, have_d, sigma};
             zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
             ++outer;
-            const double rr0 = block_sum<T>(pr.rr, red);
-            if (!have_d) bb = block_sum<T>(pr.bb, red);
+            const double rr_true = block_sum<T>(pr.rr, red);
+            if (first) bb = block_sum<T>(pr.bb, red);
             if (have_d) {
-                for (int q = tid; q < g.n_pe; q += T) x[q] += (double)d32[q];
+                for (int q = tid; q < g.n_pe; q += T) x[q] += sigma * (double)d32[q];
                 __syncthreads();
             }
-            if (bb == 0.0 || rr0 <= a.tol * a.tol * bb) {
+            if (bb == 0.0 || rr_true <= stop_rel2 * bb) {
                 if (bb == 0.0) {
                     for (int q = tid; q < g.n_pe; q += T) x[q] = 0.0;
                     __syncthreads();
@@ -824,31 +839,42 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 break;
             }
             if (it >= a.maxit) break;
-            // inner solve to inner_tol relative
-            const double istop = a.inner_tol * a.inner_tol * rr0;
-            double rr = rr0, pap;
-            {
-                PDir<float, K, KH> pd{r32, pold, pnew, pnew + a.slot_n - 1, 0.0f, false, false};
-                zmarch<float, T, K, KH>(g, lds, par, pd, w32, pg, a.nx, a.ny, a.nz);
-                pap = block_sum<T>(pd.pap, red);
-            }
-            int inner = 0;
+            const double sigma_new = sqrt(rr_true / n_el);
+            const double inv = 1.0 / sigma_new;            // scale in FP64, then round
+            for (int q = tid; q < g.n_pe; q += T) r32[q] = (float)(r64[q] * inv);
+            __syncthreads();
+            // direction update with the replaced residual: beta = |r_new|^2 / |r_old|^2
+            // in unscaled units; p_old was scaled by sigma, rescale it to sigma_new
+            const double beta_eff = first ? 0.0 : (rr_true / (rr_s * sigma * sigma)) * (sigma / sigma_new);
+            rr_s = rr_true / (sigma_new * sigma_new);
+            sigma = sigma_new;
+            rmax = rr_true;
+            have_d = false;
+            beta = beta_eff;
             for (;;) {
-                const float alpha = (float)(rr / pap);
-                PUpd<float, K, KH> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, inner > 0};
-                zmarch<float, T, K, KH>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
-                const double rn = block_sum<T>(pu.rr, red);
-                ++inner;
+                double pap;
+                {
+                    if (!first) { float *t = pold; pold = pnew; pnew = t; }
+                    PDir<float, K32, KH32> pd{r32, pold, pnew, pnew + a.slot_n - 1, (float)beta, !first, false};
+                    zmarch<float, T, K32, KH32>(g, lds, par, pd, w32, pg, a.nx, a.ny, a.nz);
+                    pap = block_sum<T>(pd.pap, red);
+                }
+                first = false;
+                const float alpha = (float)(rr_s / pap);
+                PUpd<float, K32, KH32> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, have_d};
+                zmarch<float, T, K32, KH32>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
+                const double rn_s = block_sum<T>(pu.rr, red);
                 ++it;
-                const float beta = (float)(rn / rr);
-                rr = rn;
-                if (rr <= istop || it >= a.maxit) break;
-                float *t = pold; pold = pnew; pnew = t;
-                PDir<float, K, KH> pd{r32, pold, pnew, pnew + a.slot_n - 1, beta, true, false};
-                zmarch<float, T, K, KH>(g, lds, par, pd, w32, pg, a.nx, a.ny, a.nz);
-                pap = block_sum<T>(pd.pap, red);
+                have_d = true;
+                const double rr_un = rn_s * sigma * sigma;
+                if (rr_un <= stop_rel2 * bb || rr_un <= 0.01 * rmax || it >= a.maxit || !(rn_s == rn_s)) {
+                    // replace the residual: rr_s keeps |r_k|^2 of the step just taken,
+                    // the next beta uses the true |r_k+1|^2
+                    break;
+                }
+                beta = rn_s / rr_s;
+                rr_s = rn_s;
             }
-            have_d = true;
         }
     }
 
@@ -866,7 +892,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     __syncthreads();
 }
 
-template <int T, int K, int KH, int WPE, bool MIXED>
+template <int T, int K, int KH, int K32, int KH32, int WPE, bool MIXED>
 __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
 {
     extern __shared__ double lds_dyn[];
@@ -889,7 +915,7 @@ __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
             __syncthreads();
             last_cls = cls;
         }
-        cg_zmarch_pair<T, K, KH, MIXED>(a, a.wave_begin + k, blockIdx.x, lds_dyn, red, par);
+        cg_zmarch_pair<T, K, KH, K32, KH32, MIXED>(a, a.wave_begin + k, blockIdx.x, lds_dyn, red, par);
     }
 }
 
@@ -984,12 +1010,13 @@ __global__ void k_zero_int(int *p, int n)
 // launchers
 // ---------------------------------------------------------------------------
 
-// (threads, columns per thread, halo columns per thread, min waves per SIMD)
-#define EXX_ZM_VARIANTS(X) X(256, 4, 2, 2) X(512, 4, 1, 2) X(512, 6, 1, 2)
+// (threads, FP64 columns / halo columns per thread, FP32 columns / halo
+// columns per thread, min waves per SIMD)
+#define EXX_ZM_VARIANTS(X) X(256, 4, 2, 8, 2, 2) X(512, 4, 1, 8, 1, 2) X(512, 6, 1, 8, 1, 2)
 
 static const CgVariant kVariants[] = {
-    {0, 256, 0, 0, 0},
-#define EXX_V(T, K, KH, W) {1, T, K, KH, W},
+    {0, 256, 0, 0, 0, 0, 0},
+#define EXX_V(T, K, KH, K32, KH32, W) {1, T, K, KH, K32, KH32, W},
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V
 };
@@ -1002,21 +1029,25 @@ int cg_variants(CgVariant *out, int max_n)
     return n;
 }
 
-template <int T, int K, int KH, int W, bool M>
+template <int T, int K, int KH, int K32, int KH32, int W, bool M>
 static hipError_t zm_occ(size_t lds, int *per_cu)
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cg_zmarch<T, K, KH, W, M>),
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cg_zmarch<T, K, KH, K32, KH32, W, M>),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_cg_zmarch<T, K, KH, W, M>, T, lds);
+    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_cg_zmarch<T, K, KH, K32, KH32, W, M>, T, lds);
 }
+
+#define EXX_MATCH(v, T, K, KH, K32, KH32, W) \
+    ((v).block == T && (v).cols == K && (v).halo == KH && (v).cols32 == K32 && (v).halo32 == KH32 && (v).wpe == W)
 
 hipError_t cg_occupancy(const CgVariant &v, int mixed, size_t lds, int *blocks_per_cu)
 {
     if (!v.zmarch) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_solve<256>, 256, 0);
-#define EXX_V(T, K, KH, W)                                                                     \
-    if (v.block == T && v.cols == K && v.halo == KH && v.wpe == W)                              \
-        return mixed ? zm_occ<T, K, KH, W, true>(lds, blocks_per_cu) : zm_occ<T, K, KH, W, false>(lds, blocks_per_cu);
+#define EXX_V(T, K, KH, K32, KH32, W)                                                           \
+    if (EXX_MATCH(v, T, K, KH, K32, KH32, W))                                                    \
+        return mixed ? zm_occ<T, K, KH, K32, KH32, W, true>(lds, blocks_per_cu)                  \
+                     : zm_occ<T, K, KH, K32, KH32, W, false>(lds, blocks_per_cu);
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V
     return hipErrorInvalidValue;
@@ -1028,13 +1059,13 @@ hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t ld
         hipLaunchKernelGGL(k_solve<256>, dim3(grid), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-#define EXX_V(T, K, KH, W)                                                                          \
-    if (v.block == T && v.cols == K && v.halo == KH && v.wpe == W) {                                 \
-        if (a.precision)                                                                             \
-            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, W, true>), dim3(grid), dim3(T), lds, s, a);    \
-        else                                                                                         \
-            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, W, false>), dim3(grid), dim3(T), lds, s, a);   \
-        return hipGetLastError();                                                                    \
+#define EXX_V(T, K, KH, K32, KH32, W)                                                                          \
+    if (EXX_MATCH(v, T, K, KH, K32, KH32, W)) {                                                                 \
+        if (a.precision)                                                                                        \
+            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, true>), dim3(grid), dim3(T), lds, s, a);    \
+        else                                                                                                    \
+            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, false>), dim3(grid), dim3(T), lds, s, a);   \
+        return hipGetLastError();                                                                               \
     }
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V
