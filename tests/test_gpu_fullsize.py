@@ -1,0 +1,123 @@
+"""Full-size parity: the 64-water workload (256 orbitals, 128^3 grid, 9,966
+pairs) in the launch configuration the benchmark times, checked on sampled
+outputs the oracle computes one by one, plus properties that hold at any size.
+
+* sampled pairs (self, non-self, the slowest to converge): v on PE and on the
+  shell and the pair energy against the FP64 oracle;
+* E_xx equals -sum w_ij e_ij of the per-pair energies (w = 1 self, 2 other);
+* D^k at sampled grid points equals sum over k's pairs of v_pair(g - C_pair)
+  phi_other(g), rebuilt on the host from the GPU's own per-pair potentials,
+  with the offset -> index map of the oracle's subdomain (Alg. 2 order).
+"""
+import concurrent.futures as cf
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import oracle as O  # noqa: E402
+from paper_1911_10630_amd import exx as X  # noqa: E402
+from paper_1911_10630_amd import synth as S  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def c2_run():
+    wl = S.c2_water64()
+    _say("[gpu] 64-water workload, full step")
+    phi = S.orbitals_torch(wl, device="cuda:0")
+    ctx = X.Exx.from_workload(wl)
+    n = ctx.pairs(wl.orbitals.centers)
+    E, D = ctx.step(phi)
+    torch.cuda.synchronize()
+    return wl, ctx, n, E, D, ctx.pair_info()
+
+
+def test_c2_all_pairs_converged(c2_run):
+    wl, ctx, n, E, D, info = c2_run
+    assert n == 9966
+    assert np.all(info["converged"] == 1)
+    assert info["relres"].max() <= 1e-9
+
+
+def test_c2_energy_is_weighted_pair_sum(c2_run):
+    wl, ctx, n, E, D, info = c2_run
+    w = np.where(info["i"] == info["j"], 1.0, 2.0)
+    assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
+
+
+def test_c2_sampled_pairs_vs_oracle(c2_run):
+    wl, ctx, n, E, D, info = c2_run
+    self_p = np.nonzero(info["i"] == info["j"])[0]
+    other_p = np.nonzero(info["i"] != info["j"])[0]
+    rng = np.random.default_rng(11)
+    pick = [int(rng.choice(self_p)), int(rng.choice(other_p)), int(rng.choice(other_p)),
+            int(other_p[np.argmax(info["iters"][other_p])])]
+    subs = [O.Subdomain(wl.n_grid, wl.cell, wl.r_pe[c], wl.r_me[c]) for c in (0, 1)]
+    orbs = sorted({int(info["i"][p]) for p in pick} | {int(info["j"][p]) for p in pick})
+    phis = dict(zip(orbs, S.orbitals_np(wl, orbs)))
+
+    def ref(p):
+        i, j = int(info["i"][p]), int(info["j"][p])
+        return subs[0 if i == j else 1].solve_pair(phis[i], phis[j], info["origin"][p])
+
+    _say(f"[gpu] oracle on sampled pairs {pick}")
+    with cf.ThreadPoolExecutor(len(pick)) as ex:
+        refs = list(ex.map(ref, pick))
+    for p, r in zip(pick, refs):
+        sub = subs[0 if info["i"][p] == info["j"][p] else 1]
+        got = ctx.debug_pair(p, sub.n_pe, sub.n_shell)
+        assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
+        assert np.max(np.abs(got["x"] - r["x"])) <= 1e-7 * np.max(np.abs(r["x"])), p
+        assert np.max(np.abs(got["vsh"] - r["vsh"])) <= 1e-10 * np.max(np.abs(r["vsh"])), p
+
+
+def test_c2_potential_accumulation_at_sampled_points(c2_run):
+    wl, ctx, n, E, D, info = c2_run
+    k = 37
+    mine = np.nonzero((info["i"] == k) | (info["j"] == k))[0]
+    N = np.array(wl.n_grid)
+    subs = [O.Subdomain(wl.n_grid, wl.cell, wl.r_pe[c], wl.r_me[c]) for c in (0, 1)]
+    maps = []
+    for sub in subs:
+        off = sub.offsets()
+        maps.append({tuple(o): q for q, o in enumerate(off.tolist())})
+    rng = np.random.default_rng(5)
+    pts = rng.integers(0, N, size=(1500, 3))
+    c = wl.orbitals.centers[k]
+    near = np.round(c / np.array(wl.h)).astype(int) + rng.integers(-20, 21, size=(1500, 3))
+    pts = np.concatenate([pts, np.mod(near, N)])
+    others = sorted({int(info["i"][p]) for p in mine} | {int(info["j"][p]) for p in mine})
+    phis = dict(zip(others, S.orbitals_np(wl, others)))
+    ref = np.zeros(len(pts))
+    for p in mine:
+        i, j = int(info["i"][p]), int(info["j"][p])
+        cls = 0 if i == j else 1
+        sub = subs[cls]
+        v = ctx.debug_pair(int(p), sub.n_pe, sub.n_shell)
+        vall = np.concatenate([v["x"], v["vsh"]])
+        oth = j if i == k else i
+        gc = info["origin"][p]
+        for t, g in enumerate(pts):
+            o = g - gc
+            o = (o + N // 2) % N - N // 2                 # candidate offset in [-N/2, N/2)
+            q = maps[cls].get((int(o[0]), int(o[1]), int(o[2])))
+            if q is None:
+                o2 = np.where(o < 0, o + N, o - N)        # clipped spheres: the other image
+                q = maps[cls].get((int(o2[0]), int(o2[1]), int(o2[2])))
+            if q is not None:
+                ref[t] += vall[q] * phis[oth][g[2], g[1], g[0]]
+    got = D[k].cpu().numpy()[pts[:, 2], pts[:, 1], pts[:, 0]]
+    scale = np.max(np.abs(ref))
+    assert scale > 0
+    assert np.max(np.abs(got - ref)) <= 1e-12 * scale
