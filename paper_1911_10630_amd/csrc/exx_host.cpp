@@ -11,6 +11,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 using namespace exx;
@@ -76,6 +77,18 @@ struct exx_ctx {
     DevBuf<int> d_iters, d_outer, d_conv, d_counter;
     DevBuf<float> d_scratch32;
 
+    // PE potentials of earlier steps (most recent first), keyed by (i, j)
+    struct Hist {
+        bool valid = false;
+        std::unordered_map<long long, int> index;
+        std::vector<int4> gc;
+        std::vector<long long> off;
+        DevBuf<float> v;
+    } hist[3];
+    DevBuf<PairGuess> d_guess;
+    DevBuf<long long> d_hist_off;
+    int guess_pairs = 0;     // pairs of the last solve that had a history
+
     int block = 256, grid = 0, slots = 0, wave_n = 0, n_waves = 0;
     CgVariant var{0, 256, 0, 0, 0, 0, 0};
     size_t lds_bytes = 0;
@@ -139,6 +152,18 @@ exx_status upload(exx_ctx *c, DevBuf<T> &b, const std::vector<T> &v)
     exx_status st = dev_reserve(c, b, v.size());
     if (st != EXX_OK) return st;
     if (!v.empty()) HIPCHK(c, hipMemcpy(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+    return EXX_OK;
+}
+
+// Stream-ordered upload.  With sync the host vector may die on return;
+// without, it must outlive the copy.
+template <typename T>
+exx_status upload_async(exx_ctx *c, DevBuf<T> &b, const std::vector<T> &v, hipStream_t s, bool sync)
+{
+    exx_status st = dev_reserve(c, b, v.size());
+    if (st != EXX_OK) return st;
+    if (!v.empty()) HIPCHK(c, hipMemcpyAsync(b.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    if (sync) HIPCHK(c, hipStreamSynchronize(s));
     return EXX_OK;
 }
 
@@ -702,7 +727,6 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
     a.relres_out = c->d_relres.p;
     a.counter = c->d_counter.p;
     a.static_sched = 0;
-    a.guess = c->prm.guess;
     a.precision = c->prm.precision;
     for (int k = 0; k < 3; ++k) a.h[k] = c->h[k];
     for (int k = 0; k < 4; ++k) a.wfd[k] = kFD[k];
@@ -710,18 +734,98 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
     a.inner_tol = c->prm.inner_rtol;
     a.maxit = c->prm.cg_max_iter;
     ylm_norms(a.ylm_norm);
+    // initial guess from earlier steps: constant, linear or quadratic
+    // extrapolation over the consecutive levels that hold the same (i, j)
+    const bool use_guess = c->prm.guess != EXX_GUESS_ZERO;
+    a.guess = use_guess ? 1 : 0;
+    c->guess_pairs = 0;
+    GuessArgs ga{};
+    if (use_guess) {
+        std::vector<PairGuess> tab((size_t)c->n_pairs);
+        const int max_levels = c->prm.guess == EXX_GUESS_PREVIOUS ? 1 : 3;
+        static const double coef[4][3] = {{0, 0, 0}, {1, 0, 0}, {2, -1, 0}, {3, -3, 1}};
+        for (int64_t p = 0; p < c->n_pairs; ++p) {
+            PairGuess &t = tab[p];
+            const long long key = (long long)c->ij[p].x * c->n_orb + c->ij[p].y;
+            int n = 0;
+            for (int k = 0; k < max_levels; ++k) {
+                t.off[k] = -1;
+                t.shift[k] = int4{0, 0, 0, 0};
+            }
+            for (int k = 0; k < max_levels; ++k) {
+                const exx_ctx::Hist &h = c->hist[k];
+                if (!h.valid) break;
+                auto it = h.index.find(key);
+                if (it == h.index.end()) break;
+                const int q = it->second;
+                t.off[k] = h.off[q];
+                int sh[3] = {c->gc[p].x - h.gc[q].x, c->gc[p].y - h.gc[q].y, c->gc[p].z - h.gc[q].z};
+                for (int d = 0; d < 3; ++d) {
+                    const int N = c->prm.n_grid[d];
+                    if (sh[d] > N / 2) sh[d] -= N;
+                    if (sh[d] < -N / 2) sh[d] += N;
+                }
+                t.shift[k] = int4{sh[0], sh[1], sh[2], 1};
+                ++n;
+            }
+            for (int k = max_levels; k < 3; ++k) {
+                t.off[k] = -1;
+                t.shift[k] = int4{0, 0, 0, 0};
+            }
+            for (int k = 0; k < 3; ++k) t.coef[k] = coef[n][k];
+            if (n) ++c->guess_pairs;
+        }
+        exx_status st2 = upload_async(c, c->d_guess, tab, s, true);
+        if (st2 != EXX_OK) return st2;
+        ga.cls[0] = a.cls[0];
+        ga.cls[1] = a.cls[1];
+        ga.pair_gc = c->d_gc.p;
+        ga.out_off = c->d_off.p;
+        ga.guess = c->d_guess.p;
+        for (int k = 0; k < 3; ++k) ga.hist[k] = c->hist[k].valid ? c->hist[k].v.p : nullptr;
+        ga.vout = c->d_vout.p;
+    }
     c->n_waves = 0;
     HIPCHK(c, hipEventRecord(c->ev[0], s));
     for (int64_t w0 = 0; w0 < c->n_pairs; w0 += c->wave_n) {
         a.wave_begin = (int)w0;
         a.wave_n = (int)std::min<int64_t>(c->wave_n, c->n_pairs - w0);
         HIPCHK(c, launch_prep(a, s));
+        if (use_guess) {
+            ga.wave_begin = a.wave_begin;
+            HIPCHK(c, launch_guess(ga, a.wave_n, s));
+        }
         HIPCHK(c, launch_zero_int(c->d_counter.p, 1, s));
         if (w0 == 0) HIPCHK(c, hipEventRecord(c->ev[5], s));
         HIPCHK(c, launch_cg(c->var, a, std::min(c->grid, a.wave_n), c->lds_bytes, s));
         ++c->n_waves;
     }
     HIPCHK(c, hipEventRecord(c->ev[1], s));
+    if (use_guess) {
+        // rotate the history ring and keep this step's PE potentials (FP32)
+        exx_ctx::Hist old = std::move(c->hist[2]);
+        c->hist[2] = std::move(c->hist[1]);
+        c->hist[1] = std::move(c->hist[0]);
+        exx_ctx::Hist &h = c->hist[0];
+        h = std::move(old);
+        h.valid = false;
+        h.index.clear();
+        h.gc = c->gc;
+        h.off.assign((size_t)c->n_pairs, 0);
+        long long tot = 0;
+        for (int64_t p = 0; p < c->n_pairs; ++p) {
+            h.off[p] = tot;
+            tot += c->cls[c->gc[p].w].n_pe;
+            h.index[(long long)c->ij[p].x * c->n_orb + c->ij[p].y] = (int)p;
+        }
+        exx_status st2 = dev_reserve(c, h.v, (size_t)tot);
+        if (st2 != EXX_OK) return st2;
+        // h.off lives until this level is recycled, after the copy completes
+        if ((st2 = upload_async(c, c->d_hist_off, h.off, s, false)) != EXX_OK) return st2;
+        HIPCHK(c, launch_save_history(c->d_vout.p, c->d_off.p, c->d_hist_off.p, c->d_gc.p, c->cls[0].n_pe,
+                                      c->cls[1].n_pe, (int)c->n_pairs, h.v.p, s));
+        h.valid = true;
+    }
     c->phi = phi;
     c->state = 3;
     c->solved_once = true;
@@ -880,6 +984,8 @@ void exx_destroy(exx_ctx *c)
     dev_free(c->d_ij); dev_free(c->d_gc); dev_free(c->d_off); dev_free(c->d_orb_ptr); dev_free(c->d_orb_pairs);
     dev_free(c->d_vout); dev_free(c->d_q); dev_free(c->d_e); dev_free(c->d_relres); dev_free(c->d_scratch);
     dev_free(c->d_rhs); dev_free(c->d_rho_keep);
+    dev_free(c->d_guess); dev_free(c->d_hist_off);
+    for (auto &h : c->hist) dev_free(h.v);
     dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_outer); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
     if (c->have_events)
         for (auto &e : c->ev)

@@ -88,6 +88,24 @@ struct SolveArgs {
     double ylm_norm[NLM];       // normalization of the real solid harmonics
 };
 
+// Initial guess of one pair from up to three earlier steps (Sec. III.C Step IV:
+// polynomial extrapolation of the potential from previous MD steps).
+struct PairGuess {
+    long long off[3];   // offset of the earlier PE solution in its history level, or -1
+    int4 shift[3];      // origin(now) - origin(then), minimum image, in grid points
+    double coef[3];     // extrapolation weights
+};
+
+struct GuessArgs {
+    ClassDev cls[2];
+    const int4 *pair_gc;
+    const long long *out_off;
+    const PairGuess *guess;    // [n_pairs]
+    const float *hist[3];      // history levels (most recent first)
+    double *vout;
+    int wave_begin;
+};
+
 struct DxxArgs {
     ClassDev cls[2];
     const int4 *pair_gc;
@@ -122,5 +140,8 @@ hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t ld
 hipError_t launch_dxx(const DxxArgs &a, int n_orb, hipStream_t s);
 hipError_t launch_energy(const double *e, const int2 *ij, int n_pairs, double *out, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
+hipError_t launch_guess(const GuessArgs &a, int n_pairs, hipStream_t s);
+hipError_t launch_save_history(const double *vout, const long long *out_off, const long long *hist_off,
+                               const int4 *pair_gc, int n_pe0, int n_pe1, int n_pairs, float *hist, hipStream_t s);
 
 }  // namespace exx

@@ -985,6 +985,46 @@ __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// initial guess from earlier steps, and the history it reads
+// ---------------------------------------------------------------------------
+
+// x0(o) = sum_k c_k v_{t-k}(o + shift_k) on PE, zero where the shifted point
+// lies outside the earlier PE sphere.  One work-group per pair of the wave.
+__global__ __launch_bounds__(256) void k_guess(GuessArgs a)
+{
+    const int pair = a.wave_begin + blockIdx.x;
+    const int4 pg = a.pair_gc[pair];
+    const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
+    const PairGuess pgs = a.guess[pair];
+    double *x = a.vout + a.out_off[pair];
+    for (int q = threadIdx.x; q < g.n_pe; q += 256) {
+        int ox, oy, oz;
+        unpack_xyz(g.pe_xyz[q], ox, oy, oz);
+        double v = 0.0;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            if (pgs.off[k] < 0) continue;
+            const int4 sh = pgs.shift[k];
+            const int src = pe_index(g, ox + sh.x, oy + sh.y, oz + sh.z);
+            if (src >= 0) v += pgs.coef[k] * (double)a.hist[k][pgs.off[k] + src];
+        }
+        x[q] = v;
+    }
+}
+
+// hist[hist_off[p] + q] = v_p on PE (FP32), for every pair.
+__global__ __launch_bounds__(256) void k_save_history(const double *vout, const long long *out_off,
+                                                      const long long *hist_off, const int4 *pair_gc, int n_pe0,
+                                                      int n_pe1, float *hist)
+{
+    const int p = blockIdx.x;
+    const int n = pair_gc[p].w ? n_pe1 : n_pe0;
+    const double *src = vout + out_off[p];
+    float *dst = hist + hist_off[p];
+    for (int q = threadIdx.x; q < n; q += 256) dst[q] = (float)src[q];
+}
+
+// ---------------------------------------------------------------------------
 // E reduction and small utilities
 // ---------------------------------------------------------------------------
 
@@ -1091,6 +1131,20 @@ hipError_t launch_dxx(const DxxArgs &a, int n_orb, hipStream_t s)
 hipError_t launch_energy(const double *e, const int2 *ij, int n_pairs, double *out, hipStream_t s)
 {
     hipLaunchKernelGGL(k_energy, dim3(1), dim3(1024), 0, s, e, ij, n_pairs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_guess(const GuessArgs &a, int n_pairs, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_guess, dim3(n_pairs), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_save_history(const double *vout, const long long *out_off, const long long *hist_off,
+                               const int4 *pair_gc, int n_pe0, int n_pe1, int n_pairs, float *hist, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_save_history, dim3(n_pairs), dim3(256), 0, s, vout, out_off, hist_off, pair_gc, n_pe0,
+                       n_pe1, hist);
     return hipGetLastError();
 }
 
