@@ -60,6 +60,53 @@ def cpu_baseline(wl, pi, pj, n_sample, threads, seed=0):
                        f"mean {float(np.mean(res['iters'])):.0f} CG iterations"), pick, res
 
 
+def md_run(args, wl):
+    """Synthetic MD: centres random-walk by N(0, (0.02 A)^2) per component per
+    step, orbitals rebuilt, pair list rebuilt, every step solved with the
+    requested initial guess.  One JSON line with per-step iterations."""
+    import torch
+    from paper_1911_10630_amd import exx as X
+    from paper_1911_10630_amd import synth as S
+    dev = torch.device("cuda:0")
+    rng = np.random.default_rng(2718)
+    orbs = wl.orbitals
+    ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols, inner_rtol=args.inner_rtol,
+                              guess=args.guess)
+    stream = torch.cuda.current_stream(dev)
+    steps = []
+    t_all = 0.0
+    n_all = 0
+    for k in range(args.md_steps):
+        wl_k = S.Workload(wl.name, wl.n_grid, wl.cell, orbs, wl.r_pair, wl.r_pe, wl.r_me,
+                          orbital_dtype=wl.orbital_dtype, precision=wl.precision)
+        phi = S.orbitals_torch(wl_k, device=dev)
+        dxx = torch.empty_like(phi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        n = ctx.pairs(orbs.centers)
+        ctx.solve(phi, stream)
+        E = ctx.energy_potential(dxx, stream)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = ctx.stats()
+        steps.append(dict(step=k, n_pairs=n, seconds=round(dt, 3), iters_mean=round(st["iters_total"] / n, 2),
+                          outer_mean=round(st["outer_total"] / n, 2), cg_ms=round(st["cg_ms"], 1), E_xx=E))
+        log(f"[bench] md step {k}: {n} pairs, {dt:.2f} s, mean iterations {st['iters_total'] / n:.1f}, E {E:.12f}")
+        if k > 0:                        # step 0 has no history for any guess
+            t_all += dt
+            n_all += n
+        orbs = S.md_displace(orbs, wl.cell[0], rng)
+        del phi, dxx
+    line = dict(metric="pair Poisson solves/s (MD steps 1..)", value=round(n_all / t_all, 2) if t_all else None,
+                unit="pair Poisson solves/s", n_gpus=1, steps=args.md_steps, warmup=1, higher_is_better=True,
+                dtype="f64" if wl.precision == "fp64" else "f32+f64", data="synthetic",
+                config=dict(workload=wl.name, guess=args.guess, precision=wl.precision,
+                            n_orbitals=wl.orbitals.n, grid=list(wl.n_grid)),
+                md=steps)
+    print(json.dumps(line), flush=True)
+    ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -73,6 +120,9 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 2 per thread)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--md-steps", type=int, default=0,
+                    help="run a synthetic MD trajectory of this many steps instead (initial-guess comparison)")
+    ap.add_argument("--guess", default="zero", choices=["zero", "previous", "extrap"])
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="(profiling) also run a plain device copy of this many MiB, 3 times, to calibrate "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -100,6 +150,8 @@ def main():
     wl = S.WORKLOADS[args.workload]()
     if args.precision:
         wl.precision = args.precision
+    if args.md_steps:
+        return md_run(args, wl)
     dev = torch.device("cuda:0")
     log(f"[bench] workload {wl.name}: generating {wl.orbitals.n} orbitals on {dev}")
     phi = S.orbitals_torch(wl, device=dev)

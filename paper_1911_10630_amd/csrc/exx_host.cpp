@@ -131,11 +131,14 @@ void dev_free(DevBuf<T> &b)
     b.n = 0;
 }
 
+// Grows a buffer to at least n elements.  Large buffers get 3 % slack so
+// that the pair count drifting between MD steps does not reallocate them.
 template <typename T>
 exx_status dev_reserve(exx_ctx *c, DevBuf<T> &b, size_t n)
 {
     if (n <= b.n && b.p) return EXX_OK;
     dev_free(b);
+    if (n * sizeof(T) > ((size_t)1 << 28)) n += n / 33;
     size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
     hipError_t e = hipMalloc(&b.p, bytes);
     if (e != hipSuccess) {
@@ -679,7 +682,16 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
         int64_t w = c->n_pairs;
         if (c->prm.wave_pairs > 0) w = std::min<int64_t>(w, c->prm.wave_pairs);
         const size_t have = c->d_rhs.n * sizeof(double);
-        const size_t budget = freeb + have > ((size_t)2 << 30) ? freeb + have - ((size_t)2 << 30) : 0;
+        // keep 2 GiB free, and room for the three history levels of the guess
+        size_t keep = (size_t)2 << 30;
+        if (c->prm.guess != EXX_GUESS_ZERO) {
+            size_t hist = 0;
+            for (auto &q : c->gc) hist += (size_t)c->cls[q.w].n_pe * sizeof(float);
+            size_t held = 0;
+            for (auto &h : c->hist) held += h.v.n * sizeof(float);
+            keep += 3 * hist > held ? 3 * hist - held : 0;
+        }
+        const size_t budget = freeb + have > keep ? freeb + have - keep : 0;
         w = std::min<int64_t>(w, (int64_t)(budget / per_pair));
         if (c->prm.keep_intermediates) w = c->n_pairs;
         if (w < 1) return fail(c, EXX_ENOMEM, "no device memory left for right-hand sides");

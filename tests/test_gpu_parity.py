@@ -194,3 +194,25 @@ def test_c1_fp32_orbitals(c1):
     assert Dg.dtype == torch.float32
     assert abs(Eg - E) <= 1e-8 * abs(E)
     assert gamma(D, Dg.cpu().numpy().astype(np.float64)).max() <= 1e-6
+
+
+def test_uneven_subdomain_classes_in_one_launch():
+    """Self and non-self pairs with different (R_PE, R_ME) (the paper's two
+    proto-subdomain classes) solved in one persistent launch."""
+    wl = S.c1_small()
+    wl.r_pe = (4.0 * S.ANG, 3.3 * S.ANG)
+    wl.r_me = (5.0 * S.ANG, 4.3 * S.ANG)
+    phi = S.orbitals_np(wl)
+    E, D, out = O.exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, wl.orbitals.centers, phi)
+    for prec in ("fp64", "fp32_refine"):
+        _say(f"[gpu] uneven classes {prec}")
+        ctx = X.Exx.from_workload(wl, precision=prec)
+        ctx.pairs(wl.orbitals.centers)
+        Eg, Dg = ctx.step(torch.from_numpy(phi).cuda())
+        st = ctx.stats()
+        assert st["n_pe"][0] != st["n_pe"][1] and st["n_waves"] == 1
+        info = ctx.pair_info()
+        assert np.all(info["converged"] == 1)
+        assert abs(Eg - E) <= 1e-8 * abs(E), (prec, Eg, E)
+        assert np.max(np.abs(info["e"] - out["e"]) / np.abs(out["e"])) <= 1e-8
+        assert gamma(D, Dg.cpu().numpy()).max() <= 1e-7
