@@ -52,7 +52,12 @@ typedef enum {
 
 enum { EXX_FP64 = 0, EXX_FP32_REFINE = 1 };                 /* CG arithmetic  */
 enum { EXX_F64 = 0, EXX_F32 = 1 };                          /* orbital dtype  */
-enum { EXX_GUESS_ZERO = 0, EXX_GUESS_PREVIOUS = 1, EXX_GUESS_EXTRAP = 2 };
+/* Initial CG guess (Sec. III.C Step IV): zero; the previous step's potential
+ * of the same (i, j); polynomial extrapolation over up to three earlier
+ * steps; or the learned model (exx_model_init / exx_load_model).  Every mode
+ * iterates to the same cg_rtol, so the guess changes iterations, not the
+ * converged result. */
+enum { EXX_GUESS_ZERO = 0, EXX_GUESS_PREVIOUS = 1, EXX_GUESS_EXTRAP = 2, EXX_GUESS_LEARNED = 3 };
 
 typedef struct {
     int32_t n_grid[3];      /* Nx, Ny, Nz                                       */
@@ -98,6 +103,8 @@ typedef struct {
     int64_t dxx_bytes;       /* algorithmic bytes of the D kernel               */
     int64_t device_bytes;    /* device memory held by the context              */
     int32_t n_waves;         /* pair waves of the last solve (1 = one launch)   */
+    int32_t guess_pairs;     /* pairs whose CG started from a non-zero guess    */
+    double  guess_ms;        /* last solve: guess kernels / model inference     */
 } exx_stats_t;
 
 /* Fills *p with the paper's method defaults (n = 3, l_max = 6, FP64, zero
@@ -153,6 +160,59 @@ exx_status exx_pair_info(exx_ctx *ctx, int32_t *pi, int32_t *pj, int32_t *origin
  * were not kept.  Synchronizes the device. */
 exx_status exx_debug_pair(exx_ctx *ctx, int64_t pair, double *v_pe, double *v_shell, double *q_lm,
                           double *rho, double *rhs);
+
+/* ---- learned initial guess ------------------------------------------------
+ *
+ * A 3-D convolutional U-Net (4 levels, 16-64 channels, bf16 weights with
+ * FP32 accumulation) maps a pair's right-hand side, averaged onto a cube of
+ * coarse cells of `coarsen`^3 grid points around the pair origin, to the
+ * coarse potential; the potential is interpolated back onto the PE sphere as
+ * the CG starting point (EXX_GUESS_LEARNED).  The paper names better initial
+ * guesses as the route to fewer CG iterations (Sec. III.C Step IV, Sec. VI).
+ * The model lives in the context and survives exx_pairs. */
+
+/* Creates a model with random (He-normal, seeded) weights.  coarsen: 2 or 4
+ * grid points per coarse cell edge, else EXX_EINVAL. */
+exx_status exx_model_init(exx_ctx *ctx, int32_t coarsen, uint64_t seed);
+
+/* Adam training on the pairs of the last solve: input its right-hand sides,
+ * target its converged potentials on ME.  Needs the last exx_solve to have
+ * run in one wave (every right-hand side resident), else EXX_ESTATE.
+ * epochs >= 1, 1 <= batch <= n_pairs, lr > 0.  *loss receives the mean
+ * masked squared error of the last epoch (normalized units).  Synchronizes
+ * `stream`.  The weight-gradient sums use atomics, so training is not
+ * bitwise reproducible; inference is. */
+exx_status exx_model_train(exx_ctx *ctx, int32_t epochs, int32_t batch, double lr, uint64_t seed, double *loss,
+                           void *stream);
+
+/* Serializes the model's FP32 weights into buf (host).  buf NULL: *bytes
+ * receives the size.  Else *bytes must hold at least that size (EXX_EINVAL
+ * otherwise) and receives it. */
+exx_status exx_model_save(exx_ctx *ctx, void *buf, size_t *bytes);
+
+/* Replaces the model by a blob from exx_model_save (host, copied).
+ * EXX_EINVAL if the blob's header or size does not match. */
+exx_status exx_load_model(exx_ctx *ctx, const void *weights, size_t bytes);
+
+/* Coarse cube edge the model runs at for this context (0 without model). */
+int32_t exx_model_edge(const exx_ctx *ctx);
+
+/* One 3x3x3 zero-padded convolution of model layer `layer`, for
+ * verification: y[v][co] = sum_tap sum_ci x[v + off(tap)][ci] W[tap][co][ci]
+ * with off(tap) = (tap % 3, tap / 3 % 3, tap / 9) - 1 in (x, y, z) and zero
+ * outside the cube (transposed = 0), or the input-gradient form with
+ * W[26 - tap][co][ci] summed over co (transposed = 1, channel counts
+ * swapped).  x: device bf16
+ * [n][edge^3][Cin] channels-last, voxel index (z * edge + y) * edge + x;
+ * y: device FP32 [n][edge^3][Cout].  Asynchronous on `stream`. */
+exx_status exx_model_conv(exx_ctx *ctx, int32_t layer, int32_t transposed, const void *x, float *y, int32_t n,
+                          int32_t edge, void *stream);
+
+/* Weight gradient of layer `layer`, for verification: dw[tap][co][ci] =
+ * sum_v dy[v][co] x[v + off(tap)][ci].  x, dy: device bf16 channels-last;
+ * dw: device FP32 [27][Cout][Cin], overwritten.  Asynchronous. */
+exx_status exx_model_wgrad(exx_ctx *ctx, int32_t layer, const void *x, const void *dy, float *dw, int32_t n,
+                           int32_t edge, void *stream);
 
 /* Message of the last failing call on ctx (or of the last failing
  * exx_setup when ctx is NULL).  Never NULL. */

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexx_mi355x.so")
-SOURCES = ["exx_kernels.hip", "exx_host.cpp"]
+SOURCES = ["exx_kernels.hip", "exx_net.hip", "exx_host.cpp"]
 ARCH = os.environ.get("EXX_OFFLOAD_ARCH", "gfx950")
 
 
@@ -32,8 +32,6 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(out_dir, os.path.splitext(src)[0] + ".o")
         cmd = [hipcc()] + common + ["-c", os.path.join(CSRC, src), "-o", obj]
-        if src.endswith(".hip"):
-            cmd += ["-x", "hip"] if False else []
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

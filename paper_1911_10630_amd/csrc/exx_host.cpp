@@ -88,13 +88,17 @@ struct exx_ctx {
     DevBuf<PairGuess> d_guess;
     DevBuf<long long> d_hist_off;
     int guess_pairs = 0;     // pairs of the last solve that had a history
+    // learned guess
+    ExxNet *net = nullptr;
+    int net_D = 0;           // coarse cube edge for this context's classes
+    double guess_ms = 0.0;   // last solve: guess kernels or net inference of wave 0
 
     int block = 256, grid = 0, slots = 0, wave_n = 0, n_waves = 0;
     CgVariant var{0, 256, 0, 0, 0, 0, 0};
     size_t lds_bytes = 0;
     long long slot_n = 0;
     const void *phi = nullptr;
-    hipEvent_t ev[6] = {};
+    hipEvent_t ev[7] = {};
     bool have_events = false;
     bool solved_once = false;
 };
@@ -248,6 +252,7 @@ exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
     const int mny = k.myhi - k.mylo + 1, mnz = k.mzhi - k.mzlo + 1;
     k.pe_rows.assign((size_t)pny * pnz, int4{0, 1, 0, 0});
     k.me_rows.assign((size_t)2 * mny * mnz, int4{0, 1, 0, 0});
+    for (size_t row = 0; row < (size_t)mny * mnz; ++row) k.me_rows[2 * row + 1] = int4{1, 0, 0, 0};  // empty run
     k.pe_xyz.clear();
     k.sh_xyz.clear();
     // PE packing, z-major / y / x (the order of Alg. 2)
@@ -356,6 +361,31 @@ ClassDev class_dev(const HostClass &k)
     d.n_bands32 = (int)k.bands32.size() / 12;
     d.lds_plane32 = k.plane_rows32 * (d.pnx + 6);
     return d;
+}
+
+// Largest |offset| of a PE point over both classes (grid points).
+int pe_rmax(const exx_ctx *c)
+{
+    int r = 0;
+    for (const HostClass &k : c->cls)
+        r = std::max({r, -k.pxlo, k.pxhi, -k.pylo, k.pyhi, -k.pzlo, k.pzhi});
+    return r;
+}
+
+NetPairArgs net_args(const exx_ctx *c)
+{
+    NetPairArgs n{};
+    n.cls[0] = class_dev(c->cls[0]);
+    n.cls[1] = class_dev(c->cls[1]);
+    n.pair_gc = c->d_gc.p;
+    n.out_off = c->d_off.p;
+    n.rhs = c->d_rhs.p;
+    n.slot_n = c->slot_n;
+    n.wave_begin = 0;
+    n.vout = c->d_vout.p;
+    n.h2 = std::cbrt(c->h[0] * c->h[1] * c->h[2]);
+    n.h2 *= n.h2;
+    return n;
 }
 
 // Splits the PE projection columns of one class into y bands of whole rows,
@@ -538,7 +568,7 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         return fail(nullptr, EXX_EINVAL, "unknown precision %d", p->precision);
     if (p->orbital_dtype != EXX_F64 && p->orbital_dtype != EXX_F32)
         return fail(nullptr, EXX_EINVAL, "unknown orbital_dtype %d", p->orbital_dtype);
-    if (p->guess < EXX_GUESS_ZERO || p->guess > EXX_GUESS_EXTRAP)
+    if (p->guess < EXX_GUESS_ZERO || p->guess > EXX_GUESS_LEARNED)
         return fail(nullptr, EXX_EINVAL, "unknown guess %d", p->guess);
     if (p->precision == EXX_FP32_REFINE && !(p->inner_rtol > 0.0 && p->inner_rtol < 1.0))
         return fail(nullptr, EXX_EINVAL, "inner_rtol must lie in (0, 1)");
@@ -684,7 +714,8 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
         const size_t have = c->d_rhs.n * sizeof(double);
         // keep 2 GiB free, and room for the three history levels of the guess
         size_t keep = (size_t)2 << 30;
-        if (c->prm.guess != EXX_GUESS_ZERO) {
+        if (c->prm.guess == EXX_GUESS_LEARNED) keep += (size_t)3 << 29;   // net activations
+        if (c->prm.guess == EXX_GUESS_PREVIOUS || c->prm.guess == EXX_GUESS_EXTRAP) {
             size_t hist = 0;
             for (auto &q : c->gc) hist += (size_t)c->cls[q.w].n_pe * sizeof(float);
             size_t held = 0;
@@ -747,10 +778,15 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
     a.maxit = c->prm.cg_max_iter;
     ylm_norms(a.ylm_norm);
     // initial guess from earlier steps: constant, linear or quadratic
-    // extrapolation over the consecutive levels that hold the same (i, j)
-    const bool use_guess = c->prm.guess != EXX_GUESS_ZERO;
-    a.guess = use_guess ? 1 : 0;
-    c->guess_pairs = 0;
+    // extrapolation over the consecutive levels that hold the same (i, j);
+    // or from the learned model
+    const bool use_guess = c->prm.guess == EXX_GUESS_PREVIOUS || c->prm.guess == EXX_GUESS_EXTRAP;
+    const bool learned = c->prm.guess == EXX_GUESS_LEARNED;
+    if (learned && !c->net) return fail(c, EXX_ESTATE, "guess = EXX_GUESS_LEARNED needs a model (exx_model_init or exx_load_model)");
+    a.guess = use_guess || learned ? 1 : 0;
+    c->guess_pairs = learned ? (int)c->n_pairs : 0;
+    NetPairArgs na{};
+    if (learned) na = net_args(c);
     GuessArgs ga{};
     if (use_guess) {
         std::vector<PairGuess> tab((size_t)c->n_pairs);
@@ -803,9 +839,14 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
         a.wave_begin = (int)w0;
         a.wave_n = (int)std::min<int64_t>(c->wave_n, c->n_pairs - w0);
         HIPCHK(c, launch_prep(a, s));
+        if (w0 == 0) HIPCHK(c, hipEventRecord(c->ev[6], s));
         if (use_guess) {
             ga.wave_begin = a.wave_begin;
             HIPCHK(c, launch_guess(ga, a.wave_n, s));
+        }
+        if (learned) {
+            na.wave_begin = a.wave_begin;
+            HIPCHK(c, net_infer(c->net, na, a.wave_n, c->net_D, nullptr, s));
         }
         HIPCHK(c, launch_zero_int(c->d_counter.p, 1, s));
         if (w0 == 0) HIPCHK(c, hipEventRecord(c->ev[5], s));
@@ -932,9 +973,11 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     float ms = 0.f;
     st->n_waves = c->n_waves;
     if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) st->solve_ms = ms;
-    st->prep_ms = st->cg_ms = -1.0;
+    st->prep_ms = st->cg_ms = st->guess_ms = -1.0;
+    st->guess_pairs = c->guess_pairs;
     if (c->n_waves == 1) {
-        if (hipEventElapsedTime(&ms, c->ev[0], c->ev[5]) == hipSuccess) st->prep_ms = ms;
+        if (hipEventElapsedTime(&ms, c->ev[0], c->ev[6]) == hipSuccess) st->prep_ms = ms;
+        if (hipEventElapsedTime(&ms, c->ev[6], c->ev[5]) == hipSuccess) st->guess_ms = ms;
         if (hipEventElapsedTime(&ms, c->ev[5], c->ev[1]) == hipSuccess) st->cg_ms = ms;
     }
     if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) st->dxx_ms = ms;
@@ -985,6 +1028,105 @@ exx_status exx_debug_pair(exx_ctx *c, int64_t pair, double *v_pe, double *v_shel
     return EXX_OK;
 }
 
+exx_status exx_model_init(exx_ctx *c, int32_t coarsen, uint64_t seed)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_init: ctx is NULL");
+    if (coarsen != 2 && coarsen != 4) return fail(c, EXX_EINVAL, "coarsen must be 2 or 4 (got %d)", coarsen);
+    HIPCHK(c, hipSetDevice(c->device));
+    net_destroy(c->net);
+    c->net = nullptr;
+    hipError_t e = hipSuccess;
+    ExxNet *net = net_create(coarsen, (unsigned long long)seed, &e);
+    if (e != hipSuccess) {
+        net_destroy(net);
+        return fail(c, e == hipErrorOutOfMemory ? EXX_ENOMEM : EXX_EDEVICE, "model allocation: %s", hipGetErrorString(e));
+    }
+    c->net = net;
+    c->net_D = net_edge(coarsen, pe_rmax(c));
+    return EXX_OK;
+}
+
+exx_status exx_load_model(exx_ctx *c, const void *weights, size_t bytes)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_load_model: ctx is NULL");
+    const int f = net_blob_coarsen(weights, bytes);
+    if (f < 0)
+        return fail(c, EXX_EINVAL, "exx_load_model: not a model blob of %zu bytes (got %zu)", net_model_bytes(), bytes);
+    exx_status st = exx_model_init(c, f, 0);
+    if (st != EXX_OK) return st;
+    hipError_t e = hipSuccess;
+    if (net_load(c->net, weights, bytes, &e) != 0)
+        return fail(c, EXX_EDEVICE, "exx_load_model: %s", hipGetErrorString(e));
+    return EXX_OK;
+}
+
+exx_status exx_model_save(exx_ctx *c, void *buf, size_t *bytes)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_save: ctx is NULL");
+    if (!bytes) return fail(c, EXX_EINVAL, "exx_model_save: bytes is NULL");
+    if (!c->net) return fail(c, EXX_ESTATE, "exx_model_save: no model");
+    const size_t need = net_model_bytes();
+    if (!buf) {
+        *bytes = need;
+        return EXX_OK;
+    }
+    if (*bytes < need) return fail(c, EXX_EINVAL, "exx_model_save: buffer of %zu bytes, need %zu", *bytes, need);
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, hipDeviceSynchronize());
+    HIPCHK(c, net_save(c->net, buf));
+    *bytes = need;
+    return EXX_OK;
+}
+
+exx_status exx_model_train(exx_ctx *c, int32_t epochs, int32_t batch, double lr, uint64_t seed, double *loss,
+                           void *stream)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_train: ctx is NULL");
+    if (!c->net) return fail(c, EXX_ESTATE, "exx_model_train: no model (exx_model_init or exx_load_model)");
+    if (c->state < 3) return fail(c, EXX_ESTATE, "exx_model_train before exx_solve");
+    if (c->n_waves != 1)
+        return fail(c, EXX_ESTATE, "exx_model_train needs every right-hand side resident; the last solve ran in %d waves",
+                    c->n_waves);
+    if (epochs < 1 || batch < 1 || batch > c->n_pairs || !(lr > 0.0) || !loss)
+        return fail(c, EXX_EINVAL, "exx_model_train: need epochs >= 1, 1 <= batch <= n_pairs, lr > 0, loss");
+    HIPCHK(c, hipSetDevice(c->device));
+    std::vector<int> pairs((size_t)c->n_pairs);
+    for (int64_t p = 0; p < c->n_pairs; ++p) pairs[p] = (int)p;
+    HIPCHK(c, net_train(c->net, net_args(c), pairs.data(), (int)c->n_pairs, c->net_D, epochs, batch, (float)lr,
+                        (unsigned long long)seed, loss, (hipStream_t)stream));
+    return EXX_OK;
+}
+
+exx_status exx_model_conv(exx_ctx *c, int32_t layer, int32_t transposed, const void *x, float *y, int32_t n,
+                          int32_t edge, void *stream)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_conv: ctx is NULL");
+    if (!c->net) return fail(c, EXX_ESTATE, "exx_model_conv: no model");
+    int cin = 0, cout = 0;
+    if (net_layer_dims(layer, &cin, &cout) != 0) return fail(c, EXX_EINVAL, "layer %d out of range", layer);
+    if (!x || !y || n < 1 || edge < 1 || (long long)n * edge * edge * edge > (1LL << 30))
+        return fail(c, EXX_EINVAL, "exx_model_conv: need x, y, n >= 1, 1 <= edge, n edge^3 <= 2^30");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, net_conv_test(c->net, layer, transposed, x, y, n, edge, (hipStream_t)stream));
+    return EXX_OK;
+}
+
+exx_status exx_model_wgrad(exx_ctx *c, int32_t layer, const void *x, const void *dy, float *dw, int32_t n,
+                           int32_t edge, void *stream)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_wgrad: ctx is NULL");
+    if (!c->net) return fail(c, EXX_ESTATE, "exx_model_wgrad: no model");
+    int cin = 0, cout = 0;
+    if (net_layer_dims(layer, &cin, &cout) != 0) return fail(c, EXX_EINVAL, "layer %d out of range", layer);
+    if (!x || !dy || !dw || n < 1 || edge < 1 || (long long)n * edge * edge * edge > (1LL << 30))
+        return fail(c, EXX_EINVAL, "exx_model_wgrad: need x, dy, dw, n >= 1, 1 <= edge, n edge^3 <= 2^30");
+    HIPCHK(c, hipSetDevice(c->device));
+    HIPCHK(c, net_wgrad_test(c->net, layer, x, dy, dw, n, edge, (hipStream_t)stream));
+    return EXX_OK;
+}
+
+int32_t exx_model_edge(const exx_ctx *c) { return c && c->net ? c->net_D : 0; }
+
 const char *exx_last_error(const exx_ctx *c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
 
 void exx_destroy(exx_ctx *c)
@@ -998,6 +1140,7 @@ void exx_destroy(exx_ctx *c)
     dev_free(c->d_rhs); dev_free(c->d_rho_keep);
     dev_free(c->d_guess); dev_free(c->d_hist_off);
     for (auto &h : c->hist) dev_free(h.v);
+    net_destroy(c->net);
     dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_outer); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
     if (c->have_events)
         for (auto &e : c->ev)

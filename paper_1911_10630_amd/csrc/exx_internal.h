@@ -33,7 +33,8 @@ __host__ __device__ inline void unpack_xyz(int v, int &x, int &y, int &z)
 // row (z, y) holds the run [mlo, plo-1] then [phi+1, mhi].
 struct ClassDev {
     const int4 *pe_rows;   // [pnz][pny] {base, xlo, xhi, 0}; empty row: xlo > xhi
-    const int4 *me_rows;   // [mnz][mny][2] {pe_base, plo, phi, sh_base}, {mlo, mhi, 0, 0}
+    const int4 *me_rows;   // [mnz][mny][2] {pe_base, plo, phi, sh_base}, {mlo, mhi, 0, 0};
+                           // a row outside ME has mlo > mhi
     const int *pe_xyz;     // [n_pe] packed offsets
     const int *sh_xyz;     // [n_sh] packed offsets
     const int *cols;       // [n_cols] packed (x, y, 0) of the PE projection, sorted (y, x)
@@ -53,6 +54,25 @@ struct ClassDev {
     int mxlo, mylo, mzlo, mnx, mny, mnz;   // ME bounding box
     int n_pe, n_sh;
 };
+
+// PE packed index of offset (x, y, z), or -1 if outside PE.
+__device__ __forceinline__ int pe_index(const ClassDev &g, int x, int y, int z)
+{
+    const int zz = z - g.pzlo, yy = y - g.pylo;
+    if ((unsigned)zz >= (unsigned)g.pnz || (unsigned)yy >= (unsigned)g.pny) return -1;
+    const int4 r = g.pe_rows[zz * g.pny + yy];
+    if (x < r.y || x > r.z) return -1;
+    return r.x + x - r.y;
+}
+
+// Shell packed index of an offset known to lie in ME but not in PE.
+__device__ __forceinline__ int sh_index(const ClassDev &g, int x, int y, int z)
+{
+    const int row = (z - g.mzlo) * g.mny + (y - g.mylo);
+    const int4 a = g.me_rows[2 * row];
+    const int4 b = g.me_rows[2 * row + 1];
+    return a.w + (x < a.y ? x - b.x : (a.y - b.x) + (x - a.z - 1));
+}
 
 struct SolveArgs {
     ClassDev cls[2];
@@ -143,5 +163,46 @@ hipError_t launch_zero_int(int *p, int n, hipStream_t s);
 hipError_t launch_guess(const GuessArgs &a, int n_pairs, hipStream_t s);
 hipError_t launch_save_history(const double *vout, const long long *out_off, const long long *hist_off,
                                const int4 *pair_gc, int n_pe0, int n_pe1, int n_pairs, float *hist, hipStream_t s);
+
+// Learned initial guess (exx_net.hip).  The net reads a pair's right-hand
+// side on a coarse cube (coarsening factor f, edge D coarse cells, fine
+// offsets [-fD/2, fD/2) per axis) and writes its PE guess into vout.
+struct NetPairArgs {
+    ClassDev cls[2];
+    const int4 *pair_gc;
+    const long long *out_off;
+    const double *rhs;          // right-hand sides of the wave, slot_n each
+    long long slot_n;
+    int wave_begin;
+    double *vout;               // read (training targets) or written (guess)
+    double h2;                  // output scale: RMS(v) ~ RMS(b) h^2
+};
+
+struct ExxNet;
+// Fresh net with He-initialized weights; coarsening factor f (2 or 4).
+ExxNet *net_create(int f, unsigned long long seed, hipError_t *err);
+void net_destroy(ExxNet *net);
+int net_coarsen(const ExxNet *net);
+// Coarse edge for PE offsets |o| <= r_max: f D / 2 >= r_max + 1, D a multiple of 8.
+int net_edge(int f, int r_max);
+// Device bytes of the activation buffers for `batch` samples of edge D
+// (training adds the gradient buffers).
+size_t net_buffer_bytes(int batch, int D, bool training);
+// Guess for pairs [wave_begin, wave_begin + n) of the wave in a.
+hipError_t net_infer(ExxNet *net, const NetPairArgs &a, int n, int D, double *ms, hipStream_t s);
+// Adam epochs over the given pairs (their rhs and solutions must be resident).
+hipError_t net_train(ExxNet *net, const NetPairArgs &a, const int *pairs, int n_pairs, int D, int epochs, int batch,
+                     float lr, unsigned long long seed, double *loss, hipStream_t s);
+size_t net_model_bytes();
+hipError_t net_save(ExxNet *net, void *host);
+// Returns 0, or -1 for a malformed blob (header or size), or -2 on a device error (*err).
+int net_load(ExxNet *net, const void *host, size_t bytes, hipError_t *err);
+int net_blob_coarsen(const void *host, size_t bytes);
+// One forward convolution of layer l (or its input-gradient form) on given
+// bf16 input [N][D^3][Cin], FP32 output [N][D^3][Cout]; for tests.
+hipError_t net_conv_test(ExxNet *net, int l, int transposed, const void *x, float *y, int N, int D, hipStream_t s);
+// Weight gradient of layer l for given bf16 x and dy, FP32 [27][Cout][Cin]; for tests.
+hipError_t net_wgrad_test(ExxNet *net, int l, const void *x, const void *dy, float *dw, int N, int D, hipStream_t s);
+int net_layer_dims(int l, int *cin, int *cout);
 
 }  // namespace exx

@@ -82,25 +82,6 @@ __device__ __forceinline__ double block_sum(double v, double *red)
     return s;
 }
 
-// PE packed index of offset (x, y, z), or -1 if outside PE.
-__device__ __forceinline__ int pe_index(const ClassDev &g, int x, int y, int z)
-{
-    const int zz = z - g.pzlo, yy = y - g.pylo;
-    if ((unsigned)zz >= (unsigned)g.pnz || (unsigned)yy >= (unsigned)g.pny) return -1;
-    const int4 r = g.pe_rows[zz * g.pny + yy];
-    if (x < r.y || x > r.z) return -1;
-    return r.x + x - r.y;
-}
-
-// Shell packed index of an offset known to lie in ME but not in PE.
-__device__ __forceinline__ int sh_index(const ClassDev &g, int x, int y, int z)
-{
-    const int row = (z - g.mzlo) * g.mny + (y - g.mylo);
-    const int4 a = g.me_rows[2 * row];
-    const int4 b = g.me_rows[2 * row + 1];
-    return a.w + (x < a.y ? x - b.x : (a.y - b.x) + (x - a.z - 1));
-}
-
 // (A u)_q for packed PE vector u, A = -(discrete Laplacian restricted to PE).
 __device__ __forceinline__ double apply_A_flat(const ClassDev &g, const double *u, int q, int x, int y, int z,
                                                const double (&w)[3][4])

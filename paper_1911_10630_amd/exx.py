@@ -20,11 +20,12 @@ _STATUS = {0: "EXX_OK", -1: "EXX_EINVAL", -2: "EXX_ENOMEM", -3: "EXX_EDEVICE", -
            -5: "EXX_ESTATE"}
 PRECISION = {"fp64": 0, "fp32_refine": 1}
 ORBITAL_DTYPE = {"f64": 0, "f32": 1}
-GUESS = {"zero": 0, "previous": 1, "extrap": 2}
+GUESS = {"zero": 0, "previous": 1, "extrap": 2, "learned": 3}
 NLM = 49
 
 EXPORTS = ["exx_default_params", "exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats",
-           "exx_pair_info", "exx_debug_pair", "exx_last_error", "exx_destroy"]
+           "exx_pair_info", "exx_debug_pair", "exx_last_error", "exx_destroy", "exx_model_init", "exx_model_train",
+           "exx_model_save", "exx_load_model", "exx_model_edge", "exx_model_conv", "exx_model_wgrad"]
 
 
 class ExxParams(C.Structure):
@@ -45,7 +46,8 @@ class ExxStats(C.Structure):
                 ("solve_grid", C.c_int32), ("solve_block", C.c_int32), ("cg_cols", C.c_int32),
                 ("cg_bands", C.c_int32 * 2), ("outer_total", C.c_int64), ("n_pe", C.c_int64 * 2),
                 ("n_me", C.c_int64 * 2), ("cg_bytes", C.c_int64), ("solve_bytes", C.c_int64),
-                ("dxx_bytes", C.c_int64), ("device_bytes", C.c_int64), ("n_waves", C.c_int32)]
+                ("dxx_bytes", C.c_int64), ("device_bytes", C.c_int64), ("n_waves", C.c_int32),
+                ("guess_pairs", C.c_int32), ("guess_ms", C.c_double)]
 
 
 class ExxError(RuntimeError):
@@ -80,8 +82,17 @@ def load() -> C.CDLL:
     L.exx_last_error.restype = C.c_char_p
     L.exx_destroy.argtypes = [vp]
     L.exx_destroy.restype = None
+    L.exx_model_init.argtypes = [vp, i32, C.c_uint64]
+    L.exx_model_train.argtypes = [vp, i32, i32, C.c_double, C.c_uint64, dp, vp]
+    L.exx_model_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
+    L.exx_load_model.argtypes = [vp, vp, C.c_size_t]
+    L.exx_model_edge.argtypes = [vp]
+    L.exx_model_edge.restype = i32
+    L.exx_model_conv.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp]
+    L.exx_model_wgrad.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp]
     for f in ["exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats", "exx_pair_info",
-              "exx_debug_pair"]:
+              "exx_debug_pair", "exx_model_init", "exx_model_train", "exx_model_save", "exx_load_model",
+              "exx_model_conv", "exx_model_wgrad"]:
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -216,6 +227,40 @@ class Exx:
                                           _ptr(d.get("rho")), _ptr(d.get("b"))))
         d["vsh"] = d["vsh"][:n_shell]
         return d
+
+    # ---- learned initial guess -------------------------------------------
+
+    def model_init(self, coarsen: int = 2, seed: int = 0):
+        self._check(load().exx_model_init(self._h, int(coarsen), int(seed)))
+
+    def model_train(self, epochs: int = 1, batch: int = 8, lr: float = 1e-3, seed: int = 0, stream=None) -> float:
+        import torch
+        loss = C.c_double()
+        self._check(load().exx_model_train(self._h, int(epochs), int(batch), float(lr), int(seed), C.byref(loss),
+                                           _stream_handle(stream, torch.device("cuda", self.device))))
+        return loss.value
+
+    def model_save(self) -> bytes:
+        n = C.c_size_t()
+        self._check(load().exx_model_save(self._h, None, C.byref(n)))
+        buf = C.create_string_buffer(n.value)
+        self._check(load().exx_model_save(self._h, buf, C.byref(n)))
+        return buf.raw[:n.value]
+
+    def load_model(self, blob: bytes):
+        buf = C.create_string_buffer(bytes(blob), len(blob))
+        self._check(load().exx_load_model(self._h, buf, len(blob)))
+
+    def model_edge(self) -> int:
+        return int(load().exx_model_edge(self._h))
+
+    def model_conv(self, layer: int, x, y, n: int, edge: int, transposed: bool = False, stream=None):
+        self._check(load().exx_model_conv(self._h, int(layer), 1 if transposed else 0, _ptr(x), _ptr(y), int(n),
+                                          int(edge), _stream_handle(stream, x.device)))
+
+    def model_wgrad(self, layer: int, x, dy, dw, n: int, edge: int, stream=None):
+        self._check(load().exx_model_wgrad(self._h, int(layer), _ptr(x), _ptr(dy), _ptr(dw), int(n), int(edge),
+                                           _stream_handle(stream, x.device)))
 
     def close(self):
         if getattr(self, "_h", None):

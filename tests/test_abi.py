@@ -48,6 +48,7 @@ int main(void) {
   printf("stats %zu\n", sizeof(exx_stats_t));
   O(exx_stats_t, relres_max) O(exx_stats_t, cg_ms) O(exx_stats_t, n_pe) O(exx_stats_t, n_me)
   O(exx_stats_t, cg_bytes) O(exx_stats_t, n_waves) O(exx_stats_t, cg_bands) O(exx_stats_t, outer_total)
+  O(exx_stats_t, guess_pairs) O(exx_stats_t, guess_ms)
   return 0;
 }
 '''
@@ -68,7 +69,8 @@ def test_struct_layout_matches_header():
               "precision", "orbital_dtype", "guess", "inner_rtol", "block_threads", "cg_cols", "wave_pairs",
               "keep_intermediates"]:
         assert lay[f] == getattr(X.ExxParams, f).offset, f
-    for f in ["relres_max", "cg_ms", "n_pe", "n_me", "cg_bytes", "n_waves", "cg_bands", "outer_total"]:
+    for f in ["relres_max", "cg_ms", "n_pe", "n_me", "cg_bytes", "n_waves", "cg_bands", "outer_total",
+              "guess_pairs", "guess_ms"]:
         assert lay[f] == getattr(X.ExxStats, f).offset, f
 
 
@@ -133,7 +135,24 @@ def test_calls_on_null_context():
     assert L.exx_solve(None, None, None) == X.EXX_EINVAL
     e = C.c_double()
     assert L.exx_energy_potential(None, C.byref(e), None, None) == X.EXX_EINVAL
+    assert L.exx_model_init(None, 2, 0) == X.EXX_EINVAL
+    assert L.exx_model_train(None, 1, 1, 1e-3, 0, C.byref(e), None) == X.EXX_EINVAL
+    n = C.c_size_t()
+    assert L.exx_model_save(None, None, C.byref(n)) == X.EXX_EINVAL
+    assert L.exx_load_model(None, None, 0) == X.EXX_EINVAL
+    assert L.exx_model_conv(None, 0, 0, None, None, 1, 1, None) == X.EXX_EINVAL
+    assert L.exx_model_wgrad(None, 0, None, None, None, 1, 1, None) == X.EXX_EINVAL
+    assert L.exx_model_edge(None) == 0
     L.exx_destroy(None)
+
+
+def test_learned_guess_is_a_valid_mode():
+    """guess = EXX_GUESS_LEARNED passes validation (and fails only for the
+    missing device here); one past it is rejected."""
+    st, msg = _setup_status(guess=4)
+    assert st == X.EXX_EINVAL and "guess" in msg
+    st, msg = _setup_status(guess=3)
+    assert st != X.EXX_EINVAL
 
 
 def test_setup_without_gpu_reports_device_error():
