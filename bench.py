@@ -60,6 +60,38 @@ def cpu_baseline(wl, pi, pj, n_sample, threads, seed=0):
                        f"mean {float(np.mean(res['iters'])):.0f} CG iterations"), pick, res
 
 
+def train_model(args, wl, ctx):
+    """Trains the learned-guess model before anything is timed, on the same
+    configuration with other orbital seeds (the evaluation seed is never
+    seen).  Each seed: one solve, then Adam epochs over its pairs."""
+    import torch
+    from paper_1911_10630_amd import synth as S
+    dev = torch.device("cuda:0")
+    ctx.model_init(args.coarsen, seed=5)
+    t0 = time.perf_counter()
+    n_samples, loss, train_s = 0, None, 0.0
+    for k in range(args.train_seeds):
+        wl_k = S.WORKLOADS[args.workload](seed=9001 + k)
+        if args.precision:
+            wl_k.precision = args.precision
+        phi = S.orbitals_torch(wl_k, device=dev)
+        n = ctx.pairs(wl_k.orbitals.centers)
+        ctx.step(phi)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for ep in range(args.train_epochs):
+            loss = ctx.model_train(epochs=1, batch=args.train_batch, lr=args.train_lr, seed=1000 * k + ep)
+            log(f"[bench]   epoch {ep + 1}/{args.train_epochs}: loss {loss:.4g}, {time.perf_counter() - t1:.1f} s")
+        train_s += time.perf_counter() - t1
+        n_samples += n
+        log(f"[bench] trained on seed {9001 + k}: {n} pairs x {args.train_epochs} epochs, loss {loss:.4g}, "
+            f"{time.perf_counter() - t1:.1f} s")
+        del phi
+    return dict(coarsen=args.coarsen, edge=ctx.model_edge(), train_seeds=args.train_seeds,
+                train_pairs=n_samples, epochs=args.train_epochs, batch=args.train_batch, lr=args.train_lr,
+                last_loss=loss, train_s=round(train_s, 1), total_s=round(time.perf_counter() - t0, 1))
+
+
 def md_run(args, wl):
     """Synthetic MD: centres random-walk by N(0, (0.02 A)^2) per component per
     step, orbitals rebuilt, pair list rebuilt, every step solved with the
@@ -72,6 +104,7 @@ def md_run(args, wl):
     orbs = wl.orbitals
     ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols, inner_rtol=args.inner_rtol,
                               guess=args.guess)
+    learned = train_model(args, wl, ctx) if args.guess == "learned" else None
     stream = torch.cuda.current_stream(dev)
     steps = []
     t_all = 0.0
@@ -90,7 +123,8 @@ def md_run(args, wl):
         dt = time.perf_counter() - t0
         st = ctx.stats()
         steps.append(dict(step=k, n_pairs=n, seconds=round(dt, 3), iters_mean=round(st["iters_total"] / n, 2),
-                          outer_mean=round(st["outer_total"] / n, 2), cg_ms=round(st["cg_ms"], 1), E_xx=E))
+                          outer_mean=round(st["outer_total"] / n, 2), cg_ms=round(st["cg_ms"], 1),
+                          guess_ms=round(st["guess_ms"], 1), E_xx=E))
         log(f"[bench] md step {k}: {n} pairs, {dt:.2f} s, mean iterations {st['iters_total'] / n:.1f}, E {E:.12f}")
         if k > 0:                        # step 0 has no history for any guess
             t_all += dt
@@ -103,6 +137,8 @@ def md_run(args, wl):
                 config=dict(workload=wl.name, guess=args.guess, precision=wl.precision,
                             n_orbitals=wl.orbitals.n, grid=list(wl.n_grid)),
                 md=steps)
+    if learned:
+        line["learned"] = learned
     print(json.dumps(line), flush=True)
     ctx.close()
 
@@ -122,7 +158,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--md-steps", type=int, default=0,
                     help="run a synthetic MD trajectory of this many steps instead (initial-guess comparison)")
-    ap.add_argument("--guess", default="zero", choices=["zero", "previous", "extrap"])
+    ap.add_argument("--guess", default="zero", choices=["zero", "previous", "extrap", "learned"])
+    ap.add_argument("--coarsen", type=int, default=2, help="learned guess: grid points per coarse cell edge")
+    ap.add_argument("--train-seeds", type=int, default=2, help="learned guess: training configurations")
+    ap.add_argument("--train-epochs", type=int, default=2)
+    ap.add_argument("--train-batch", type=int, default=8)
+    ap.add_argument("--train-lr", type=float, default=1e-3)
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="(profiling) also run a plain device copy of this many MiB, 3 times, to calibrate "
                          "the FETCH_SIZE / WRITE_SIZE counters")
@@ -155,7 +196,10 @@ def main():
     dev = torch.device("cuda:0")
     log(f"[bench] workload {wl.name}: generating {wl.orbitals.n} orbitals on {dev}")
     phi = S.orbitals_torch(wl, device=dev)
-    ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols, inner_rtol=args.inner_rtol)
+    guess = "learned" if args.guess == "learned" else "zero"
+    ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols, inner_rtol=args.inner_rtol,
+                              guess=guess)
+    learned = train_model(args, wl, ctx) if guess == "learned" else None
     n_pairs = ctx.pairs(wl.orbitals.centers)
     info = ctx.pair_info(results=False)
     dxx = torch.empty_like(phi)
@@ -207,9 +251,14 @@ def main():
                             energy_ms=round(st["energy_ms"], 3), cg_bytes=st["cg_bytes"],
                             dxx_gbs=round(st["dxx_bytes"] / (st["dxx_ms"] * 1e-3) / 1e9, 1) if st["dxx_ms"] > 0 else None,
                             grid=st["solve_grid"], block=st["solve_block"], waves=st["n_waves"],
+                            autotuned_variants=st["tuned"], tune_ms=round(st["tune_ms"], 1),
                             cg_cols=st["cg_cols"], cg_bands=st["cg_bands"], outer_total=st["outer_total"],
                             inner_rtol=args.inner_rtol if wl.precision != "fp64" else None,
                             kernel_hash=kernel_hash()))
+    if learned:
+        line["config"]["guess"] = "learned"
+        learned["guess_ms"] = round(st["guess_ms"], 2)
+        line["learned"] = learned
 
     if not args.no_cpu_baseline:
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)

@@ -78,6 +78,10 @@ typedef struct {
                                -1 = the flat kernel (any sphere size)           */
     int64_t wave_pairs;     /* max pairs per launch wave; 0 = as many as fit    */
     int32_t keep_intermediates; /* 1: keep rho, b per pair for exx_debug_pair   */
+    int32_t autotune;       /* 1 (default): exx_setup times every CG kernel
+                               variant that fits (a few CG iterations on a
+                               synthetic batch) and keeps the fastest;
+                               0: choose by occupancy alone                  */
 } exx_params;
 
 typedef struct {
@@ -105,10 +109,12 @@ typedef struct {
     int32_t n_waves;         /* pair waves of the last solve (1 = one launch)   */
     int32_t guess_pairs;     /* pairs whose CG started from a non-zero guess    */
     double  guess_ms;        /* last solve: guess kernels / model inference     */
+    int32_t tuned;           /* CG variants the set-up autotuner timed (0: none) */
+    double  tune_ms;         /* time of those tuning launches                   */
 } exx_stats_t;
 
 /* Fills *p with the paper's method defaults (n = 3, l_max = 6, FP64, zero
- * guess, cg_rtol 1e-10, cg_max_iter 20000).  Grid, cell and radii are zeroed
+ * guess, cg_rtol 1e-10, cg_max_iter 20000) and autotune = 1.  Grid, cell and radii are zeroed
  * and must be set by the caller. */
 void exx_default_params(exx_params *p);
 
@@ -179,7 +185,9 @@ exx_status exx_model_init(exx_ctx *ctx, int32_t coarsen, uint64_t seed);
  * target its converged potentials on ME.  Needs the last exx_solve to have
  * run in one wave (every right-hand side resident), else EXX_ESTATE.
  * epochs >= 1, 1 <= batch <= n_pairs, lr > 0.  *loss receives the mean
- * masked squared error of the last epoch (normalized units).  Synchronizes
+ * masked squared error of the last epoch (normalized units: potential over
+ * RMS(b) h^2, per coarse cell that meets ME).  epochs = 0 only evaluates
+ * that error over every pair, without updating (lr ignored).  Synchronizes
  * `stream`.  The weight-gradient sums use atomics, so training is not
  * bitwise reproducible; inference is. */
 exx_status exx_model_train(exx_ctx *ctx, int32_t epochs, int32_t batch, double lr, uint64_t seed, double *loss,

@@ -91,9 +91,12 @@ struct exx_ctx {
     // learned guess
     ExxNet *net = nullptr;
     int net_D = 0;           // coarse cube edge for this context's classes
+    DevBuf<unsigned char> d_bnd[2];   // per class: PE points whose stencil leaves PE
     double guess_ms = 0.0;   // last solve: guess kernels or net inference of wave 0
 
     int block = 256, grid = 0, slots = 0, wave_n = 0, n_waves = 0;
+    int tuned = 0;           // variants timed by the autotuner (0: heuristic choice)
+    double tune_ms = 0.0;    // time of the timed tuning launches
     CgVariant var{0, 256, 0, 0, 0, 0, 0};
     size_t lds_bytes = 0;
     long long slot_n = 0;
@@ -385,6 +388,8 @@ NetPairArgs net_args(const exx_ctx *c)
     n.vout = c->d_vout.p;
     n.h2 = std::cbrt(c->h[0] * c->h[1] * c->h[2]);
     n.h2 *= n.h2;
+    n.bnd[0] = c->d_bnd[0].p;
+    n.bnd[1] = c->d_bnd[1].p;
     return n;
 }
 
@@ -463,20 +468,166 @@ size_t zmarch_lds(const HostClass &k, int plane_rows, int plane_rows32)
     return (pny * pnz + 3) / 4 * 4 * sizeof(int) + std::max(p64, p32);
 }
 
-// Chooses the CG kernel: among the z-march variants that fit (and match the
-// requested block / cols), the one with the most resident waves per CU,
-// then the fewest bands; the flat kernel when none fits.
+// Installs variant v: band tables of both classes on the device.
+exx_status install_variant(exx_ctx *c, const CgVariant &v, size_t lds)
+{
+    c->var = v;
+    c->lds_bytes = v.zmarch ? lds : 0;
+    for (auto &k : c->cls) {
+        if (k.d_bands) { (void)hipFree(k.d_bands); k.d_bands = nullptr; }
+        if (k.d_bands32) { (void)hipFree(k.d_bands32); k.d_bands32 = nullptr; }
+        k.bands.clear();
+        k.bands32.clear();
+        k.plane_rows = k.plane_rows32 = 0;
+        if (v.zmarch) {
+            make_bands(k, v.cols, v.halo, v.block, k.bands, &k.plane_rows);
+            HIPCHK(c, hipMalloc((void **)&k.d_bands, k.bands.size() * sizeof(int)));
+            HIPCHK(c, hipMemcpy(k.d_bands, k.bands.data(), k.bands.size() * sizeof(int), hipMemcpyHostToDevice));
+            if (c->prm.precision == EXX_FP32_REFINE) {
+                make_bands(k, v.cols32, v.halo32, v.block, k.bands32, &k.plane_rows32);
+                HIPCHK(c, hipMalloc((void **)&k.d_bands32, k.bands32.size() * sizeof(int)));
+                HIPCHK(c, hipMemcpy(k.d_bands32, k.bands32.data(), k.bands32.size() * sizeof(int),
+                                    hipMemcpyHostToDevice));
+            }
+        }
+    }
+    c->block = v.block;
+    return EXX_OK;
+}
+
+struct Candidate {
+    CgVariant v;
+    size_t lds;
+    int per_cu;
+    long score;
+};
+
+// Measured choice among the candidates: each runs kTuneIters CG iterations
+// on every pair of a synthetic batch (non-self class, constant right-hand
+// side, residual target 0 so no pair stops early; two pairs per resident
+// work-group of the widest grid), after one untimed launch; the fastest
+// wins.  Returns the index of the winner, or -1 (heuristic) when the device
+// cannot hold the batch.
+int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
+{
+    constexpr int kTuneIters = 20;
+    const HostClass &k = c->cls[1];
+    int max_grid = 0;
+    for (const Candidate &q : cands) max_grid = std::max(max_grid, q.per_cu * c->n_cu);
+    const int n = 2 * max_grid;
+    const long long slot_n = ((long long)std::max(c->cls[0].n_pe, c->cls[1].n_pe) + 1 + 63) / 64 * 64;
+    const long long per_pair = (long long)k.n_pe + k.n_sh;
+    const size_t ngrid = (size_t)c->prm.n_grid[0] * c->prm.n_grid[1] * c->prm.n_grid[2];
+    const bool mixed = c->prm.precision == EXX_FP32_REFINE;
+    const size_t need = (size_t)n * (slot_n + per_pair) * 8 + (size_t)max_grid * slot_n * (3 * 8 + (mixed ? 16 : 0)) +
+                        ngrid * 8 + (size_t)n * (NLM * 8 + 64);
+    size_t freeb = 0, totalb = 0;
+    if (hipMemGetInfo(&freeb, &totalb) != hipSuccess || need + ((size_t)2 << 30) > freeb) return -1;
+    std::vector<void *> allocs;
+    auto dev = [&](size_t bytes) -> void * {
+        void *p = nullptr;
+        if (hipMalloc(&p, std::max<size_t>(bytes, 8)) != hipSuccess) return nullptr;
+        allocs.push_back(p);
+        return p;
+    };
+    auto release = [&]() { for (void *p : allocs) (void)hipFree(p); allocs.clear(); };
+    double *phi = (double *)dev(ngrid * 8), *rhs = (double *)dev((size_t)n * slot_n * 8);
+    double *vout = (double *)dev((size_t)n * per_pair * 8), *scr = (double *)dev((size_t)max_grid * 3 * slot_n * 8);
+    float *scr32 = mixed ? (float *)dev((size_t)max_grid * 4 * slot_n * 4) : nullptr;
+    double *q = (double *)dev((size_t)n * NLM * 8), *e = (double *)dev((size_t)n * 8), *rr = (double *)dev((size_t)n * 8);
+    int *it = (int *)dev((size_t)n * 4), *ou = (int *)dev((size_t)n * 4), *cv = (int *)dev((size_t)n * 4);
+    int *counter = (int *)dev(4);
+    int4 *gc = (int4 *)dev((size_t)n * sizeof(int4));
+    int2 *ij = (int2 *)dev((size_t)n * sizeof(int2));
+    long long *off = (long long *)dev((size_t)n * 8);
+    hipEvent_t ev[2] = {};
+    int best = -1;
+    float best_ms = 0.f;
+    if (allocs.size() != (size_t)(mixed ? 15 : 14) || hipEventCreate(&ev[0]) != hipSuccess ||
+        hipEventCreate(&ev[1]) != hipSuccess) {
+        release();
+        for (auto &x : ev) if (x) (void)hipEventDestroy(x);
+        return -1;
+    }
+    std::vector<int4> hgc((size_t)n, int4{0, 0, 0, 1});
+    std::vector<int2> hij((size_t)n, int2{0, 0});
+    std::vector<long long> hoff((size_t)n);
+    for (int p = 0; p < n; ++p) hoff[p] = (long long)p * per_pair;
+    bool ok = hipMemset(phi, 0, ngrid * 8) == hipSuccess &&
+              hipMemset(rhs, 0x3f, (size_t)n * slot_n * 8) == hipSuccess &&    // b = 4.8e-4 everywhere
+              hipMemset(vout, 0, (size_t)n * per_pair * 8) == hipSuccess &&
+              hipMemcpy(gc, hgc.data(), hgc.size() * sizeof(int4), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(ij, hij.data(), hij.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(off, hoff.data(), hoff.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+    SolveArgs a{};
+    a.pair_gc = gc;
+    a.pair_ij = ij;
+    a.out_off = off;
+    a.phi = phi;
+    a.phi_f32 = 0;
+    a.nx = c->prm.n_grid[0];
+    a.ny = c->prm.n_grid[1];
+    a.nz = c->prm.n_grid[2];
+    a.ngrid = (long long)ngrid;
+    a.vout = vout;
+    a.rhs = rhs;
+    a.scratch = scr;
+    a.scratch32 = scr32;
+    a.slot_n = slot_n;
+    a.q_out = q;
+    a.e_out = e;
+    a.iters_out = it;
+    a.outer_out = ou;
+    a.conv_out = cv;
+    a.relres_out = rr;
+    a.counter = counter;
+    a.wave_begin = 0;
+    a.wave_n = n;
+    a.guess = c->prm.guess != EXX_GUESS_ZERO ? 1 : 0;
+    a.precision = c->prm.precision;
+    for (int d = 0; d < 3; ++d) a.h[d] = c->h[d];
+    for (int d = 0; d < 4; ++d) a.wfd[d] = kFD[d];
+    a.tol = 0.0;
+    a.inner_tol = c->prm.inner_rtol;
+    a.maxit = kTuneIters;
+    ylm_norms(a.ylm_norm);
+    for (size_t i = 0; ok && i < cands.size(); ++i) {
+        if (install_variant(c, cands[i].v, cands[i].lds) != EXX_OK) { ok = false; break; }
+        a.cls[0] = class_dev(c->cls[0]);
+        a.cls[1] = class_dev(c->cls[1]);
+        const int grid = std::min(n, cands[i].per_cu * c->n_cu);
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && ok; ++rep) {
+            ok = launch_zero_int(counter, 1, 0) == hipSuccess && hipEventRecord(ev[0], 0) == hipSuccess &&
+                 launch_cg(cands[i].v, a, grid, cands[i].lds, 0) == hipSuccess && hipEventRecord(ev[1], 0) == hipSuccess &&
+                 hipEventSynchronize(ev[1]) == hipSuccess && hipEventElapsedTime(&ms, ev[0], ev[1]) == hipSuccess;
+        }
+        if (ok && (best < 0 || ms < best_ms)) { best = (int)i; best_ms = ms; }
+        *tune_ms += ms;
+    }
+    (void)hipDeviceSynchronize();
+    release();
+    for (auto &x : ev) (void)hipEventDestroy(x);
+    (void)hipGetLastError();
+    return ok ? best : -1;
+}
+
+// Chooses the CG kernel among the z-march variants that fit (and match a
+// requested block / cols): by measurement when params.autotune is set and
+// more than one fits, else the one with the most resident waves per CU, then
+// the most work-groups per CU, then the fewest bands.  The flat kernel when
+// none fits.
 exx_status select_variant(exx_ctx *c)
 {
     CgVariant vs[32];
     const int nv = cg_variants(vs, 32);
-    int best = -1;
-    long best_score = -1;
-    size_t best_lds = 0;
+    std::vector<Candidate> cands;
     std::vector<int> b0, b1;
+    const int mode = cg_mode(c->prm.precision, c->prm.guess != EXX_GUESS_ZERO);
+    bool flat = false;
     for (int i = 0; i < nv; ++i) {
         const CgVariant &v = vs[i];
-        if (c->prm.cg_cols < 0) { if (!v.zmarch) { best = i; break; } continue; }
+        if (c->prm.cg_cols < 0) { if (!v.zmarch) { flat = true; break; } continue; }
         if (!v.zmarch) continue;
         if (c->prm.block_threads && v.block != c->prm.block_threads) continue;
         if (c->prm.cg_cols && v.cols != c->prm.cg_cols) continue;
@@ -492,40 +643,31 @@ exx_status select_variant(exx_ctx *c)
         const size_t lds = std::max(zmarch_lds(c->cls[0], r0, s0), zmarch_lds(c->cls[1], r1, s1));
         if (lds > kMaxLds) continue;
         int per_cu = 0;
-        if (cg_occupancy(v, c->prm.precision, lds, &per_cu) != hipSuccess || per_cu < 1) continue;
+        if (cg_occupancy(v, mode, lds, &per_cu) != hipSuccess || per_cu < 1) continue;
         const int nb = (int)(b0.size() + b1.size()) / 12;
-        // resident waves first, then independent work-groups, then fewer bands
-        const long score = (long)per_cu * v.block / 64 * 1000 + per_cu * 100 - nb;
-        if (score > best_score) { best = i; best_score = score; best_lds = lds; }
+        cands.push_back({v, lds, per_cu, (long)per_cu * v.block / 64 * 1000 + per_cu * 100 - nb});
     }
-    if (best < 0) {
-        if (c->prm.block_threads || c->prm.cg_cols)
+    c->tuned = 0;
+    c->tune_ms = 0.0;
+    if (cands.empty()) {
+        if (!flat && (c->prm.block_threads || c->prm.cg_cols))
             return fail(c, EXX_EINVAL, "no CG kernel variant with block %d and %d columns fits this subdomain",
                         c->prm.block_threads, c->prm.cg_cols);
-        for (int i = 0; i < nv; ++i) if (!vs[i].zmarch) best = i;
+        for (int i = 0; i < nv; ++i)
+            if (!vs[i].zmarch) return install_variant(c, vs[i], 0);
+        return fail(c, EXX_EINVAL, "no CG kernel available");
     }
-    c->var = vs[best];
-    c->lds_bytes = c->var.zmarch ? best_lds : 0;
-    for (auto &k : c->cls) {
-        if (k.d_bands) { (void)hipFree(k.d_bands); k.d_bands = nullptr; }
-        if (k.d_bands32) { (void)hipFree(k.d_bands32); k.d_bands32 = nullptr; }
-        k.bands.clear();
-        k.bands32.clear();
-        k.plane_rows = k.plane_rows32 = 0;
-        if (c->var.zmarch) {
-            make_bands(k, c->var.cols, c->var.halo, c->var.block, k.bands, &k.plane_rows);
-            HIPCHK(c, hipMalloc((void **)&k.d_bands, k.bands.size() * sizeof(int)));
-            HIPCHK(c, hipMemcpy(k.d_bands, k.bands.data(), k.bands.size() * sizeof(int), hipMemcpyHostToDevice));
-            if (c->prm.precision == EXX_FP32_REFINE) {
-                make_bands(k, c->var.cols32, c->var.halo32, c->var.block, k.bands32, &k.plane_rows32);
-                HIPCHK(c, hipMalloc((void **)&k.d_bands32, k.bands32.size() * sizeof(int)));
-                HIPCHK(c, hipMemcpy(k.d_bands32, k.bands32.data(), k.bands32.size() * sizeof(int),
-                                    hipMemcpyHostToDevice));
-            }
-        }
+    int best = -1;
+    if (c->prm.autotune && cands.size() > 1) {
+        best = autotune(c, cands, &c->tune_ms);
+        if (best >= 0) c->tuned = (int)cands.size();
     }
-    c->block = c->var.block;
-    return EXX_OK;
+    if (best < 0) {
+        best = 0;
+        for (size_t i = 1; i < cands.size(); ++i)
+            if (cands[i].score > cands[best].score) best = (int)i;
+    }
+    return install_variant(c, cands[best].v, cands[best].lds);
 }
 
 }  // namespace
@@ -548,6 +690,7 @@ void exx_default_params(exx_params *p)
     p->orbital_dtype = EXX_F64;
     p->guess = EXX_GUESS_ZERO;
     p->inner_rtol = 1e-5;
+    p->autotune = 1;
 }
 
 exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
@@ -690,7 +833,7 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     if ((st = dev_reserve(c, c->d_E, 1)) != EXX_OK) return st;
     // persistent grid and per-slot scratch
     int per_cu = 0;
-    HIPCHK(c, cg_occupancy(c->var, c->prm.precision, c->lds_bytes, &per_cu));
+    HIPCHK(c, cg_occupancy(c->var, cg_mode(c->prm.precision, c->prm.guess != EXX_GUESS_ZERO), c->lds_bytes, &per_cu));
     per_cu = std::max(per_cu, 1);
     c->grid = (int)std::min<int64_t>(c->n_pairs, (int64_t)per_cu * c->n_cu);
     c->grid = std::max(c->grid, 1);
@@ -975,6 +1118,8 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) st->solve_ms = ms;
     st->prep_ms = st->cg_ms = st->guess_ms = -1.0;
     st->guess_pairs = c->guess_pairs;
+    st->tuned = c->tuned;
+    st->tune_ms = c->tune_ms;
     if (c->n_waves == 1) {
         if (hipEventElapsedTime(&ms, c->ev[0], c->ev[6]) == hipSuccess) st->prep_ms = ms;
         if (hipEventElapsedTime(&ms, c->ev[6], c->ev[5]) == hipSuccess) st->guess_ms = ms;
@@ -1043,6 +1188,13 @@ exx_status exx_model_init(exx_ctx *c, int32_t coarsen, uint64_t seed)
     }
     c->net = net;
     c->net_D = net_edge(coarsen, pe_rmax(c));
+    for (int k = 0; k < 2; ++k)
+        if (!c->d_bnd[k].p) {
+            exx_status st = dev_reserve(c, c->d_bnd[k], (size_t)c->cls[k].n_pe);
+            if (st != EXX_OK) return st;
+            HIPCHK(c, net_boundary_flags(class_dev(c->cls[k]), c->d_bnd[k].p, 0));
+        }
+    HIPCHK(c, hipDeviceSynchronize());
     return EXX_OK;
 }
 
@@ -1087,8 +1239,8 @@ exx_status exx_model_train(exx_ctx *c, int32_t epochs, int32_t batch, double lr,
     if (c->n_waves != 1)
         return fail(c, EXX_ESTATE, "exx_model_train needs every right-hand side resident; the last solve ran in %d waves",
                     c->n_waves);
-    if (epochs < 1 || batch < 1 || batch > c->n_pairs || !(lr > 0.0) || !loss)
-        return fail(c, EXX_EINVAL, "exx_model_train: need epochs >= 1, 1 <= batch <= n_pairs, lr > 0, loss");
+    if (epochs < 0 || batch < 1 || batch > c->n_pairs || !(lr > 0.0 || epochs == 0) || !loss)
+        return fail(c, EXX_EINVAL, "exx_model_train: need epochs >= 0, 1 <= batch <= n_pairs, lr > 0, loss");
     HIPCHK(c, hipSetDevice(c->device));
     std::vector<int> pairs((size_t)c->n_pairs);
     for (int64_t p = 0; p < c->n_pairs; ++p) pairs[p] = (int)p;
@@ -1141,6 +1293,7 @@ void exx_destroy(exx_ctx *c)
     dev_free(c->d_guess); dev_free(c->d_hist_off);
     for (auto &h : c->hist) dev_free(h.v);
     net_destroy(c->net);
+    dev_free(c->d_bnd[0]); dev_free(c->d_bnd[1]);
     dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_outer); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
     if (c->have_events)
         for (auto &e : c->ev)

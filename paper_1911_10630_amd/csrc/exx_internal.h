@@ -155,7 +155,10 @@ struct CgVariant {
     int wpe;      // minimum resident waves per SIMD the kernel is compiled for
 };
 int cg_variants(CgVariant *out, int max_n);
-hipError_t cg_occupancy(const CgVariant &v, int mixed, size_t lds_bytes, int *blocks_per_cu);
+// Kernel mode for a precision (EXX_FP64 / EXX_FP32_REFINE) and whether CG
+// starts from a guess in vout.
+int cg_mode(int precision, int guess);
+hipError_t cg_occupancy(const CgVariant &v, int mode, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t lds_bytes, hipStream_t s);
 hipError_t launch_dxx(const DxxArgs &a, int n_orb, hipStream_t s);
 hipError_t launch_energy(const double *e, const int2 *ij, int n_pairs, double *out, hipStream_t s);
@@ -176,6 +179,7 @@ struct NetPairArgs {
     int wave_begin;
     double *vout;               // read (training targets) or written (guess)
     double h2;                  // output scale: RMS(v) ~ RMS(b) h^2
+    const unsigned char *bnd[2];// per class, per PE point: 1 if the stencil leaves PE
 };
 
 struct ExxNet;
@@ -185,6 +189,8 @@ void net_destroy(ExxNet *net);
 int net_coarsen(const ExxNet *net);
 // Coarse edge for PE offsets |o| <= r_max: f D / 2 >= r_max + 1, D a multiple of 8.
 int net_edge(int f, int r_max);
+// flag[q] = 1 for PE points whose stencil leaves PE (n_pe bytes).
+hipError_t net_boundary_flags(const ClassDev &g, unsigned char *flag, hipStream_t s);
 // Device bytes of the activation buffers for `batch` samples of edge D
 // (training adds the gradient buffers).
 size_t net_buffer_bytes(int batch, int D, bool training);

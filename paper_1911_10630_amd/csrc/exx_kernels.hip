@@ -720,11 +720,17 @@ struct PFin {
     }
 };
 
+// Kernel modes: FP64 CG from zero, FP64 CG from the guess in vout (one more
+// pass type, so more registers), FP32 CG with FP64 reliable updates (guess
+// read at run time).
+enum { CG_FP64 = 0, CG_FP64_GUESS = 1, CG_MIXED = 2 };
+
 // One pair: FP64 CG, or FP32 CG with FP64 iterative refinement.
-template <int T, int K, int KH, int K32, int KH32, bool MIXED>
+template <int T, int K, int KH, int K32, int KH32, int MODE>
 __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, long long slot, double *lds, double *red,
                                                int &par)
 {
+    constexpr bool MIXED = MODE == CG_MIXED;
     const int tid = threadIdx.x;
     const int4 pg = a.pair_gc[pair];
     const int2 ij = a.pair_ij[pair];
@@ -732,7 +738,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     double *x = a.vout + a.out_off[pair];
     const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
     const StencilW<double> w64 = stencil_w<double>(a);
-    const bool guess = a.guess != 0;
+    const bool guess = MIXED ? a.guess != 0 : MODE == CG_FP64_GUESS;
     int it = 0, conv = 0, outer = 0;
     double bb = 0.0;
 
@@ -741,7 +747,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         double *pold = r + a.slot_n, *pnew = pold + a.slot_n;
         const double *rsrc = b;
         double rr = 0.0, pap = 0.0;
-        if (guess) {
+        if constexpr (MODE == CG_FP64_GUESS) {
             PRes<K, KH, double, double> pr{x, x, b, r, r + a.slot_n - 1, false, 0.0};
             zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
             ++outer;
@@ -873,7 +879,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     __syncthreads();
 }
 
-template <int T, int K, int KH, int K32, int KH32, int WPE, bool MIXED>
+template <int T, int K, int KH, int K32, int KH32, int WPE, int MODE>
 __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
 {
     extern __shared__ double lds_dyn[];
@@ -896,7 +902,7 @@ __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
             __syncthreads();
             last_cls = cls;
         }
-        cg_zmarch_pair<T, K, KH, K32, KH32, MIXED>(a, a.wave_begin + k, blockIdx.x, lds_dyn, red, par);
+        cg_zmarch_pair<T, K, KH, K32, KH32, MODE>(a, a.wave_begin + k, blockIdx.x, lds_dyn, red, par);
     }
 }
 
@@ -1050,7 +1056,7 @@ int cg_variants(CgVariant *out, int max_n)
     return n;
 }
 
-template <int T, int K, int KH, int K32, int KH32, int W, bool M>
+template <int T, int K, int KH, int K32, int KH32, int W, int M>
 static hipError_t zm_occ(size_t lds, int *per_cu)
 {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cg_zmarch<T, K, KH, K32, KH32, W, M>),
@@ -1062,13 +1068,16 @@ static hipError_t zm_occ(size_t lds, int *per_cu)
 #define EXX_MATCH(v, T, K, KH, K32, KH32, W) \
     ((v).block == T && (v).cols == K && (v).halo == KH && (v).cols32 == K32 && (v).halo32 == KH32 && (v).wpe == W)
 
-hipError_t cg_occupancy(const CgVariant &v, int mixed, size_t lds, int *blocks_per_cu)
+int cg_mode(int precision, int guess) { return precision ? CG_MIXED : guess ? CG_FP64_GUESS : CG_FP64; }
+
+hipError_t cg_occupancy(const CgVariant &v, int mode, size_t lds, int *blocks_per_cu)
 {
     if (!v.zmarch) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_solve<256>, 256, 0);
 #define EXX_V(T, K, KH, K32, KH32, W)                                                           \
     if (EXX_MATCH(v, T, K, KH, K32, KH32, W))                                                    \
-        return mixed ? zm_occ<T, K, KH, K32, KH32, W, true>(lds, blocks_per_cu)                  \
-                     : zm_occ<T, K, KH, K32, KH32, W, false>(lds, blocks_per_cu);
+        return mode == CG_MIXED        ? zm_occ<T, K, KH, K32, KH32, W, CG_MIXED>(lds, blocks_per_cu)      \
+               : mode == CG_FP64_GUESS ? zm_occ<T, K, KH, K32, KH32, W, CG_FP64_GUESS>(lds, blocks_per_cu) \
+                                       : zm_occ<T, K, KH, K32, KH32, W, CG_FP64>(lds, blocks_per_cu);
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V
     return hipErrorInvalidValue;
@@ -1083,9 +1092,12 @@ hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t ld
 #define EXX_V(T, K, KH, K32, KH32, W)                                                                          \
     if (EXX_MATCH(v, T, K, KH, K32, KH32, W)) {                                                                 \
         if (a.precision)                                                                                        \
-            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, true>), dim3(grid), dim3(T), lds, s, a);    \
+            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_MIXED>), dim3(grid), dim3(T), lds, s, a); \
+        else if (a.guess)                                                                                       \
+            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_FP64_GUESS>), dim3(grid), dim3(T), lds, s, \
+                               a);                                                                              \
         else                                                                                                    \
-            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, false>), dim3(grid), dim3(T), lds, s, a);   \
+            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_FP64>), dim3(grid), dim3(T), lds, s, a);  \
         return hipGetLastError();                                                                               \
     }
     EXX_ZM_VARIANTS(EXX_V)

@@ -52,48 +52,81 @@ __device__ __forceinline__ float bf2f(bf16_t b) { return __uint_as_float(((unsig
 
 // Y[v][co] = sum_tap sum_ci X[v + off(tap)][ci] W[tap][co][ci], off(tap) =
 // (tap % 3, tap / 3 % 3, tap / 9) - 1 in (x, y, z).  N samples of D^3 voxels.
-// grid (ceil(N D^3 / 64), Cout / 16), 256 threads: 4 waves x 16 voxels, each
-// wave one 16 x 16 output tile.
-template <bool RELU, bool OUT_F32>
+// grid ceil(N D^3 / (64 MV)), 256 threads.  Each wave computes MV tiles of
+// 16 voxels times all NCO = Cout / 16 channel tiles: an input fragment
+// feeds NCO MFMAs and a weight fragment MV MFMAs.
+template <int MV, int NCO, bool RELU, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv3(const bf16_t *__restrict__ X, const bf16_t *__restrict__ W, void *Yv,
-                                               int N, int D, int Cin, int Cout)
+                                               int N, int D, int Cin)
 {
+    constexpr int Cout = 16 * NCO;
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int m = lane & 15, kq = lane >> 4;
     const int D3 = D * D * D, nvox = N * D3;
-    const int v0 = blockIdx.x * 64 + wv * 16;
-    const int co_base = blockIdx.y * 16;
-    const int va = v0 + m;
-    const bool aval = va < nvox;
-    const int vs = aval ? va : 0;
-    const int n = vs / D3, r = vs - n * D3;
-    const int z = r / (D * D), y = (r / D) % D, x = r % D;
-    f4_t acc = {0.f, 0.f, 0.f, 0.f};
+    const int v0 = (blockIdx.x * 4 + wv) * 16 * MV;
+    int n[MV], z[MV], y[MV], x[MV];
+    bool aval[MV];
+#pragma unroll
+    for (int u = 0; u < MV; ++u) {
+        const int va = v0 + 16 * u + m;
+        aval[u] = va < nvox;
+        const int vs = aval[u] ? va : 0;
+        n[u] = vs / D3;
+        const int r = vs - n[u] * D3;
+        z[u] = r / (D * D);
+        y[u] = (r / D) % D;
+        x[u] = r % D;
+    }
+    f4_t acc[MV][NCO];
+#pragma unroll
+    for (int u = 0; u < MV; ++u)
+#pragma unroll
+        for (int t = 0; t < NCO; ++t) acc[u][t] = (f4_t){0.f, 0.f, 0.f, 0.f};
     for (int tap = 0; tap < 27; ++tap) {
-        const int zz = z + tap / 9 - 1, yy = y + (tap / 3) % 3 - 1, xx = x + tap % 3 - 1;
-        const bool ok = aval && (unsigned)zz < (unsigned)D && (unsigned)yy < (unsigned)D && (unsigned)xx < (unsigned)D;
-        const long long vn = ok ? (long long)n * D3 + (zz * D + yy) * D + xx : 0;
-        const bf16_t *xp = X + vn * Cin + 4 * kq;
-        const bf16_t *wp = W + ((long long)tap * Cout + co_base + m) * Cin + 4 * kq;
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        const bf16_t *xp[MV];
+        bool ok[MV];
+#pragma unroll
+        for (int u = 0; u < MV; ++u) {
+            const int zz = z[u] + dz, yy = y[u] + dy, xx = x[u] + dx;
+            ok[u] = aval[u] && (unsigned)zz < (unsigned)D && (unsigned)yy < (unsigned)D && (unsigned)xx < (unsigned)D;
+            const long long vn = ok[u] ? (long long)n[u] * D3 + (zz * D + yy) * D + xx : 0;
+            xp[u] = X + vn * Cin + 4 * kq;
+        }
+        const bf16_t *wp = W + ((long long)tap * Cout + m) * Cin + 4 * kq;
         for (int cb = 0; cb < Cin; cb += 16) {
-            s4_t a = *reinterpret_cast<const s4_t *>(xp + cb);
-            const s4_t b = *reinterpret_cast<const s4_t *>(wp + cb);
-            if (!ok) a = (s4_t){0, 0, 0, 0};
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+            s4_t a[MV];
+#pragma unroll
+            for (int u = 0; u < MV; ++u) {
+                a[u] = *reinterpret_cast<const s4_t *>(xp[u] + cb);
+                if (!ok[u]) a[u] = (s4_t){0, 0, 0, 0};
+            }
+#pragma unroll
+            for (int t = 0; t < NCO; ++t) {
+                const s4_t b = *reinterpret_cast<const s4_t *>(wp + (long long)t * 16 * Cin + cb);
+#pragma unroll
+                for (int u = 0; u < MV; ++u)
+                    acc[u][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[u], b, acc[u][t], 0, 0, 0);
+            }
         }
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const int v = v0 + 4 * kq + i;
-        if (v >= nvox) continue;
-        float val = acc[i];
-        if (RELU) val = fmaxf(val, 0.f);
-        const long long o = (long long)v * Cout + co_base + m;
-        if (OUT_F32)
-            static_cast<float *>(Yv)[o] = val;
-        else
-            static_cast<bf16_t *>(Yv)[o] = f2bf(val);
-    }
+    for (int u = 0; u < MV; ++u)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int v = v0 + 16 * u + 4 * kq + i;
+            if (v >= nvox) continue;
+#pragma unroll
+            for (int t = 0; t < NCO; ++t) {
+                float val = acc[u][t][i];
+                if (RELU) val = fmaxf(val, 0.f);
+                const long long o = (long long)v * Cout + t * 16 + m;
+                if (OUT_F32)
+                    static_cast<float *>(Yv)[o] = val;
+                else
+                    static_cast<bf16_t *>(Yv)[o] = f2bf(val);
+            }
+        }
 }
 
 // dW[tap][co][ci] += sum_v dY[v][co] X[v + off(tap)][ci].
@@ -299,120 +332,155 @@ __global__ void k_adam(float *w, float *m, float *v, float *g, bf16_t *w16, bf16
 
 __device__ __forceinline__ int pair_of(const int *pairs, int base, int k) { return pairs ? pairs[k] : base + k; }
 
-// In ME (PE or shell): the potential there (PE from x, shell from x + n_pe).
-__device__ __forceinline__ bool me_value(const ClassDev &g, const double *x, int ox, int oy, int oz, double &v)
+// flag[q] = 1 if the stencil of PE point q reaches outside PE (b carries the
+// Dirichlet term there).  PE is convex, so the six far ends decide.
+__global__ void k_pe_boundary(ClassDev g, unsigned char *flag)
 {
-    const int q = pe_index(g, ox, oy, oz);
-    if (q >= 0) { v = x[q]; return true; }
-    const int zz = oz - g.mzlo, yy = oy - g.mylo;
-    if ((unsigned)zz >= (unsigned)g.mnz || (unsigned)yy >= (unsigned)g.mny) return false;
-    const int4 rb = g.me_rows[2 * (zz * g.mny + yy) + 1];
-    if (ox < rb.x || ox > rb.y) return false;
-    v = x[g.n_pe + sh_index(g, ox, oy, oz)];
-    return true;
+    GRID_STRIDE(q, g.n_pe)
+    {
+        int ox, oy, oz;
+        unpack_xyz(g.pe_xyz[q], ox, oy, oz);
+        const bool inner = pe_index(g, ox - FD_N, oy, oz) >= 0 && pe_index(g, ox + FD_N, oy, oz) >= 0 &&
+                           pe_index(g, ox, oy - FD_N, oz) >= 0 && pe_index(g, ox, oy + FD_N, oz) >= 0 &&
+                           pe_index(g, ox, oy, oz - FD_N) >= 0 && pe_index(g, ox, oy, oz + FD_N) >= 0;
+        flag[q] = inner ? 0 : 1;
+    }
 }
 
-// One work-group per sample.  s = RMS of b on PE (FP64).  Input channels,
-// each a mean over the cell's f^3 fine offsets: 0 = b / s at PE points whose
-// stencil stays in PE, 1 = b / s at PE points next to the boundary (b holds
-// the Dirichlet term there), 2 = fraction of the cell in PE; 3..15 zero.
-// Training target (tgt != NULL): mean of v / (s h^2) over the cell's points
-// in ME, weight 1 where the cell meets ME, else 0.
-__global__ __launch_bounds__(256) void k_net_input(NetPairArgs a, const int *pairs, int base, int D, int f, bf16_t *in,
-                                                   float2 *tgt, double *scale)
+// Sum of b^2 over PE, in fixed-order partial sums: grid (kScaleChunks,
+// samples); chunk j of sample k covers q = j * 256 + t (mod stride).
+constexpr int kScaleChunks = 64;
+__global__ __launch_bounds__(256) void k_net_sumsq(NetPairArgs a, const int *pairs, int base, double *part)
 {
     __shared__ double red[4];
-    const int pair = pair_of(pairs, base, blockIdx.x);
-    const int4 pg = a.pair_gc[pair];
-    const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
+    const int k = blockIdx.y;
+    const int pair = pair_of(pairs, base, k);
+    const ClassDev &g = a.pair_gc[pair].w ? a.cls[1] : a.cls[0];
     const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
-    const double *x = a.vout + a.out_off[pair];
     double ss = 0.0;
-    for (int q = threadIdx.x; q < g.n_pe; q += 256) ss += b[q] * b[q];
+    for (int q = blockIdx.x * 256 + threadIdx.x; q < g.n_pe; q += kScaleChunks * 256) ss += b[q] * b[q];
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = ss;
     __syncthreads();
-    const double tot = red[0] + red[1] + red[2] + red[3];
-    const double s = tot > 0.0 ? sqrt(tot / (double)g.n_pe) : 0.0;
+    if (threadIdx.x == 0) part[k * kScaleChunks + blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+// scale[k] = RMS of b over PE for sample k (FP64), from the partial sums.
+__global__ void k_net_scale(NetPairArgs a, const int *pairs, int base, int nb, const double *part, double *scale)
+{
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nb) return;
+    const int pair = pair_of(pairs, base, k);
+    const ClassDev &g = a.pair_gc[pair].w ? a.cls[1] : a.cls[0];
+    double tot = 0.0;
+    for (int j = 0; j < kScaleChunks; ++j) tot += part[k * kScaleChunks + j];
+    scale[k] = tot > 0.0 ? sqrt(tot / (double)g.n_pe) : 0.0;
+}
+
+// One thread per coarse cell: grid (ceil(D^3 / 256), samples).  Input
+// channels, each a mean over the cell's f^3 fine offsets: 0 = b / s at PE
+// points whose stencil stays in PE, 1 = b / s at PE points next to the
+// boundary, 2 = fraction of the cell in PE; 3..15 zero.  Training target
+// (tgt != NULL): mean of v / (s h^2) over the cell's points in ME (PE values
+// from x, shell values from x + n_pe), weight 1 where the cell meets ME.
+// The cell's points are walked row by row: f^2 (y, z) rows of f points.
+__global__ __launch_bounds__(256) void k_net_cells(NetPairArgs a, const int *pairs, int base, int D, int f, bf16_t *in,
+                                                   float2 *tgt, const double *scale)
+{
+    const int D3 = D * D * D;
+    const int c = blockIdx.x * 256 + threadIdx.x;
+    if (c >= D3) return;
+    const int k = blockIdx.y;
+    const int pair = pair_of(pairs, base, k);
+    const int cls = a.pair_gc[pair].w;
+    const ClassDev &g = cls ? a.cls[1] : a.cls[0];
+    const unsigned char *bnd = a.bnd[cls];
+    const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
+    const double *x = a.vout + a.out_off[pair];
+    const double s = scale[k];
     const double inv = s > 0.0 ? 1.0 / s : 0.0;
     const double invx = s > 0.0 ? 1.0 / (s * a.h2) : 0.0;
-    if (threadIdx.x == 0) scale[blockIdx.x] = s;
-    const int D3 = D * D * D, half = f * D / 2;
-    const double invf3 = 1.0 / (double)(f * f * f);
-    bf16_t *ip = in + (long long)blockIdx.x * D3 * 16;
-    float2 *tp = tgt ? tgt + (long long)blockIdx.x * D3 : nullptr;
-    for (int c = threadIdx.x; c < D3; c += 256) {
-        const int cx = c % D, cy = (c / D) % D, cz = c / (D * D);
-        double s_in = 0.0, s_bd = 0.0, s_x = 0.0;
-        int n_pe = 0, n_me = 0;
-        for (int k = 0; k < f * f * f; ++k) {
-            const int ox = -half + f * cx + k % f, oy = -half + f * cy + (k / f) % f, oz = -half + f * cz + k / (f * f);
-            const int q = pe_index(g, ox, oy, oz);
-            if (q >= 0) {
+    const int half = f * D / 2;
+    const int cx = c % D, cy = (c / D) % D, cz = c / (D * D);
+    const int x0 = -half + f * cx, y0 = -half + f * cy, z0 = -half + f * cz;
+    double s_in = 0.0, s_bd = 0.0, s_x = 0.0;
+    int n_pe = 0, n_me = 0;
+    for (int r = 0; r < f * f; ++r) {
+        const int oy = y0 + r % f, oz = z0 + r / f;
+        const int pz = oz - g.pzlo, py = oy - g.pylo;
+        if ((unsigned)pz < (unsigned)g.pnz && (unsigned)py < (unsigned)g.pny) {
+            const int4 row = g.pe_rows[pz * g.pny + py];     // {base, xlo, xhi}
+            const int lo = max(x0, row.y), hi = min(x0 + f - 1, row.z);
+            for (int ox = lo; ox <= hi; ++ox) {
+                const int q = row.x + ox - row.y;
+                (bnd[q] ? s_bd : s_in) += b[q];
                 ++n_pe;
-                // PE is convex: the stencil stays in PE iff its six far ends do
-                const bool inner = pe_index(g, ox - FD_N, oy, oz) >= 0 && pe_index(g, ox + FD_N, oy, oz) >= 0 &&
-                                   pe_index(g, ox, oy - FD_N, oz) >= 0 && pe_index(g, ox, oy + FD_N, oz) >= 0 &&
-                                   pe_index(g, ox, oy, oz - FD_N) >= 0 && pe_index(g, ox, oy, oz + FD_N) >= 0;
-                (inner ? s_in : s_bd) += b[q];
             }
-            if (tp) {
-                double v;
-                if (me_value(g, x, ox, oy, oz, v)) {
-                    s_x += v;
+        }
+        if (tgt) {
+            const int mz = oz - g.mzlo, my = oy - g.mylo;
+            if ((unsigned)mz < (unsigned)g.mnz && (unsigned)my < (unsigned)g.mny) {
+                const int4 ra = g.me_rows[2 * (mz * g.mny + my)];       // {pe_base, plo, phi, sh_base}
+                const int4 rb = g.me_rows[2 * (mz * g.mny + my) + 1];   // {mlo, mhi}
+                const int lo = max(x0, rb.x), hi = min(x0 + f - 1, rb.y);
+                for (int ox = lo; ox <= hi; ++ox) {
+                    const long long idx = (ox >= ra.y && ox <= ra.z)
+                                              ? (long long)ra.x + ox - ra.y
+                                              : (long long)g.n_pe + ra.w + (ox < ra.y ? ox - rb.x : (ra.y - rb.x) + (ox - ra.z - 1));
+                    s_x += x[idx];
                     ++n_me;
                 }
             }
         }
-        bf16_t *cell = ip + (long long)c * 16;
-        cell[0] = f2bf((float)(s_in * inv * invf3));
-        cell[1] = f2bf((float)(s_bd * inv * invf3));
-        cell[2] = f2bf((float)(n_pe * invf3));
-#pragma unroll
-        for (int ch = 3; ch < 16; ++ch) cell[ch] = 0;
-        if (tp) tp[c] = n_me ? make_float2((float)(s_x * invx / n_me), 1.f) : make_float2(0.f, 0.f);
     }
+    const double invf3 = 1.0 / (double)(f * f * f);
+    bf16_t *cell = in + ((long long)k * D3 + c) * 16;
+    cell[0] = f2bf((float)(s_in * inv * invf3));
+    cell[1] = f2bf((float)(s_bd * inv * invf3));
+    cell[2] = f2bf((float)(n_pe * invf3));
+#pragma unroll
+    for (int ch = 3; ch < 16; ++ch) cell[ch] = 0;
+    if (tgt) tgt[(long long)k * D3 + c] = n_me ? make_float2((float)(s_x * invx / n_me), 1.f) : make_float2(0.f, 0.f);
 }
 
-// One work-group per sample: v(o) = s h^2 trilinear(out[.][0]) at each PE
-// point o (cell centres as nodes, clamped at the cube faces).  A non-finite
-// value (a diverged or corrupt model) becomes 0, so CG always starts from a
-// finite guess.
+// One thread per PE point: grid (ceil(max n_pe / 256), samples).
+// v(o) = s h^2 trilinear(out[.][0]) at PE point o (cell centres as nodes,
+// clamped at the cube faces).  A non-finite value (a diverged or corrupt
+// model) becomes 0, so CG always starts from a finite guess.
 __global__ __launch_bounds__(256) void k_net_output(NetPairArgs a, int base, int D, int f, const float *out,
                                                     const double *scale)
 {
-    const int pair = base + blockIdx.x;
-    const int4 pg = a.pair_gc[pair];
-    const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
+    const int k = blockIdx.y;
+    const int pair = base + k;
+    const ClassDev &g = a.pair_gc[pair].w ? a.cls[1] : a.cls[0];
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= g.n_pe) return;
     double *x = a.vout + a.out_off[pair];
-    const double sc = scale[blockIdx.x] * a.h2;
-    const int D3 = D * D * D;
-    const float *op = out + (long long)blockIdx.x * D3 * 16;
+    const double sc = scale[k] * a.h2;
+    const float *op = out + (long long)k * D * D * D * 16;
     const float half = 0.5f * f * D, c0 = 0.5f * (f - 1), invf = 1.f / f;
-    for (int q = threadIdx.x; q < g.n_pe; q += 256) {
-        int ox, oy, oz;
-        unpack_xyz(g.pe_xyz[q], ox, oy, oz);
-        const float u[3] = {(ox + half - c0) * invf, (oy + half - c0) * invf, (oz + half - c0) * invf};
-        int i0[3], i1[3];
-        float t[3];
+    int ox, oy, oz;
+    unpack_xyz(g.pe_xyz[q], ox, oy, oz);
+    const float u[3] = {(ox + half - c0) * invf, (oy + half - c0) * invf, (oz + half - c0) * invf};
+    int i0[3], i1[3];
+    float t[3];
 #pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            const float fl = floorf(u[d]);
-            t[d] = u[d] - fl;
-            const int lo = (int)fl;
-            i0[d] = min(max(lo, 0), D - 1);
-            i1[d] = min(max(lo + 1, 0), D - 1);
-        }
-        float v = 0.f;
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const int xx = (k & 1) ? i1[0] : i0[0], yy = (k & 2) ? i1[1] : i0[1], zz = (k & 4) ? i1[2] : i0[2];
-            const float wgt = ((k & 1) ? t[0] : 1.f - t[0]) * ((k & 2) ? t[1] : 1.f - t[1]) * ((k & 4) ? t[2] : 1.f - t[2]);
-            v += wgt * op[((long long)(zz * D + yy) * D + xx) * 16];
-        }
-        const double val = sc * (double)v;
-        x[q] = isfinite(val) ? val : 0.0;
+    for (int d = 0; d < 3; ++d) {
+        const float fl = floorf(u[d]);
+        t[d] = u[d] - fl;
+        const int lo = (int)fl;
+        i0[d] = min(max(lo, 0), D - 1);
+        i1[d] = min(max(lo + 1, 0), D - 1);
     }
+    float v = 0.f;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+        const int xx = (j & 1) ? i1[0] : i0[0], yy = (j & 2) ? i1[1] : i0[1], zz = (j & 4) ? i1[2] : i0[2];
+        const float wgt = ((j & 1) ? t[0] : 1.f - t[0]) * ((j & 2) ? t[1] : 1.f - t[1]) * ((j & 4) ? t[2] : 1.f - t[2]);
+        v += wgt * op[((long long)(zz * D + yy) * D + xx) * 16];
+    }
+    const double val = sc * (double)v;
+    x[q] = isfinite(val) ? val : 0.0;
 }
 
 // ---------------------------------------------------------------------------
@@ -451,7 +519,7 @@ struct ExxNet {
     bf16_t *act[NROLE] = {}, *grad[NROLE] = {};
     float *out = nullptr, *acc = nullptr;
     float2 *tgt = nullptr;
-    double *scale = nullptr;
+    double *scale = nullptr, *part = nullptr;
     int *pairs = nullptr;
     int pairs_cap = 0;
     hipEvent_t ev[2] = {};
@@ -488,8 +556,9 @@ static void free_buffers(ExxNet *net)
     for (auto *arr : {net->act, net->grad})
         for (int r = 0; r < NROLE; ++r)
             if (arr[r]) { (void)hipFree(arr[r]); arr[r] = nullptr; }
-    for (void *p : {(void *)net->out, (void *)net->tgt, (void *)net->scale, (void *)net->acc})
+    for (void *p : {(void *)net->out, (void *)net->tgt, (void *)net->scale, (void *)net->part, (void *)net->acc})
         if (p) (void)hipFree(p);
+    net->part = nullptr;
     net->out = nullptr;
     net->tgt = nullptr;
     net->scale = nullptr;
@@ -512,6 +581,7 @@ static hipError_t net_alloc(ExxNet *net, int batch, int D, bool training)
     if ((e = hipMalloc(&net->out, (size_t)v1 * 16 * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc(&net->tgt, (size_t)v1 * sizeof(float2))) != hipSuccess) return e;
     if ((e = hipMalloc(&net->scale, (size_t)batch * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc(&net->part, (size_t)batch * kScaleChunks * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc(&net->acc, 2 * sizeof(float))) != hipSuccess) return e;
     net->cap = batch;
     net->capD = D;
@@ -580,13 +650,22 @@ static void conv(ExxNet *net, int l, const bf16_t *X, void *Y, int N, int D, boo
     const int cin = transposed ? ly.cout : ly.cin, cout = transposed ? ly.cin : ly.cout;
     const bf16_t *W = transposed ? ly.wt16 : ly.w16;
     const long long nvox = (long long)N * D * D * D;
-    const dim3 grid((unsigned)((nvox + 63) / 64), (unsigned)(cout / 16));
-    if (f32)
-        hipLaunchKernelGGL((k_conv3<false, true>), grid, dim3(256), 0, s, X, W, Y, N, D, cin, cout);
-    else if (relu)
-        hipLaunchKernelGGL((k_conv3<true, false>), grid, dim3(256), 0, s, X, W, Y, N, D, cin, cout);
-    else
-        hipLaunchKernelGGL((k_conv3<false, false>), grid, dim3(256), 0, s, X, W, Y, N, D, cin, cout);
+    // voxel tiles per wave: enough MFMAs per loaded fragment at few channels
+    switch (cout / 16 * 4 + (f32 ? 2 : 0) + (relu ? 1 : 0)) {
+#define EXX_CONV_CASE(NCO, RELU, F32)                                                                       \
+    case NCO * 4 + (F32 ? 2 : 0) + (RELU ? 1 : 0): {                                                        \
+        constexpr int MV = NCO == 1 ? 4 : NCO == 2 ? 2 : 1;                                                 \
+        const dim3 grid((unsigned)((nvox + 64 * MV - 1) / (64 * MV)));                                      \
+        hipLaunchKernelGGL((k_conv3<MV, NCO, RELU, F32>), grid, dim3(256), 0, s, X, W, Y, N, D, cin);        \
+        break;                                                                                              \
+    }
+#define EXX_CONV_CASES(NCO) EXX_CONV_CASE(NCO, false, false) EXX_CONV_CASE(NCO, true, false) EXX_CONV_CASE(NCO, false, true)
+        // every channel count of the layers and of their transposes (16 .. 128)
+        EXX_CONV_CASES(1) EXX_CONV_CASES(2) EXX_CONV_CASES(3) EXX_CONV_CASES(4) EXX_CONV_CASES(6) EXX_CONV_CASES(8)
+#undef EXX_CONV_CASES
+#undef EXX_CONV_CASE
+        default: break;
+    }
 }
 
 static void wgrad(const ExxNet::Layer &ly, const bf16_t *X, const bf16_t *dY, float *dW, int N, int D, hipStream_t s)
@@ -696,6 +775,23 @@ static void backward(ExxNet *net, int N, int D, hipStream_t s)
     W(0, a[IN], g[E1A], D);
 }
 
+static void net_input(ExxNet *net, const NetPairArgs &a, const int *pairs, int base, int nb, int D, bool target,
+                      hipStream_t s)
+{
+    hipLaunchKernelGGL(k_net_sumsq, dim3((unsigned)kScaleChunks, (unsigned)nb), dim3(256), 0, s, a, pairs, base, net->part);
+    hipLaunchKernelGGL(k_net_scale, dim3((unsigned)((nb + 63) / 64)), dim3(64), 0, s, a, pairs, base, nb,
+                       (const double *)net->part, net->scale);
+    const dim3 grid((unsigned)((D * D * D + 255) / 256), (unsigned)nb);
+    hipLaunchKernelGGL(k_net_cells, grid, dim3(256), 0, s, a, pairs, base, D, net->f, net->act[IN],
+                       target ? net->tgt : (float2 *)nullptr, (const double *)net->scale);
+}
+
+hipError_t net_boundary_flags(const ClassDev &g, unsigned char *flag, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pe_boundary, dim3(grid_for(g.n_pe)), dim3(256), 0, s, g, flag);
+    return hipGetLastError();
+}
+
 static int infer_batch(int D)
 {
     // about 1 GiB of activations
@@ -712,10 +808,11 @@ hipError_t net_infer(ExxNet *net, const NetPairArgs &a, int n, int D, double *ms
     for (int b0 = 0; b0 < n; b0 += B) {
         const int nb = std::min(B, n - b0);
         const int base = a.wave_begin + b0;
-        hipLaunchKernelGGL(k_net_input, dim3(nb), dim3(256), 0, s, a, (const int *)nullptr, base, D, net->f, net->act[IN],
-                           (float2 *)nullptr, net->scale);
+        net_input(net, a, nullptr, base, nb, D, false, s);
         forward(net, nb, D, s);
-        hipLaunchKernelGGL(k_net_output, dim3(nb), dim3(256), 0, s, a, base, D, net->f, net->out, net->scale);
+        const int npe = std::max(a.cls[0].n_pe, a.cls[1].n_pe);
+        hipLaunchKernelGGL(k_net_output, dim3((unsigned)((npe + 255) / 256), (unsigned)nb), dim3(256), 0, s, a, base, D,
+                           net->f, net->out, net->scale);
     }
     if ((e = hipEventRecord(net->ev[1], s)) != hipSuccess) return e;
     if (ms) {
@@ -743,6 +840,33 @@ hipError_t net_train(ExxNet *net, const NetPairArgs &a, const int *pairs, int n_
     const float b1 = 0.9f, b2 = 0.999f;
     double last = 0.0;
     std::vector<float> accs;
+    if (epochs == 0) {
+        // evaluation only: the masked squared error over every pair, no update
+        if ((e = hipMemcpyAsync(net->pairs, order.data(), (size_t)n_pairs * sizeof(int), hipMemcpyHostToDevice, s)) !=
+            hipSuccess)
+            return e;
+        const int nbat = (n_pairs + batch - 1) / batch;
+        accs.assign((size_t)2 * nbat, 0.f);
+        for (int bi = 0; bi < nbat; ++bi) {
+            const int nb = std::min(batch, n_pairs - bi * batch);
+            net_input(net, a, net->pairs + bi * batch, 0, nb, D, true, s);
+            forward(net, nb, D, s);
+            const long long nvox = (long long)nb * D * D * D;
+            if ((e = hipMemsetAsync(net->acc, 0, 2 * sizeof(float), s)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_loss, dim3(grid_for(nvox)), dim3(256), 0, s, net->out, net->tgt, net->grad[OUT], net->acc,
+                               nvox);
+            if ((e = hipMemcpyAsync(&accs[2 * bi], net->acc, 2 * sizeof(float), hipMemcpyDeviceToHost, s)) != hipSuccess)
+                return e;
+        }
+        if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+        double num = 0.0, den = 0.0;
+        for (int bi = 0; bi < nbat; ++bi) {
+            num += accs[2 * bi];
+            den += accs[2 * bi + 1];
+        }
+        *loss = den > 0.0 ? num / den : 0.0;
+        return hipGetLastError();
+    }
     for (int ep = 0; ep < epochs; ++ep) {
         std::shuffle(order.begin(), order.end(), rng);
         if ((e = hipMemcpyAsync(net->pairs, order.data(), (size_t)n_pairs * sizeof(int), hipMemcpyHostToDevice, s)) !=
@@ -751,8 +875,7 @@ hipError_t net_train(ExxNet *net, const NetPairArgs &a, const int *pairs, int n_
         const int nbat = n_pairs / batch;
         accs.assign((size_t)2 * nbat, 0.f);
         for (int bi = 0; bi < nbat; ++bi) {
-            hipLaunchKernelGGL(k_net_input, dim3(batch), dim3(256), 0, s, a, (const int *)(net->pairs + bi * batch), 0, D,
-                               net->f, net->act[IN], net->tgt, net->scale);
+            net_input(net, a, net->pairs + bi * batch, 0, batch, D, true, s);
             forward(net, batch, D, s);
             const long long nvox = (long long)batch * D * D * D;
             if ((e = hipMemsetAsync(net->acc, 0, 2 * sizeof(float), s)) != hipSuccess) return e;

@@ -216,3 +216,23 @@ def test_uneven_subdomain_classes_in_one_launch():
         assert abs(Eg - E) <= 1e-8 * abs(E), (prec, Eg, E)
         assert np.max(np.abs(info["e"] - out["e"]) / np.abs(out["e"])) <= 1e-8
         assert gamma(D, Dg.cpu().numpy()).max() <= 1e-7
+
+
+def test_autotuner_times_every_fitting_variant(c1):
+    """exx_setup times each z-march variant that fits (all three on the small
+    spheres) and keeps one of them; the solve still matches the oracle.  With
+    autotune off the occupancy rule decides and no variant is timed."""
+    wl, phi, E, D, out = c1
+    _say("[gpu] autotune")
+    ctx = X.Exx.from_workload(wl, autotune=True)
+    ctx.pairs(wl.orbitals.centers)
+    Eg, Dg = ctx.step(torch.from_numpy(phi).cuda())
+    st = ctx.stats()
+    assert st["tuned"] == 3 and st["tune_ms"] > 0.0
+    assert (st["solve_block"], st["cg_cols"]) in [(256, 4), (512, 4), (512, 6)]
+    assert abs(Eg - E) <= 1e-8 * abs(E)
+    assert gamma(D, Dg.cpu().numpy()).max() <= 1e-7
+    off = X.Exx.from_workload(wl, autotune=False)
+    off.pairs(wl.orbitals.centers)
+    off.step(torch.from_numpy(phi).cuda())
+    assert off.stats()["tuned"] == 0
