@@ -159,6 +159,8 @@ def main():
     ap.add_argument("--md-steps", type=int, default=0,
                     help="run a synthetic MD trajectory of this many steps instead (initial-guess comparison)")
     ap.add_argument("--guess", default="zero", choices=["zero", "previous", "extrap", "learned"])
+    ap.add_argument("--graph", action="store_true",
+                    help="launch each solve as a captured HIP graph (the CG kernel is then timed with the whole solve)")
     ap.add_argument("--coarsen", type=int, default=2, help="learned guess: grid points per coarse cell edge")
     ap.add_argument("--train-seeds", type=int, default=2, help="learned guess: training configurations")
     ap.add_argument("--train-epochs", type=int, default=2)
@@ -198,7 +200,7 @@ def main():
     phi = S.orbitals_torch(wl, device=dev)
     guess = "learned" if args.guess == "learned" else "zero"
     ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols, inner_rtol=args.inner_rtol,
-                              guess=guess)
+                              guess=guess, graph=args.graph)
     learned = train_model(args, wl, ctx) if guess == "learned" else None
     n_pairs = ctx.pairs(wl.orbitals.centers)
     info = ctx.pair_info(results=False)
@@ -252,6 +254,7 @@ def main():
                             dxx_gbs=round(st["dxx_bytes"] / (st["dxx_ms"] * 1e-3) / 1e9, 1) if st["dxx_ms"] > 0 else None,
                             grid=st["solve_grid"], block=st["solve_block"], waves=st["n_waves"],
                             autotuned_variants=st["tuned"], tune_ms=round(st["tune_ms"], 1),
+                            graph_launches=st["graph_launches"],
                             cg_cols=st["cg_cols"], cg_bands=st["cg_bands"], outer_total=st["outer_total"],
                             inner_rtol=args.inner_rtol if wl.precision != "fp64" else None,
                             kernel_hash=kernel_hash()))

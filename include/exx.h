@@ -22,6 +22,9 @@
  * (the convention of Eq. l2g).  The caller applies the hybrid mixing
  * fraction a_x (Eq. hyb); E_xx and D are returned unscaled.
  *
+ * Timing fields of exx_stats are HIP-event times; in graph mode only the
+ * whole solve is timed (prep_ms, cg_ms, guess_ms read -1).
+ *
  * Call order: exx_setup -> exx_pairs -> exx_solve -> exx_energy_potential
  * (then exx_pairs or exx_solve again for the next step).  Out-of-order calls
  * return EXX_ESTATE.  No call throws or aborts; every failure returns a
@@ -82,6 +85,11 @@ typedef struct {
                                variant that fits (a few CG iterations on a
                                synthetic batch) and keeps the fastest;
                                0: choose by occupancy alone                  */
+    int32_t graph;          /* 1: exx_solve captures its launches into a HIP
+                               graph on a stream of its own and replays it
+                               while the pairs, phi and the model buffers are
+                               unchanged (zero or learned guess; the
+                               history guesses always run eagerly)           */
 } exx_params;
 
 typedef struct {
@@ -111,6 +119,8 @@ typedef struct {
     double  guess_ms;        /* last solve: guess kernels / model inference     */
     int32_t tuned;           /* CG variants the set-up autotuner timed (0: none) */
     double  tune_ms;         /* time of those tuning launches                   */
+    int32_t graph_builds;    /* graph mode: captures so far                     */
+    int32_t graph_launches;  /* graph mode: solves launched as a graph          */
 } exx_stats_t;
 
 /* Fills *p with the paper's method defaults (n = 3, l_max = 6, FP64, zero

@@ -96,6 +96,13 @@ struct exx_ctx {
 
     int block = 256, grid = 0, slots = 0, wave_n = 0, n_waves = 0;
     int tuned = 0;           // variants timed by the autotuner (0: heuristic choice)
+    // graph mode: the captured solve and what it was captured for
+    hipStream_t gstream = nullptr;
+    hipGraphExec_t gexec = nullptr;
+    unsigned long long pairs_gen = 0, g_pairs_gen = 0, g_net_gen = 0;
+    const void *g_phi = nullptr;
+    bool g_learned = false, last_graph = false;
+    int graph_builds = 0, graph_launches = 0;
     double tune_ms = 0.0;    // time of the timed tuning launches
     CgVariant var{0, 256, 0, 0, 0, 0, 0};
     size_t lds_bytes = 0;
@@ -876,6 +883,7 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
             return st;
     }
     c->state = 2;
+    ++c->pairs_gen;
     if (n_pairs) *n_pairs = c->n_pairs;
     return EXX_OK;
 }
@@ -976,27 +984,67 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
         for (int k = 0; k < 3; ++k) ga.hist[k] = c->hist[k].valid ? c->hist[k].v.p : nullptr;
         ga.vout = c->d_vout.p;
     }
-    c->n_waves = 0;
-    HIPCHK(c, hipEventRecord(c->ev[0], s));
-    for (int64_t w0 = 0; w0 < c->n_pairs; w0 += c->wave_n) {
-        a.wave_begin = (int)w0;
-        a.wave_n = (int)std::min<int64_t>(c->wave_n, c->n_pairs - w0);
-        HIPCHK(c, launch_prep(a, s));
-        if (w0 == 0) HIPCHK(c, hipEventRecord(c->ev[6], s));
-        if (use_guess) {
-            ga.wave_begin = a.wave_begin;
-            HIPCHK(c, launch_guess(ga, a.wave_n, s));
+    c->n_waves = (int)((c->n_pairs + c->wave_n - 1) / c->wave_n);
+    // every launch of the solve, wave by wave; phase events only when eager
+    auto enqueue = [&](hipStream_t st, bool events) -> hipError_t {
+        hipError_t e;
+        for (int64_t w0 = 0; w0 < c->n_pairs; w0 += c->wave_n) {
+            a.wave_begin = (int)w0;
+            a.wave_n = (int)std::min<int64_t>(c->wave_n, c->n_pairs - w0);
+            if ((e = launch_prep(a, st)) != hipSuccess) return e;
+            if (events && w0 == 0 && (e = hipEventRecord(c->ev[6], st)) != hipSuccess) return e;
+            if (use_guess) {
+                ga.wave_begin = a.wave_begin;
+                if ((e = launch_guess(ga, a.wave_n, st)) != hipSuccess) return e;
+            }
+            if (learned) {
+                na.wave_begin = a.wave_begin;
+                if ((e = net_infer(c->net, na, a.wave_n, c->net_D, nullptr, st)) != hipSuccess) return e;
+            }
+            if ((e = launch_zero_int(c->d_counter.p, 1, st)) != hipSuccess) return e;
+            if (events && w0 == 0 && (e = hipEventRecord(c->ev[5], st)) != hipSuccess) return e;
+            if ((e = launch_cg(c->var, a, std::min(c->grid, a.wave_n), c->lds_bytes, st)) != hipSuccess) return e;
         }
-        if (learned) {
-            na.wave_begin = a.wave_begin;
-            HIPCHK(c, net_infer(c->net, na, a.wave_n, c->net_D, nullptr, s));
+        return hipSuccess;
+    };
+    // Graph mode (zero or learned guess): the launches are captured once on
+    // the context's own stream and replayed while the pairs, phi and the
+    // model's buffers are unchanged; the caller's stream and the graph
+    // stream are ordered by events.
+    c->last_graph = c->prm.graph && !use_guess;
+    if (c->last_graph) {
+        if (!c->gstream) HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
+        if (learned) HIPCHK(c, net_reserve(c->net, (int)std::min<int64_t>(c->wave_n, c->n_pairs), c->net_D));
+        const unsigned long long net_gen = c->net ? net_generation(c->net) : 0;
+        if (!c->gexec || c->g_pairs_gen != c->pairs_gen || c->g_phi != phi || c->g_net_gen != net_gen ||
+            c->g_learned != learned) {
+            if (c->gexec) { (void)hipGraphExecDestroy(c->gexec); c->gexec = nullptr; }
+            HIPCHK(c, hipStreamBeginCapture(c->gstream, hipStreamCaptureModeThreadLocal));
+            const hipError_t e1 = enqueue(c->gstream, false);
+            hipGraph_t g = nullptr;
+            const hipError_t e2 = hipStreamEndCapture(c->gstream, &g);
+            HIPCHK(c, e1);
+            HIPCHK(c, e2);
+            const hipError_t e3 = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCHK(c, e3);
+            c->g_pairs_gen = c->pairs_gen;
+            c->g_phi = phi;
+            c->g_net_gen = net_gen;
+            c->g_learned = learned;
+            ++c->graph_builds;
         }
-        HIPCHK(c, launch_zero_int(c->d_counter.p, 1, s));
-        if (w0 == 0) HIPCHK(c, hipEventRecord(c->ev[5], s));
-        HIPCHK(c, launch_cg(c->var, a, std::min(c->grid, a.wave_n), c->lds_bytes, s));
-        ++c->n_waves;
+        HIPCHK(c, hipEventRecord(c->ev[0], s));
+        HIPCHK(c, hipStreamWaitEvent(c->gstream, c->ev[0], 0));
+        HIPCHK(c, hipGraphLaunch(c->gexec, c->gstream));
+        HIPCHK(c, hipEventRecord(c->ev[1], c->gstream));
+        HIPCHK(c, hipStreamWaitEvent(s, c->ev[1], 0));
+        ++c->graph_launches;
+    } else {
+        HIPCHK(c, hipEventRecord(c->ev[0], s));
+        HIPCHK(c, enqueue(s, true));
+        HIPCHK(c, hipEventRecord(c->ev[1], s));
     }
-    HIPCHK(c, hipEventRecord(c->ev[1], s));
     if (use_guess) {
         // rotate the history ring and keep this step's PE potentials (FP32)
         exx_ctx::Hist old = std::move(c->hist[2]);
@@ -1120,7 +1168,9 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     st->guess_pairs = c->guess_pairs;
     st->tuned = c->tuned;
     st->tune_ms = c->tune_ms;
-    if (c->n_waves == 1) {
+    st->graph_builds = c->graph_builds;
+    st->graph_launches = c->graph_launches;
+    if (c->n_waves == 1 && !c->last_graph) {
         if (hipEventElapsedTime(&ms, c->ev[0], c->ev[6]) == hipSuccess) st->prep_ms = ms;
         if (hipEventElapsedTime(&ms, c->ev[6], c->ev[5]) == hipSuccess) st->guess_ms = ms;
         if (hipEventElapsedTime(&ms, c->ev[5], c->ev[1]) == hipSuccess) st->cg_ms = ms;
@@ -1293,6 +1343,8 @@ void exx_destroy(exx_ctx *c)
     dev_free(c->d_guess); dev_free(c->d_hist_off);
     for (auto &h : c->hist) dev_free(h.v);
     net_destroy(c->net);
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->gstream) (void)hipStreamDestroy(c->gstream);
     dev_free(c->d_bnd[0]); dev_free(c->d_bnd[1]);
     dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_outer); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
     if (c->have_events)

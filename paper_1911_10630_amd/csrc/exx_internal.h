@@ -194,6 +194,10 @@ hipError_t net_boundary_flags(const ClassDev &g, unsigned char *flag, hipStream_
 // Device bytes of the activation buffers for `batch` samples of edge D
 // (training adds the gradient buffers).
 size_t net_buffer_bytes(int batch, int D, bool training);
+// Allocates the inference buffers for waves of n pairs (nothing if they exist).
+hipError_t net_reserve(ExxNet *net, int n, int D);
+// Changes whenever the model's device buffers are reallocated.
+unsigned long long net_generation(const ExxNet *net);
 // Guess for pairs [wave_begin, wave_begin + n) of the wave in a.
 hipError_t net_infer(ExxNet *net, const NetPairArgs &a, int n, int D, double *ms, hipStream_t s);
 // Adam epochs over the given pairs (their rhs and solutions must be resident).

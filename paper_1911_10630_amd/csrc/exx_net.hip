@@ -522,8 +522,11 @@ struct ExxNet {
     double *scale = nullptr, *part = nullptr;
     int *pairs = nullptr;
     int pairs_cap = 0;
+    unsigned long long generation = 0;   // bumped whenever the buffers move
     hipEvent_t ev[2] = {};
 };
+
+unsigned long long net_generation(const ExxNet *net) { return net->generation; }
 
 int net_coarsen(const ExxNet *net) { return net->f; }
 
@@ -571,6 +574,7 @@ static hipError_t net_alloc(ExxNet *net, int batch, int D, bool training)
 {
     if (batch <= net->cap && D == net->capD && (net->cap_grad || !training)) return hipSuccess;
     free_buffers(net);
+    ++net->generation;
     const long long v1 = (long long)batch * D * D * D;
     hipError_t e;
     for (int r = 0; r < NROLE; ++r) {
@@ -799,12 +803,18 @@ static int infer_batch(int D)
     return (int)std::max<size_t>(1, std::min<size_t>(64, ((size_t)1 << 30) / per));
 }
 
+hipError_t net_reserve(ExxNet *net, int n, int D)
+{
+    const int B = std::min(infer_batch(D), std::max(n, 1));
+    return net_alloc(net, std::max(B, net->cap), D, net->cap_grad);
+}
+
 hipError_t net_infer(ExxNet *net, const NetPairArgs &a, int n, int D, double *ms, hipStream_t s)
 {
     const int B = std::min(infer_batch(D), std::max(n, 1));
     hipError_t e = net_alloc(net, std::max(B, net->cap), D, net->cap_grad);
     if (e != hipSuccess) return e;
-    if ((e = hipEventRecord(net->ev[0], s)) != hipSuccess) return e;
+    if (ms && (e = hipEventRecord(net->ev[0], s)) != hipSuccess) return e;
     for (int b0 = 0; b0 < n; b0 += B) {
         const int nb = std::min(B, n - b0);
         const int base = a.wave_begin + b0;
@@ -814,8 +824,8 @@ hipError_t net_infer(ExxNet *net, const NetPairArgs &a, int n, int D, double *ms
         hipLaunchKernelGGL(k_net_output, dim3((unsigned)((npe + 255) / 256), (unsigned)nb), dim3(256), 0, s, a, base, D,
                            net->f, net->out, net->scale);
     }
-    if ((e = hipEventRecord(net->ev[1], s)) != hipSuccess) return e;
     if (ms) {
+        if ((e = hipEventRecord(net->ev[1], s)) != hipSuccess) return e;
         if ((e = hipEventSynchronize(net->ev[1])) != hipSuccess) return e;
         float t = 0.f;
         if ((e = hipEventElapsedTime(&t, net->ev[0], net->ev[1])) != hipSuccess) return e;

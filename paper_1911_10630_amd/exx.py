@@ -35,7 +35,7 @@ class ExxParams(C.Structure):
                 ("precision", C.c_int32), ("orbital_dtype", C.c_int32), ("guess", C.c_int32),
                 ("inner_rtol", C.c_double), ("block_threads", C.c_int32), ("cg_cols", C.c_int32),
                 ("wave_pairs", C.c_int64),
-                ("keep_intermediates", C.c_int32), ("autotune", C.c_int32)]
+                ("keep_intermediates", C.c_int32), ("autotune", C.c_int32), ("graph", C.c_int32)]
 
 
 class ExxStats(C.Structure):
@@ -48,7 +48,7 @@ class ExxStats(C.Structure):
                 ("n_me", C.c_int64 * 2), ("cg_bytes", C.c_int64), ("solve_bytes", C.c_int64),
                 ("dxx_bytes", C.c_int64), ("device_bytes", C.c_int64), ("n_waves", C.c_int32),
                 ("guess_pairs", C.c_int32), ("guess_ms", C.c_double), ("tuned", C.c_int32),
-                ("tune_ms", C.c_double)]
+                ("tune_ms", C.c_double), ("graph_builds", C.c_int32), ("graph_launches", C.c_int32)]
 
 
 class ExxError(RuntimeError):
@@ -119,7 +119,7 @@ class Exx:
 
     def __init__(self, n_grid, cell, r_pair, r_pe, r_me, *, cg_rtol=1e-10, cg_max_iter=20000,
                  precision="fp64", orbital_dtype="f64", guess="zero", inner_rtol=1e-5, block_threads=0,
-                 cg_cols=0, wave_pairs=0, keep_intermediates=False, autotune=True, device=0):
+                 cg_cols=0, wave_pairs=0, keep_intermediates=False, autotune=True, graph=False, device=0):
         L = load()
         p = ExxParams()
         L.exx_default_params(C.byref(p))
@@ -142,6 +142,7 @@ class Exx:
         p.wave_pairs = int(wave_pairs)
         p.keep_intermediates = 1 if keep_intermediates else 0
         p.autotune = 1 if autotune else 0
+        p.graph = 1 if graph else 0
         self.params = p
         self.device = int(device)
         self.n_grid = tuple(int(v) for v in n_grid)

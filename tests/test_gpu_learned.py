@@ -271,3 +271,22 @@ def test_training_needs_resident_right_hand_sides(c1_ref):
     with pytest.raises(X.ExxError) as ei:
         ctx.model_train(epochs=1, batch=4)
     assert ei.value.status == X.EXX_ESTATE
+
+
+def test_learned_guess_in_graph_mode(c1_ref, trained):
+    """The learned guess (net inference kernels) captured in the solve graph
+    replays to the eager result bitwise."""
+    wl, phi, *_ = c1_ref
+    blob, _ = trained
+    eager = X.Exx.from_workload(wl, guess="learned")
+    eager.load_model(blob)
+    eager.pairs(wl.orbitals.centers)
+    phit = torch.from_numpy(phi).cuda()
+    E0, D0 = eager.step(phit)
+    g = X.Exx.from_workload(wl, guess="learned", graph=True)
+    g.load_model(blob)
+    g.pairs(wl.orbitals.centers)
+    for k in range(3):
+        E1, D1 = g.step(phit)
+        assert E1 == E0 and torch.equal(D1, D0), k
+    assert g.stats()["graph_launches"] == 3 and g.stats()["graph_builds"] == 1

@@ -236,3 +236,25 @@ def test_autotuner_times_every_fitting_variant(c1):
     off.pairs(wl.orbitals.centers)
     off.step(torch.from_numpy(phi).cuda())
     assert off.stats()["tuned"] == 0
+
+
+def test_graph_mode_replays_bitwise(c1, c1_gpu):
+    """Graph mode: the first solve captures, later solves replay; each replay
+    (with eager device work and synchronizations between) gives bitwise the
+    eager result.  New pairs re-capture."""
+    wl, phi, E, D, out = c1
+    ctx0, n, Eg, Dg, info, phit = c1_gpu
+    _say("[gpu] graph mode")
+    ctx = X.Exx.from_workload(wl, graph=True)
+    ctx.pairs(wl.orbitals.centers)
+    for k in range(3):
+        E2, D2 = ctx.step(phit)
+        junk = torch.randn(1 << 20, device="cuda").sum().item()   # eager work between replays
+        assert np.isfinite(junk)
+        assert E2 == Eg and np.array_equal(D2.cpu().numpy(), Dg), k
+    st = ctx.stats()
+    assert st["graph_builds"] == 1 and st["graph_launches"] == 3
+    assert st["prep_ms"] == -1.0 and st["solve_ms"] > 0.0
+    ctx.pairs(wl.orbitals.centers)
+    E3, _ = ctx.step(phit)
+    assert E3 == Eg and ctx.stats()["graph_builds"] == 2
