@@ -19,7 +19,8 @@
  * conjugate gradient (Sec. III.C, Step IV).
  *
  * Units: bohr and hartree.  Grids: [n_orb][Nz][Ny][Nx], x fastest, 0-based
- * (the convention of Eq. l2g).  The caller applies the hybrid mixing
+ * (the convention of Eq. l2g); with local boxes (params.box_dims) orbitals
+ * and D are [n_orb][bz][by][bx] instead, each on its own box.  The caller applies the hybrid mixing
  * fraction a_x (Eq. hyb); E_xx and D are returned unscaled.
  *
  * Timing fields of exx_stats are HIP-event times; in graph mode only the
@@ -90,6 +91,10 @@ typedef struct {
                                while the pairs, phi and the model buffers are
                                unchanged (zero or learned guess; the
                                history guesses always run eagerly)           */
+    int32_t box_dims[3];    /* orbital storage box (bx, by, bz) in grid points;
+                               0 = the whole grid.  Orbital k (and D^k) is
+                               stored on the periodic box starting at
+                               exx_box_origins()[k] and is zero outside it */
 } exx_params;
 
 typedef struct {
@@ -143,11 +148,21 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out);
  * on the device. */
 exx_status exx_pairs(exx_ctx *ctx, int32_t n_orb, const double *centers, int64_t *n_pairs);
 
+/* Box origins chosen by exx_pairs, host [n_orb][3] grid points: origin =
+ * nearest grid point of the centre minus box_dims / 2 (mod N), or 0 along
+ * an axis where the box spans the grid.  exx_pairs returns EXX_EINVAL if an
+ * ME sphere of a pair leaves the box of one of its orbitals (D would be cut
+ * off): boxes of edge 2 (R_pair / 2 + R_ME) / h + 4 always suffice. */
+exx_status exx_box_origins(exx_ctx *ctx, int32_t *origins);
+
 /* Enqueues every pair solve on `stream` (a hipStream_t; NULL = default):
  * gather and pair density, multipole moments, shell potential and
  * right-hand side, conjugate gradient, pair energy.  phi: device,
  * [n_orb][Nz][Ny][Nx] of orbital_dtype, read-only, must stay valid until
- * the stream work completes.  Asynchronous. */
+ * the stream work completes.  Asynchronous.  When the pairs' potentials
+ * do not fit at once, the pairs run in waves and D is summed wave by wave
+ * into FP64 partial sums during this call (results do not depend on the
+ * split). */
 exx_status exx_solve(exx_ctx *ctx, const void *phi, void *stream);
 
 /* Enqueues D accumulation and the E reduction on `stream`, then

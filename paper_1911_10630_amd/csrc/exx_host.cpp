@@ -77,6 +77,13 @@ struct exx_ctx {
     DevBuf<int> d_iters, d_outer, d_conv, d_counter;
     DevBuf<float> d_scratch32;
 
+    // orbital boxes
+    int box[3] = {0, 0, 0};
+    long long box_vol = 0;
+    std::vector<int4> box_org;
+    DevBuf<int4> d_box_org;
+    DevBuf<double> d_dacc;   // FP64 partial sums of D across waves
+
     // PE potentials of earlier steps (most recent first), keyed by (i, j)
     struct Hist {
         bool valid = false;
@@ -84,7 +91,7 @@ struct exx_ctx {
         std::vector<int4> gc;
         std::vector<long long> off;
         DevBuf<float> v;
-    } hist[3];
+    } hist[3], hist_next;
     DevBuf<PairGuess> d_guess;
     DevBuf<long long> d_hist_off;
     int guess_pairs = 0;     // pairs of the last solve that had a history
@@ -373,6 +380,42 @@ ClassDev class_dev(const HostClass &k)
     return d;
 }
 
+OrbBox orb_box(const exx_ctx *c)
+{
+    OrbBox b{};
+    b.org = c->d_box_org.p;
+    b.bx = c->box[0];
+    b.by = c->box[1];
+    b.bz = c->box[2];
+    b.vol = c->box_vol;
+    return b;
+}
+
+DxxArgs dxx_args(const exx_ctx *c, const void *phi, void *dxx)
+{
+    DxxArgs d{};
+    d.cls[0] = class_dev(c->cls[0]);
+    d.cls[1] = class_dev(c->cls[1]);
+    d.pair_gc = c->d_gc.p;
+    d.pair_ij = c->d_ij.p;
+    d.out_off = c->d_off.p;
+    d.orb_ptr = c->d_orb_ptr.p;
+    d.orb_pairs = c->d_orb_pairs.p;
+    d.phi = phi;
+    d.box = orb_box(c);
+    d.dxx = dxx;
+    d.acc = c->d_dacc.p;
+    d.f32 = c->prm.orbital_dtype == EXX_F32;
+    d.nx = c->prm.n_grid[0];
+    d.ny = c->prm.n_grid[1];
+    d.nz = c->prm.n_grid[2];
+    d.ngrid = (long long)d.nx * d.ny * d.nz;
+    d.vout = c->d_vout.p;
+    d.pair_lo = 0;
+    d.pair_hi = (int)c->n_pairs;
+    return d;
+}
+
 // Largest |offset| of a PE point over both classes (grid points).
 int pe_rmax(const exx_ctx *c)
 {
@@ -545,12 +588,13 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
     int *it = (int *)dev((size_t)n * 4), *ou = (int *)dev((size_t)n * 4), *cv = (int *)dev((size_t)n * 4);
     int *counter = (int *)dev(4);
     int4 *gc = (int4 *)dev((size_t)n * sizeof(int4));
+    int4 *org = (int4 *)dev(sizeof(int4));
     int2 *ij = (int2 *)dev((size_t)n * sizeof(int2));
     long long *off = (long long *)dev((size_t)n * 8);
     hipEvent_t ev[2] = {};
     int best = -1;
     float best_ms = 0.f;
-    if (allocs.size() != (size_t)(mixed ? 15 : 14) || hipEventCreate(&ev[0]) != hipSuccess ||
+    if (allocs.size() != (size_t)(mixed ? 16 : 15) || hipEventCreate(&ev[0]) != hipSuccess ||
         hipEventCreate(&ev[1]) != hipSuccess) {
         release();
         for (auto &x : ev) if (x) (void)hipEventDestroy(x);
@@ -565,12 +609,14 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
               hipMemset(vout, 0, (size_t)n * per_pair * 8) == hipSuccess &&
               hipMemcpy(gc, hgc.data(), hgc.size() * sizeof(int4), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(ij, hij.data(), hij.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemset(org, 0, sizeof(int4)) == hipSuccess &&
               hipMemcpy(off, hoff.data(), hoff.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
     SolveArgs a{};
     a.pair_gc = gc;
     a.pair_ij = ij;
     a.out_off = off;
     a.phi = phi;
+    a.box = OrbBox{org, c->prm.n_grid[0], c->prm.n_grid[1], c->prm.n_grid[2], (long long)ngrid};
     a.phi_f32 = 0;
     a.nx = c->prm.n_grid[0];
     a.ny = c->prm.n_grid[1];
@@ -720,6 +766,9 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         return fail(nullptr, EXX_EINVAL, "unknown orbital_dtype %d", p->orbital_dtype);
     if (p->guess < EXX_GUESS_ZERO || p->guess > EXX_GUESS_LEARNED)
         return fail(nullptr, EXX_EINVAL, "unknown guess %d", p->guess);
+    for (int a = 0; a < 3; ++a)
+        if (p->box_dims[a] < 0 || p->box_dims[a] > p->n_grid[a])
+            return fail(nullptr, EXX_EINVAL, "box_dims[%d] = %d outside [0, n_grid]", a, p->box_dims[a]);
     if (p->precision == EXX_FP32_REFINE && !(p->inner_rtol > 0.0 && p->inner_rtol < 1.0))
         return fail(nullptr, EXX_EINVAL, "inner_rtol must lie in (0, 1)");
     double hmax = 0.0;
@@ -750,7 +799,9 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
     for (int a = 0; a < 3; ++a) {
         c->h[a] = p->cell[a] / p->n_grid[a];
         c->c0[a] = (int)nint_away(0.5 * p->n_grid[a]);
+        c->box[a] = p->box_dims[a] > 0 ? p->box_dims[a] : p->n_grid[a];
     }
+    c->box_vol = (long long)c->box[0] * c->box[1] * c->box[2];
     for (int k = 0; k < 2; ++k) {
         exx_status st = build_class(c, c->cls[k], p->r_pe[k], p->r_me[k]);
         if (st != EXX_OK) return bail(st);
@@ -801,13 +852,43 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
             const int cl = i == j ? 0 : 1;
             c->ij.push_back(int2{i, j});
             c->gc.push_back(int4{g[0], g[1], g[2], cl});
-            c->out_off.push_back(off);
             off += c->cls[cl].n_pe + c->cls[cl].n_sh;
             if (i == j) ++c->n_self;
         }
     c->n_pairs = (int64_t)c->ij.size();
-    c->vout_n = off;
     c->n_orb = n_orb;
+    // orbital boxes: origin = nearest grid point of the centre minus half the
+    // box; a box as wide as the grid has origin 0
+    c->box_org.assign((size_t)n_orb, int4{0, 0, 0, 0});
+    for (int i = 0; i < n_orb; ++i) {
+        int o[3];
+        for (int a = 0; a < 3; ++a) {
+            if (c->box[a] >= N[a]) { o[a] = 0; continue; }
+            double m = C[3 * i + a] - L[a] * std::floor(C[3 * i + a] / L[a]);
+            o[a] = mod_pos(nint_away(m / c->h[a]) - c->box[a] / 2, N[a]);
+        }
+        c->box_org[i] = int4{o[0], o[1], o[2], 0};
+    }
+    // every ME sphere must lie inside the boxes of both its orbitals, or D
+    // would be cut off
+    for (size_t p = 0; p < c->ij.size(); ++p) {
+        const HostClass &k = c->cls[c->gc[p].w];
+        const int lo[3] = {k.mxlo, k.mylo, k.mzlo}, ext[3] = {k.mxhi - k.mxlo + 1, k.myhi - k.mylo + 1, k.mzhi - k.mzlo + 1};
+        const int gp[3] = {c->gc[p].x, c->gc[p].y, c->gc[p].z};
+        for (int side = 0; side < 2; ++side) {
+            const int orb = side ? c->ij[p].y : c->ij[p].x;
+            const int oo[3] = {c->box_org[orb].x, c->box_org[orb].y, c->box_org[orb].z};
+            for (int a = 0; a < 3; ++a) {
+                if (c->box[a] >= N[a]) continue;
+                const int start = mod_pos((long)gp[a] + lo[a] - oo[a], N[a]);
+                if (start + ext[a] > c->box[a])
+                    return fail(c, EXX_EINVAL,
+                                "box_dims[%d] = %d is too small: the ME sphere of pair (%d, %d) leaves the box of "
+                                "orbital %d",
+                                a, c->box[a], c->ij[p].x, c->ij[p].y, orb);
+            }
+        }
+    }
     c->orb_ptr.assign(n_orb + 1, 0);
     for (auto &q : c->ij) {
         c->orb_ptr[q.x + 1]++;
@@ -825,11 +906,10 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     exx_status st;
     if ((st = upload(c, c->d_ij, c->ij)) != EXX_OK) return st;
     if ((st = upload(c, c->d_gc, c->gc)) != EXX_OK) return st;
-    if ((st = upload(c, c->d_off, c->out_off)) != EXX_OK) return st;
     if ((st = upload(c, c->d_orb_ptr, c->orb_ptr)) != EXX_OK) return st;
     if ((st = upload(c, c->d_orb_pairs, c->orb_pairs)) != EXX_OK) return st;
+    if ((st = upload(c, c->d_box_org, c->box_org)) != EXX_OK) return st;
     const size_t np = (size_t)c->n_pairs;
-    if ((st = dev_reserve(c, c->d_vout, (size_t)c->vout_n)) != EXX_OK) return st;
     if ((st = dev_reserve(c, c->d_q, np * NLM)) != EXX_OK) return st;
     if ((st = dev_reserve(c, c->d_e, np)) != EXX_OK) return st;
     if ((st = dev_reserve(c, c->d_relres, np)) != EXX_OK) return st;
@@ -853,31 +933,58 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
         if ((st = dev_reserve(c, c->d_scratch32, (size_t)c->slots * 4 * c->slot_n)) != EXX_OK) return st;
     }
     if ((st = dev_reserve(c, c->d_scratch, (size_t)c->slots * 3 * c->slot_n)) != EXX_OK) return st;
-    // right-hand sides of one wave of pairs; the wave is as large as the
-    // device allows (one launch of each kernel when everything fits)
+    // Waves of pairs: each wave holds its pairs' right-hand sides and
+    // potentials.  One wave when everything fits; otherwise D is summed wave
+    // by wave into FP64 partial sums (so the result does not depend on the
+    // split) and the waves are as large as the device allows.
     {
         size_t freeb = 0, totalb = 0;
         HIPCHK(c, hipMemGetInfo(&freeb, &totalb));
-        const size_t per_pair = (size_t)c->slot_n * sizeof(double);
-        int64_t w = c->n_pairs;
-        if (c->prm.wave_pairs > 0) w = std::min<int64_t>(w, c->prm.wave_pairs);
-        const size_t have = c->d_rhs.n * sizeof(double);
-        // keep 2 GiB free, and room for the three history levels of the guess
+        const long long v_max = std::max<long long>((long long)c->cls[0].n_pe + c->cls[0].n_sh,
+                                                    (long long)c->cls[1].n_pe + c->cls[1].n_sh);
+        const size_t per_pair = (size_t)(c->slot_n + v_max) * sizeof(double);
+        const size_t have = (c->d_rhs.n + c->d_vout.n + c->d_dacc.n) * sizeof(double);
+        // keep 2 GiB free, and room for the model or the guess history
         size_t keep = (size_t)2 << 30;
         if (c->prm.guess == EXX_GUESS_LEARNED) keep += (size_t)3 << 29;   // net activations
         if (c->prm.guess == EXX_GUESS_PREVIOUS || c->prm.guess == EXX_GUESS_EXTRAP) {
             size_t hist = 0;
             for (auto &q : c->gc) hist += (size_t)c->cls[q.w].n_pe * sizeof(float);
-            size_t held = 0;
+            size_t held = c->hist_next.v.n * sizeof(float);
             for (auto &h : c->hist) held += h.v.n * sizeof(float);
-            keep += 3 * hist > held ? 3 * hist - held : 0;
+            const size_t levels = c->prm.guess == EXX_GUESS_PREVIOUS ? 2 : 4;   // kept + the one being written
+            keep += levels * hist > held ? levels * hist - held : 0;
         }
         const size_t budget = freeb + have > keep ? freeb + have - keep : 0;
-        w = std::min<int64_t>(w, (int64_t)(budget / per_pair));
+        const size_t dacc = (size_t)c->n_orb * c->box_vol * sizeof(double);
+        int64_t w = c->n_pairs;
+        if ((size_t)c->n_pairs * per_pair > budget)
+            w = budget > dacc ? (int64_t)((budget - dacc) / per_pair) : 0;
+        if (c->prm.wave_pairs > 0) w = std::min<int64_t>(w, c->prm.wave_pairs);
         if (c->prm.keep_intermediates) w = c->n_pairs;
-        if (w < 1) return fail(c, EXX_ENOMEM, "no device memory left for right-hand sides");
+        w = std::min<int64_t>(w, c->n_pairs);
+        if (w < 1) return fail(c, EXX_ENOMEM, "no device memory left for a wave of pairs");
         c->wave_n = (int)w;
+        // potentials: offsets relative to the pair's wave
+        c->out_off.assign((size_t)c->n_pairs, 0);
+        long long vmax = 0;
+        for (int64_t w0 = 0; w0 < c->n_pairs; w0 += w) {
+            long long o = 0;
+            for (int64_t p = w0; p < std::min<int64_t>(w0 + w, c->n_pairs); ++p) {
+                c->out_off[p] = o;
+                o += (long long)c->cls[c->gc[p].w].n_pe + c->cls[c->gc[p].w].n_sh;
+            }
+            vmax = std::max(vmax, o);
+        }
+        c->vout_n = vmax;
+        if ((st = upload(c, c->d_off, c->out_off)) != EXX_OK) return st;
+        if ((st = dev_reserve(c, c->d_vout, (size_t)vmax)) != EXX_OK) return st;
         if ((st = dev_reserve(c, c->d_rhs, (size_t)w * c->slot_n)) != EXX_OK) return st;
+        if (w < c->n_pairs) {
+            if ((st = dev_reserve(c, c->d_dacc, (size_t)c->n_orb * c->box_vol)) != EXX_OK) return st;
+        } else {
+            dev_free(c->d_dacc);
+        }
         if (c->prm.keep_intermediates &&
             (st = dev_reserve(c, c->d_rho_keep, (size_t)c->n_pairs * c->slot_n)) != EXX_OK)
             return st;
@@ -902,6 +1009,7 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
     a.pair_ij = c->d_ij.p;
     a.out_off = c->d_off.p;
     a.phi = phi;
+    a.box = orb_box(c);
     a.phi_f32 = c->prm.orbital_dtype == EXX_F32;
     a.nx = c->prm.n_grid[0];
     a.ny = c->prm.n_grid[1];
@@ -985,6 +1093,27 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
         ga.vout = c->d_vout.p;
     }
     c->n_waves = (int)((c->n_pairs + c->wave_n - 1) / c->wave_n);
+    // the level this step's potentials go to (saved wave by wave)
+    exx_ctx::Hist &nx = c->hist_next;
+    if (use_guess) {
+        nx.valid = false;
+        nx.index.clear();
+        nx.gc = c->gc;
+        nx.off.assign((size_t)c->n_pairs, 0);
+        long long tot = 0;
+        for (int64_t p = 0; p < c->n_pairs; ++p) {
+            nx.off[p] = tot;
+            tot += c->cls[c->gc[p].w].n_pe;
+            nx.index[(long long)c->ij[p].x * c->n_orb + c->ij[p].y] = (int)p;
+        }
+        exx_status st2 = dev_reserve(c, nx.v, (size_t)tot);
+        if (st2 != EXX_OK) return st2;
+        // nx.off lives until this level is recycled, after the copy completes
+        if ((st2 = upload_async(c, c->d_hist_off, nx.off, s, false)) != EXX_OK) return st2;
+    }
+    const bool multi = c->n_waves > 1;
+    DxxArgs dacc{};
+    if (multi) dacc = dxx_args(c, phi, nullptr);
     // every launch of the solve, wave by wave; phase events only when eager
     auto enqueue = [&](hipStream_t st, bool events) -> hipError_t {
         hipError_t e;
@@ -1004,6 +1133,18 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
             if ((e = launch_zero_int(c->d_counter.p, 1, st)) != hipSuccess) return e;
             if (events && w0 == 0 && (e = hipEventRecord(c->ev[5], st)) != hipSuccess) return e;
             if ((e = launch_cg(c->var, a, std::min(c->grid, a.wave_n), c->lds_bytes, st)) != hipSuccess) return e;
+            if ((e = launch_pair_energy(a, st)) != hipSuccess) return e;
+            if (use_guess &&
+                (e = launch_save_history(c->d_vout.p, c->d_off.p, c->d_hist_off.p, c->d_gc.p, c->cls[0].n_pe,
+                                         c->cls[1].n_pe, a.wave_begin, a.wave_n, nx.v.p, st)) != hipSuccess)
+                return e;
+            if (multi) {
+                // this wave's share of D, added to the partial sums in pair order
+                dacc.pair_lo = a.wave_begin;
+                dacc.pair_hi = a.wave_begin + a.wave_n;
+                dacc.acc_first = w0 == 0;
+                if ((e = launch_dxx(dacc, c->n_orb, 1, st)) != hipSuccess) return e;
+            }
         }
         return hipSuccess;
     };
@@ -1046,29 +1187,15 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
         HIPCHK(c, hipEventRecord(c->ev[1], s));
     }
     if (use_guess) {
-        // rotate the history ring and keep this step's PE potentials (FP32)
-        exx_ctx::Hist old = std::move(c->hist[2]);
-        c->hist[2] = std::move(c->hist[1]);
-        c->hist[1] = std::move(c->hist[0]);
-        exx_ctx::Hist &h = c->hist[0];
-        h = std::move(old);
-        h.valid = false;
-        h.index.clear();
-        h.gc = c->gc;
-        h.off.assign((size_t)c->n_pairs, 0);
-        long long tot = 0;
-        for (int64_t p = 0; p < c->n_pairs; ++p) {
-            h.off[p] = tot;
-            tot += c->cls[c->gc[p].w].n_pe;
-            h.index[(long long)c->ij[p].x * c->n_orb + c->ij[p].y] = (int)p;
-        }
-        exx_status st2 = dev_reserve(c, h.v, (size_t)tot);
-        if (st2 != EXX_OK) return st2;
-        // h.off lives until this level is recycled, after the copy completes
-        if ((st2 = upload_async(c, c->d_hist_off, h.off, s, false)) != EXX_OK) return st2;
-        HIPCHK(c, launch_save_history(c->d_vout.p, c->d_off.p, c->d_hist_off.p, c->d_gc.p, c->cls[0].n_pe,
-                                      c->cls[1].n_pe, (int)c->n_pairs, h.v.p, s));
-        h.valid = true;
+        // rotate the ring: this step's level becomes the most recent; the
+        // PREVIOUS guess keeps one level, the extrapolations three
+        const int levels = c->prm.guess == EXX_GUESS_PREVIOUS ? 1 : 3;
+        exx_ctx::Hist spare = std::move(c->hist[levels - 1]);
+        for (int k = levels - 1; k > 0; --k) c->hist[k] = std::move(c->hist[k - 1]);
+        c->hist[0] = std::move(nx);
+        c->hist[0].valid = true;
+        c->hist_next = std::move(spare);
+        c->hist_next.valid = false;
     }
     c->phi = phi;
     c->state = 3;
@@ -1083,24 +1210,12 @@ exx_status exx_energy_potential(exx_ctx *c, double *e_xx, void *dxx, void *strea
     if (!e_xx || !dxx) return fail(c, EXX_EINVAL, "exx_energy_potential: e_xx and dxx are required");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
-    DxxArgs d{};
-    d.cls[0] = class_dev(c->cls[0]);
-    d.cls[1] = class_dev(c->cls[1]);
-    d.pair_gc = c->d_gc.p;
-    d.pair_ij = c->d_ij.p;
-    d.out_off = c->d_off.p;
-    d.orb_ptr = c->d_orb_ptr.p;
-    d.orb_pairs = c->d_orb_pairs.p;
-    d.phi = c->phi;
-    d.dxx = dxx;
-    d.f32 = c->prm.orbital_dtype == EXX_F32;
-    d.nx = c->prm.n_grid[0];
-    d.ny = c->prm.n_grid[1];
-    d.nz = c->prm.n_grid[2];
-    d.ngrid = (long long)d.nx * d.ny * d.nz;
-    d.vout = c->d_vout.p;
+    const DxxArgs d = dxx_args(c, c->phi, dxx);
     HIPCHK(c, hipEventRecord(c->ev[2], s));
-    HIPCHK(c, launch_dxx(d, c->n_orb, s));
+    if (c->n_waves > 1)
+        HIPCHK(c, launch_dxx_final(d, c->n_orb, s));   // D was summed wave by wave during the solve
+    else
+        HIPCHK(c, launch_dxx(d, c->n_orb, 0, s));
     HIPCHK(c, hipEventRecord(c->ev[3], s));
     HIPCHK(c, launch_energy(c->d_e.p, c->d_ij.p, (int)c->n_pairs, c->d_E.p, s));
     HIPCHK(c, hipEventRecord(c->ev[4], s));
@@ -1152,15 +1267,17 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
         st->n_not_converged += cv[p] ? 0 : 1;
         st->relres_max = std::max(st->relres_max, rr[p]);
         // algorithmic bytes per unknown: 8 vector passes per CG iteration,
-        // 32 B per FP64 residual pass (x, b, d in; x, r out) and 32 B for the
-        // closing pass (x, b and the two orbitals in)
-        const int64_t cg = (int64_t)k.n_pe * ((int64_t)it[p] * 8 * scg + (int64_t)ou[p] * 32 + 32);
+        // 32 B per FP64 residual pass (x, b, d in; x, r out) and 16 B for the
+        // closing residual pass (x, b in); the pair energy reads x and the
+        // two orbitals, the preparation the two orbitals (and writes b and
+        // the shell potential)
+        const int64_t cg = (int64_t)k.n_pe * ((int64_t)it[p] * 8 * scg + (int64_t)ou[p] * 32 + 16);
         st->cg_bytes += cg;
-        st->solve_bytes += cg + (int64_t)2 * k.n_pe * sphi + (int64_t)k.n_sh * 8;
+        st->solve_bytes += cg + (int64_t)k.n_pe * (2 * sphi + 8) + (int64_t)k.n_sh * 8 + (int64_t)k.n_pe * (8 + 2 * sphi);
         const int m = c->ij[p].x == c->ij[p].y ? 1 : 2;
         st->dxx_bytes += (int64_t)m * (k.n_pe + k.n_sh) * (8 + sphi);
     }
-    st->dxx_bytes += (int64_t)c->n_orb * c->prm.n_grid[0] * c->prm.n_grid[1] * c->prm.n_grid[2] * sphi;
+    st->dxx_bytes += (int64_t)c->n_orb * c->box_vol * sphi;
     float ms = 0.f;
     st->n_waves = c->n_waves;
     if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) st->solve_ms = ms;
@@ -1211,6 +1328,9 @@ exx_status exx_debug_pair(exx_ctx *c, int64_t pair, double *v_pe, double *v_shel
     if (pair < 0 || pair >= c->n_pairs) return fail(c, EXX_EINVAL, "pair %lld out of range", (long long)pair);
     if ((rho || rhs) && !c->prm.keep_intermediates)
         return fail(c, EXX_ESTATE, "exx_debug_pair: intermediates were not kept (keep_intermediates = 0)");
+    if ((v_pe || v_shell) && c->n_waves > 1 && pair < (int64_t)(c->n_waves - 1) * c->wave_n)
+        return fail(c, EXX_ESTATE, "exx_debug_pair: the potentials of pair %lld were released with its wave",
+                    (long long)pair);
     HIPCHK(c, hipSetDevice(c->device));
     HIPCHK(c, hipDeviceSynchronize());
     const HostClass &k = c->cls[c->gc[pair].w];
@@ -1327,6 +1447,19 @@ exx_status exx_model_wgrad(exx_ctx *c, int32_t layer, const void *x, const void 
     return EXX_OK;
 }
 
+exx_status exx_box_origins(exx_ctx *c, int32_t *origins)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_box_origins: ctx is NULL");
+    if (!origins) return fail(c, EXX_EINVAL, "exx_box_origins: origins is NULL");
+    if (c->state < 2) return fail(c, EXX_ESTATE, "exx_box_origins before exx_pairs");
+    for (int i = 0; i < c->n_orb; ++i) {
+        origins[3 * i] = c->box_org[i].x;
+        origins[3 * i + 1] = c->box_org[i].y;
+        origins[3 * i + 2] = c->box_org[i].z;
+    }
+    return EXX_OK;
+}
+
 int32_t exx_model_edge(const exx_ctx *c) { return c && c->net ? c->net_D : 0; }
 
 const char *exx_last_error(const exx_ctx *c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
@@ -1342,6 +1475,8 @@ void exx_destroy(exx_ctx *c)
     dev_free(c->d_rhs); dev_free(c->d_rho_keep);
     dev_free(c->d_guess); dev_free(c->d_hist_off);
     for (auto &h : c->hist) dev_free(h.v);
+    dev_free(c->hist_next.v);
+    dev_free(c->d_box_org); dev_free(c->d_dacc);
     net_destroy(c->net);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);

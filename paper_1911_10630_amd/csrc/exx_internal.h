@@ -74,12 +74,37 @@ __device__ __forceinline__ int sh_index(const ClassDev &g, int x, int y, int z)
     return a.w + (x < a.y ? x - b.x : (a.y - b.x) + (x - a.z - 1));
 }
 
+// Orbital storage: orbital k lives on the periodic box [org_k, org_k + b)
+// of the grid, layout [n_orb][bz][by][bx], x fastest; outside its box an
+// orbital is zero.  The whole grid is the box with org = 0, b = N.
+struct OrbBox {
+    const int4 *org;            // [n_orb] box origin (grid point)
+    int bx, by, bz;
+    long long vol;              // bx * by * bz
+};
+
+// Value of orbital k (base = k * vol, origin o) at grid point (gx, gy, gz).
+// Branch-free: points outside the box load element 0 and select zero.
+__device__ __forceinline__ double load_orb(const void *phi, int f32, const OrbBox &B, long long base, int4 o, int gx,
+                                           int gy, int gz, int nx, int ny, int nz)
+{
+    int lx = gx - o.x, ly = gy - o.y, lz = gz - o.z;
+    lx += lx < 0 ? nx : 0;
+    ly += ly < 0 ? ny : 0;
+    lz += lz < 0 ? nz : 0;
+    const bool in = lx < B.bx && ly < B.by && lz < B.bz;
+    const long long idx = in ? base + ((long long)lz * B.by + ly) * B.bx + lx : 0;
+    const double v = f32 ? (double)static_cast<const float *>(phi)[idx] : static_cast<const double *>(phi)[idx];
+    return in ? v : 0.0;
+}
+
 struct SolveArgs {
     ClassDev cls[2];
     const int4 *pair_gc;        // [n_pairs] {gx, gy, gz, class}
     const int2 *pair_ij;        // [n_pairs] {i, j}
-    const long long *out_off;   // [n_pairs] offset of the pair's v in vout
-    const void *phi;            // [n_orb][Nz][Ny][Nx]
+    const long long *out_off;   // [n_pairs] offset of the pair's v in vout (relative to its wave)
+    const void *phi;            // [n_orb][bz][by][bx] on the orbital boxes
+    OrbBox box;
     int phi_f32;
     int nx, ny, nz;
     long long ngrid;
@@ -134,7 +159,11 @@ struct DxxArgs {
     const int *orb_ptr;         // [n_orb + 1] CSR over orbitals
     const int *orb_pairs;       // pair indices, ascending per orbital
     const void *phi;
-    void *dxx;
+    OrbBox box;
+    void *dxx;                  // [n_orb][bz][by][bx]
+    double *acc;                // FP64 partial sums across waves (accumulating form)
+    int acc_first;              // 1: the first wave (partial sums start at 0)
+    int pair_lo, pair_hi;       // pairs of this wave
     int f32;
     int nx, ny, nz;
     long long ngrid;
@@ -143,6 +172,8 @@ struct DxxArgs {
 
 // Launchers (exx_kernels.hip).
 hipError_t launch_prep(const SolveArgs &a, hipStream_t s);
+// e_ij = h^3 sum rho x for the pairs of the wave (after their CG).
+hipError_t launch_pair_energy(const SolveArgs &a, hipStream_t s);
 // Persistent CG kernels: "flat" (any sphere) and "zmarch" (register queue,
 // needs the LDS plane to fit).  Variants are (block, columns per thread).
 struct CgVariant {
@@ -160,12 +191,17 @@ int cg_variants(CgVariant *out, int max_n);
 int cg_mode(int precision, int guess);
 hipError_t cg_occupancy(const CgVariant &v, int mode, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t lds_bytes, hipStream_t s);
-hipError_t launch_dxx(const DxxArgs &a, int n_orb, hipStream_t s);
+// D from the pairs [pair_lo, pair_hi): written to dxx (accumulate = 0) or
+// added to the FP64 partial sums acc (accumulate = 1); launch_dxx_final
+// converts acc to dxx.
+hipError_t launch_dxx(const DxxArgs &a, int n_orb, int accumulate, hipStream_t s);
+hipError_t launch_dxx_final(const DxxArgs &a, int n_orb, hipStream_t s);
 hipError_t launch_energy(const double *e, const int2 *ij, int n_pairs, double *out, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
 hipError_t launch_guess(const GuessArgs &a, int n_pairs, hipStream_t s);
 hipError_t launch_save_history(const double *vout, const long long *out_off, const long long *hist_off,
-                               const int4 *pair_gc, int n_pe0, int n_pe1, int n_pairs, float *hist, hipStream_t s);
+                               const int4 *pair_gc, int n_pe0, int n_pe1, int wave_begin, int wave_n, float *hist,
+                               hipStream_t s);
 
 // Learned initial guess (exx_net.hip).  The net reads a pair's right-hand
 // side on a coarse cube (coarsening factor f, edge D coarse cells, fine

@@ -14,6 +14,8 @@
 //   k_energy  E_xx = -sum w_ij e_ij in pair order, one work-group.
 #include "exx_internal.h"
 
+#include <algorithm>
+
 namespace exx {
 
 // ---------------------------------------------------------------------------
@@ -24,11 +26,6 @@ __device__ __forceinline__ int wrap_n(int v, int n)
 {
     v = v < 0 ? v + n : v;
     return v >= n ? v - n : v;
-}
-
-__device__ __forceinline__ double load_phi(const void *phi, int f32, long long idx)
-{
-    return f32 ? (double)(static_cast<const float *>(phi)[idx]) : static_cast<const double *>(phi)[idx];
 }
 
 // Unnormalized real regular solid harmonics U_lm(x, y, z), index l*l + l + m:
@@ -120,10 +117,14 @@ __device__ __forceinline__ void fd_weights(const SolveArgs &a, double (&w)[3][4]
     }
 }
 
-__device__ __forceinline__ long long grid_index(const SolveArgs &a, const int4 &pg, int x, int y, int z)
+// rho_ij at offset (x, y, z) from the pair origin (Eq. l2g): the two
+// orbitals read from their boxes at the wrapped grid point.
+__device__ __forceinline__ double pair_rho(const SolveArgs &a, const int4 &pg, long long oi, long long oj, int4 org_i,
+                                           int4 org_j, int x, int y, int z)
 {
     const int gx = wrap_n(pg.x + x, a.nx), gy = wrap_n(pg.y + y, a.ny), gz = wrap_n(pg.z + z, a.nz);
-    return ((long long)gz * a.ny + gy) * a.nx + gx;
+    return load_orb(a.phi, a.phi_f32, a.box, oi, org_i, gx, gy, gz, a.nx, a.ny, a.nz) *
+           load_orb(a.phi, a.phi_f32, a.box, oj, org_j, gx, gy, gz, a.nx, a.ny, a.nz);
 }
 
 constexpr int PREP_BLOCK = 256;
@@ -145,7 +146,8 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep(SolveArgs a)
     double *bv = a.rhs + (long long)blockIdx.x * a.slot_n;
     double *keep = a.rho_keep ? a.rho_keep + (long long)pair * a.slot_n : nullptr;
     const double hx = a.h[0], hy = a.h[1], hz = a.h[2];
-    const long long oi = (long long)ij.x * a.ngrid, oj = (long long)ij.y * a.ngrid;
+    const long long oi = (long long)ij.x * a.box.vol, oj = (long long)ij.y * a.box.vol;
+    const int4 org_i = a.box.org[ij.x], org_j = a.box.org[ij.y];
     double w[3][4];
     fd_weights(a, w);
 
@@ -155,8 +157,7 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep(SolveArgs a)
     for (int q = tid; q < g.n_pe; q += PREP_BLOCK) {
         int x, y, z;
         unpack_xyz(g.pe_xyz[q], x, y, z);
-        const long long gi = grid_index(a, pg, x, y, z);
-        const double rv = load_phi(a.phi, a.phi_f32, oi + gi) * load_phi(a.phi, a.phi_f32, oj + gi);
+        const double rv = pair_rho(a, pg, oi, oj, org_i, org_j, x, y, z);
         bv[q] = rv;
         if (keep) keep[q] = rv;
         double U[NLM];
@@ -286,23 +287,16 @@ __device__ void cg_one_pair(const SolveArgs &a, int pair, long long slot, double
         ++k;
     }
 
-    // pair energy with the re-gathered density (Step V, Eq. exx_omega) and the
-    // true residual ||b - A x|| / ||b||
-    const long long oi = (long long)ij.x * a.ngrid, oj = (long long)ij.y * a.ngrid;
-    double e = 0.0, res = 0.0;
+    // true residual ||b - A x|| / ||b|| (the pair energy is k_pair_energy's)
+    double res = 0.0;
     for (int q = tid; q < n; q += BLOCK) {
         int x, y, z;
         unpack_xyz(g.pe_xyz[q], x, y, z);
-        const long long gi = grid_index(a, pg, x, y, z);
-        const double rv = load_phi(a.phi, a.phi_f32, oi + gi) * load_phi(a.phi, a.phi_f32, oj + gi);
-        e += rv * xv[q];
         const double d = bv[q] - apply_A_flat(g, xv, q, x, y, z, w);
         res += d * d;
     }
-    e = block_sum<BLOCK>(e, red);
     res = block_sum<BLOCK>(res, red);
     if (tid == 0) {
-        a.e_out[pair] = e * (a.h[0] * a.h[1] * a.h[2]);
         a.iters_out[pair] = k;
         a.outer_out[pair] = 0;
         a.conv_out[pair] = conv;
@@ -677,19 +671,16 @@ struct PRes {
     }
 };
 
-// final pass: true residual b - A x and energy sum rho x with rho re-gathered
+// final pass: true residual b - A x
 template <int K, int KH>
 struct PFin {
     const double *x, *b;
-    const void *phi;
-    long long oi, oj;
-    int f32, nx, ny;
-    double e = 0.0, res = 0.0;
+    double res = 0.0;
     double fx[K];
     int fa[K];
     double hx[KH];
     int ha[KH];
-    double ob[K], opi[K], opj[K];
+    double ob[K];
     int oa[K];
     __device__ __forceinline__ void fetch_own(int k, int a)
     {
@@ -703,20 +694,15 @@ struct PFin {
         hx[j] = raw_load(x, a);
     }
     __device__ __forceinline__ double fin_halo(int j) { return ha[j] >= 0 ? hx[j] : 0.0; }
-    __device__ __forceinline__ void fetch_out(int k, int a, int gx, int gy, int gz)
+    __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
     {
         oa[k] = a;
         ob[k] = raw_load(b, a);
-        const long long gi = ((long long)gz * ny + gy) * nx + gx;
-        opi[k] = load_phi(phi, f32, oi + gi);
-        opj[k] = load_phi(phi, f32, oj + gi);
     }
-    __device__ __forceinline__ void output(int k, double u, double Au)
+    __device__ __forceinline__ void output(int k, double, double Au)
     {
-        const bool ok = oa[k] >= 0;
-        const double t = ok ? ob[k] - Au : 0.0;
+        const double t = oa[k] >= 0 ? ob[k] - Au : 0.0;
         res += t * t;
-        e += ok ? opi[k] * opj[k] * u : 0.0;
     }
 };
 
@@ -865,12 +851,10 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         }
     }
 
-    PFin<K, KH> pf{x, b, a.phi, (long long)ij.x * a.ngrid, (long long)ij.y * a.ngrid, a.phi_f32, a.nx, a.ny};
+    PFin<K, KH> pf{x, b};
     zmarch<double, T, K, KH>(g, lds, par, pf, w64, pg, a.nx, a.ny, a.nz);
-    const double e = block_sum<T>(pf.e, red);
     const double res = block_sum<T>(pf.res, red);
     if (tid == 0) {
-        a.e_out[pair] = e * (a.h[0] * a.h[1] * a.h[2]);
         a.iters_out[pair] = it;
         a.outer_out[pair] = outer;
         a.conv_out[pair] = conv;
@@ -907,6 +891,31 @@ __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
 }
 
 // ---------------------------------------------------------------------------
+// pair energy (Step V, Eq. exx_omega): e_ij = h^3 sum_PE rho_ij x, rho_ij
+// re-gathered from the orbital boxes.  One work-group per pair of the wave.
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(PREP_BLOCK) void k_pair_energy(SolveArgs a)
+{
+    __shared__ double red[PREP_BLOCK / 64];
+    const int pair = a.wave_begin + blockIdx.x;
+    const int4 pg = a.pair_gc[pair];
+    const int2 ij = a.pair_ij[pair];
+    const ClassDev &g = pg.w ? a.cls[1] : a.cls[0];
+    const double *x = a.vout + a.out_off[pair];
+    const long long oi = (long long)ij.x * a.box.vol, oj = (long long)ij.y * a.box.vol;
+    const int4 org_i = a.box.org[ij.x], org_j = a.box.org[ij.y];
+    double e = 0.0;
+    for (int q = threadIdx.x; q < g.n_pe; q += PREP_BLOCK) {
+        int ox, oy, oz;
+        unpack_xyz(g.pe_xyz[q], ox, oy, oz);
+        e += pair_rho(a, pg, oi, oj, org_i, org_j, ox, oy, oz) * x[q];
+    }
+    e = block_sum<PREP_BLOCK>(e, red);
+    if (threadIdx.x == 0) a.e_out[pair] = e * (a.h[0] * a.h[1] * a.h[2]);
+}
+
+// ---------------------------------------------------------------------------
 // D accumulation: owner computes, pair order, no atomics
 // ---------------------------------------------------------------------------
 
@@ -914,33 +923,45 @@ constexpr int DXX_BLOCK = 256;
 constexpr int DXX_PER_THREAD = 4;
 constexpr int DXX_TILE = DXX_BLOCK * DXX_PER_THREAD;
 
-template <typename TO>
+template <typename TO, bool ACC>
 __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
 {
     const int k = blockIdx.y;
     const long long t0 = (long long)blockIdx.x * DXX_TILE;
+    const OrbBox &B = a.box;
+    const int4 ok_org = B.org[k];
     double acc[DXX_PER_THREAD];
     int gx[DXX_PER_THREAD], gy[DXX_PER_THREAD], gz[DXX_PER_THREAD];
     bool ok[DXX_PER_THREAD];
 #pragma unroll
     for (int e = 0; e < DXX_PER_THREAD; ++e) {
-        const long long gi = t0 + e * DXX_BLOCK + threadIdx.x;
-        ok[e] = gi < a.ngrid;
-        const long long gl = ok[e] ? gi : 0;
-        gx[e] = (int)(gl % a.nx);
-        gy[e] = (int)((gl / a.nx) % a.ny);
-        gz[e] = (int)(gl / ((long long)a.nx * a.ny));
-        acc[e] = 0.0;
+        const long long li = t0 + e * DXX_BLOCK + threadIdx.x;
+        ok[e] = li < B.vol;
+        const long long ll = ok[e] ? li : 0;
+        gx[e] = wrap_n(ok_org.x + (int)(ll % B.bx), a.nx);
+        gy[e] = wrap_n(ok_org.y + (int)((ll / B.bx) % B.by), a.ny);
+        gz[e] = wrap_n(ok_org.z + (int)(ll / ((long long)B.bx * B.by)), a.nz);
+        acc[e] = ACC && !a.acc_first && ok[e] ? a.acc[(long long)k * B.vol + li] : 0.0;
     }
-    const int pb = a.orb_ptr[k], pe = a.orb_ptr[k + 1];
-    for (int pp = pb; pp < pe; ++pp) {
+    // this orbital's pairs inside [pair_lo, pair_hi): its list is ascending
+    int lo = a.orb_ptr[k], hi = a.orb_ptr[k + 1];
+    {
+        int l = lo, r = hi;
+        while (l < r) { const int m = (l + r) >> 1; if (a.orb_pairs[m] < a.pair_lo) l = m + 1; else r = m; }
+        int l2 = l, r2 = hi;
+        while (l2 < r2) { const int m = (l2 + r2) >> 1; if (a.orb_pairs[m] < a.pair_hi) l2 = m + 1; else r2 = m; }
+        lo = l;
+        hi = l2;
+    }
+    for (int pp = lo; pp < hi; ++pp) {
         const int pair = a.orb_pairs[pp];
         const int4 pg = a.pair_gc[pair];
         const int2 ij = a.pair_ij[pair];
         const int other = ij.x == k ? ij.y : ij.x;
         const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
         const double *v = a.vout + a.out_off[pair];
-        const long long oo = (long long)other * a.ngrid;
+        const long long oo = (long long)other * B.vol;
+        const int4 oo_org = B.org[other];
 #pragma unroll
         for (int e = 0; e < DXX_PER_THREAD; ++e) {
             if (!ok[e]) continue;
@@ -959,16 +980,26 @@ __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
                 vv = v[r0.x + ox - r0.y];
             else
                 vv = v[g.n_pe + r0.w + (ox < r0.y ? ox - r1.x : (r0.y - r1.x) + (ox - r0.z - 1))];
-            const long long gi = t0 + e * DXX_BLOCK + threadIdx.x;
-            acc[e] += vv * load_phi(a.phi, a.f32, oo + gi);
+            acc[e] += vv * load_orb(a.phi, a.f32, B, oo, oo_org, gx[e], gy[e], gz[e], a.nx, a.ny, a.nz);
         }
     }
-    TO *out = static_cast<TO *>(a.dxx) + (long long)k * a.ngrid;
 #pragma unroll
     for (int e = 0; e < DXX_PER_THREAD; ++e) {
-        const long long gi = t0 + e * DXX_BLOCK + threadIdx.x;
-        if (ok[e]) out[gi] = (TO)acc[e];
+        const long long li = t0 + e * DXX_BLOCK + threadIdx.x;
+        if (!ok[e]) continue;
+        if (ACC)
+            a.acc[(long long)k * B.vol + li] = acc[e];
+        else
+            static_cast<TO *>(a.dxx)[(long long)k * B.vol + li] = (TO)acc[e];
     }
+}
+
+// dxx = the FP64 partial sums, rounded to the orbital dtype.
+template <typename TO>
+__global__ void k_dxx_final(const double *acc, TO *dxx, long long n)
+{
+    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
+        dxx[t] = (TO)acc[t];
 }
 
 // ---------------------------------------------------------------------------
@@ -1002,9 +1033,9 @@ __global__ __launch_bounds__(256) void k_guess(GuessArgs a)
 // hist[hist_off[p] + q] = v_p on PE (FP32), for every pair.
 __global__ __launch_bounds__(256) void k_save_history(const double *vout, const long long *out_off,
                                                       const long long *hist_off, const int4 *pair_gc, int n_pe0,
-                                                      int n_pe1, float *hist)
+                                                      int n_pe1, int wave_begin, float *hist)
 {
-    const int p = blockIdx.x;
+    const int p = wave_begin + blockIdx.x;
     const int n = pair_gc[p].w ? n_pe1 : n_pe0;
     const double *src = vout + out_off[p];
     float *dst = hist + hist_off[p];
@@ -1105,19 +1136,38 @@ hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t ld
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_pair_energy(const SolveArgs &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_pair_energy, dim3(a.wave_n), dim3(PREP_BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_prep(const SolveArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_prep, dim3(a.wave_n), dim3(PREP_BLOCK), 0, s, a);
     return hipGetLastError();
 }
 
-hipError_t launch_dxx(const DxxArgs &a, int n_orb, hipStream_t s)
+hipError_t launch_dxx(const DxxArgs &a, int n_orb, int accumulate, hipStream_t s)
 {
-    const dim3 grid((unsigned)((a.ngrid + DXX_TILE - 1) / DXX_TILE), (unsigned)n_orb);
-    if (a.f32)
-        hipLaunchKernelGGL(k_dxx<float>, grid, dim3(DXX_BLOCK), 0, s, a);
+    const dim3 grid((unsigned)((a.box.vol + DXX_TILE - 1) / DXX_TILE), (unsigned)n_orb);
+    if (accumulate)
+        hipLaunchKernelGGL((k_dxx<double, true>), grid, dim3(DXX_BLOCK), 0, s, a);
+    else if (a.f32)
+        hipLaunchKernelGGL((k_dxx<float, false>), grid, dim3(DXX_BLOCK), 0, s, a);
     else
-        hipLaunchKernelGGL(k_dxx<double>, grid, dim3(DXX_BLOCK), 0, s, a);
+        hipLaunchKernelGGL((k_dxx<double, false>), grid, dim3(DXX_BLOCK), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dxx_final(const DxxArgs &a, int n_orb, hipStream_t s)
+{
+    const long long n = (long long)n_orb * a.box.vol;
+    const dim3 grid((unsigned)std::min<long long>((n + 255) / 256, 1LL << 20));
+    if (a.f32)
+        hipLaunchKernelGGL(k_dxx_final<float>, grid, dim3(256), 0, s, a.acc, static_cast<float *>(a.dxx), n);
+    else
+        hipLaunchKernelGGL(k_dxx_final<double>, grid, dim3(256), 0, s, a.acc, static_cast<double *>(a.dxx), n);
     return hipGetLastError();
 }
 
@@ -1134,10 +1184,11 @@ hipError_t launch_guess(const GuessArgs &a, int n_pairs, hipStream_t s)
 }
 
 hipError_t launch_save_history(const double *vout, const long long *out_off, const long long *hist_off,
-                               const int4 *pair_gc, int n_pe0, int n_pe1, int n_pairs, float *hist, hipStream_t s)
+                               const int4 *pair_gc, int n_pe0, int n_pe1, int wave_begin, int wave_n, float *hist,
+                               hipStream_t s)
 {
-    hipLaunchKernelGGL(k_save_history, dim3(n_pairs), dim3(256), 0, s, vout, out_off, hist_off, pair_gc, n_pe0,
-                       n_pe1, hist);
+    hipLaunchKernelGGL(k_save_history, dim3(wave_n), dim3(256), 0, s, vout, out_off, hist_off, pair_gc, n_pe0, n_pe1,
+                       wave_begin, hist);
     return hipGetLastError();
 }
 

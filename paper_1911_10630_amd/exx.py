@@ -25,7 +25,8 @@ NLM = 49
 
 EXPORTS = ["exx_default_params", "exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats",
            "exx_pair_info", "exx_debug_pair", "exx_last_error", "exx_destroy", "exx_model_init", "exx_model_train",
-           "exx_model_save", "exx_load_model", "exx_model_edge", "exx_model_conv", "exx_model_wgrad"]
+           "exx_model_save", "exx_load_model", "exx_model_edge", "exx_model_conv", "exx_model_wgrad",
+           "exx_box_origins"]
 
 
 class ExxParams(C.Structure):
@@ -35,7 +36,8 @@ class ExxParams(C.Structure):
                 ("precision", C.c_int32), ("orbital_dtype", C.c_int32), ("guess", C.c_int32),
                 ("inner_rtol", C.c_double), ("block_threads", C.c_int32), ("cg_cols", C.c_int32),
                 ("wave_pairs", C.c_int64),
-                ("keep_intermediates", C.c_int32), ("autotune", C.c_int32), ("graph", C.c_int32)]
+                ("keep_intermediates", C.c_int32), ("autotune", C.c_int32), ("graph", C.c_int32),
+                ("box_dims", C.c_int32 * 3)]
 
 
 class ExxStats(C.Structure):
@@ -83,6 +85,7 @@ def load() -> C.CDLL:
     L.exx_last_error.restype = C.c_char_p
     L.exx_destroy.argtypes = [vp]
     L.exx_destroy.restype = None
+    L.exx_box_origins.argtypes = [vp, vp]
     L.exx_model_init.argtypes = [vp, i32, C.c_uint64]
     L.exx_model_train.argtypes = [vp, i32, i32, C.c_double, C.c_uint64, dp, vp]
     L.exx_model_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
@@ -93,7 +96,7 @@ def load() -> C.CDLL:
     L.exx_model_wgrad.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp]
     for f in ["exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats", "exx_pair_info",
               "exx_debug_pair", "exx_model_init", "exx_model_train", "exx_model_save", "exx_load_model",
-              "exx_model_conv", "exx_model_wgrad"]:
+              "exx_model_conv", "exx_model_wgrad", "exx_box_origins"]:
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
@@ -119,7 +122,7 @@ class Exx:
 
     def __init__(self, n_grid, cell, r_pair, r_pe, r_me, *, cg_rtol=1e-10, cg_max_iter=20000,
                  precision="fp64", orbital_dtype="f64", guess="zero", inner_rtol=1e-5, block_threads=0,
-                 cg_cols=0, wave_pairs=0, keep_intermediates=False, autotune=True, graph=False, device=0):
+                 cg_cols=0, wave_pairs=0, keep_intermediates=False, autotune=True, graph=False, box=None, device=0):
         L = load()
         p = ExxParams()
         L.exx_default_params(C.byref(p))
@@ -143,9 +146,13 @@ class Exx:
         p.keep_intermediates = 1 if keep_intermediates else 0
         p.autotune = 1 if autotune else 0
         p.graph = 1 if graph else 0
+        if box is not None:
+            for a in range(3):
+                p.box_dims[a] = int(box[a])
         self.params = p
         self.device = int(device)
         self.n_grid = tuple(int(v) for v in n_grid)
+        self.box = tuple(int(box[a]) if box is not None and box[a] > 0 else self.n_grid[a] for a in range(3))
         self.orbital_dtype = orbital_dtype
         h = C.c_void_p()
         st = L.exx_setup(C.byref(p), self.device, C.byref(h))
@@ -160,6 +167,8 @@ class Exx:
         kw.setdefault("cg_rtol", wl.cg_rtol)
         kw.setdefault("precision", wl.precision)
         kw.setdefault("orbital_dtype", wl.orbital_dtype)
+        if getattr(wl, "box", None) is not None:
+            kw.setdefault("box", wl.box)
         return cls(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, **kw)
 
     def _check(self, st):
@@ -177,9 +186,15 @@ class Exx:
     def _check_grid(self, t, name):
         import torch
         want = torch.float64 if self.orbital_dtype == "f64" else torch.float32
-        Nx, Ny, Nz = self.n_grid
-        if not t.is_cuda or t.dtype != want or not t.is_contiguous() or tuple(t.shape) != (self.n_orb, Nz, Ny, Nx):
-            raise ValueError(f"{name} must be a contiguous {want} CUDA tensor of shape {(self.n_orb, Nz, Ny, Nx)}")
+        bx, by, bz = self.box
+        if not t.is_cuda or t.dtype != want or not t.is_contiguous() or tuple(t.shape) != (self.n_orb, bz, by, bx):
+            raise ValueError(f"{name} must be a contiguous {want} CUDA tensor of shape {(self.n_orb, bz, by, bx)}")
+
+    def box_origins(self) -> np.ndarray:
+        """[n_orb][3] grid origins of the orbital boxes (zeros for whole-grid storage)."""
+        out = np.zeros((self.n_orb, 3), np.int32)
+        self._check(load().exx_box_origins(self._h, _ptr(out)))
+        return out
 
     def solve(self, phi, stream=None):
         self._check_grid(phi, "phi")

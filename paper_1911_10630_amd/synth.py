@@ -63,6 +63,7 @@ class Workload:
     precision: str = "fp64"  # "fp64" | "fp32_refine"
     md_steps: int = 1
     seed: int = 0
+    box: Optional[tuple] = None   # orbital storage box (bx, by, bz); None = whole grid
 
     @property
     def h(self) -> tuple:
@@ -91,14 +92,17 @@ def _min_image_1d(coord: np.ndarray, c: float, L: float) -> np.ndarray:
     return d - L * np.round(d / L)
 
 
-def orbital_values_np(orbs: OrbitalSet, k: int, n_grid, cell) -> np.ndarray:
-    """Grid values of orbital k, numpy float64, layout [Nz][Ny][Nx]."""
+def orbital_values_np(orbs: OrbitalSet, k: int, n_grid, cell, origin=(0, 0, 0), box=None) -> np.ndarray:
+    """Values of orbital k, numpy float64, layout [Nz][Ny][Nx]; or, with a
+    box (bx, by, bz) starting at grid point `origin`, on that periodic box
+    [bz][by][bx], normalized on the box (the orbital is zero outside it)."""
     Nx, Ny, Nz = n_grid
+    bx, by, bz = box if box is not None else (Nx, Ny, Nz)
     h = [cell[a] / n_grid[a] for a in range(3)]
     c = orbs.centers[k]
-    dx = _min_image_1d(np.arange(Nx) * h[0], c[0], cell[0])[None, None, :]
-    dy = _min_image_1d(np.arange(Ny) * h[1], c[1], cell[1])[None, :, None]
-    dz = _min_image_1d(np.arange(Nz) * h[2], c[2], cell[2])[:, None, None]
+    dx = _min_image_1d(((origin[0] + np.arange(bx)) % Nx) * h[0], c[0], cell[0])[None, None, :]
+    dy = _min_image_1d(((origin[1] + np.arange(by)) % Ny) * h[1], c[1], cell[1])[None, :, None]
+    dz = _min_image_1d(((origin[2] + np.arange(bz)) % Nz) * h[2], c[2], cell[2])[:, None, None]
     al = orbs.alpha[k]
     g = np.exp(-al * dx * dx) * np.exp(-al * dy * dy) * np.exp(-al * dz * dz)
     if orbs.kind[k] == 1:
@@ -114,18 +118,47 @@ def orbital_values_np(orbs: OrbitalSet, k: int, n_grid, cell) -> np.ndarray:
     return phi / nrm
 
 
-def orbitals_np(wl: Workload, idx: Optional[Sequence[int]] = None) -> np.ndarray:
-    """All (or selected) orbitals as numpy float64 [n][Nz][Ny][Nx]."""
+def orbitals_np(wl: Workload, idx: Optional[Sequence[int]] = None, origins=None) -> np.ndarray:
+    """All (or selected) orbitals as numpy float64 [n][Nz][Ny][Nx], or on the
+    workload's boxes [n][bz][by][bx] given the box origins [n_orb][3]."""
     idx = range(wl.orbitals.n) if idx is None else idx
-    Nx, Ny, Nz = wl.n_grid
-    out = np.empty((len(idx), Nz, Ny, Nx), dtype=np.float64)
+    box = wl.box if origins is not None else None
+    bx, by, bz = box if box is not None else wl.n_grid
+    out = np.empty((len(idx), bz, by, bx), dtype=np.float64)
     for o, k in enumerate(idx):
-        out[o] = orbital_values_np(wl.orbitals, k, wl.n_grid, wl.cell)
+        org = tuple(origins[k]) if origins is not None else (0, 0, 0)
+        out[o] = orbital_values_np(wl.orbitals, k, wl.n_grid, wl.cell, org, box)
     return out
 
 
-def orbitals_torch(wl: Workload, device="cpu", dtype=None):
-    """All orbitals as a torch tensor [n][Nz][Ny][Nx] on `device`.
+def embed_boxes(vals: np.ndarray, origins, n_grid) -> np.ndarray:
+    """Box arrays [n][bz][by][bx] placed (periodically) into zero grids [n][Nz][Ny][Nx]."""
+    Nx, Ny, Nz = n_grid
+    n, bz, by, bx = vals.shape
+    out = np.zeros((n, Nz, Ny, Nx), dtype=vals.dtype)
+    for k in range(n):
+        ox, oy, oz = (int(v) for v in origins[k])
+        ix = (ox + np.arange(bx)) % Nx
+        iy = (oy + np.arange(by)) % Ny
+        iz = (oz + np.arange(bz)) % Nz
+        out[k][np.ix_(iz, iy, ix)] = vals[k]
+    return out
+
+
+def extract_boxes(full: np.ndarray, origins, box) -> np.ndarray:
+    """The inverse of embed_boxes: box arrays cut (periodically) from grids."""
+    n, Nz, Ny, Nx = full.shape
+    bx, by, bz = box
+    out = np.empty((n, bz, by, bx), dtype=full.dtype)
+    for k in range(n):
+        ox, oy, oz = (int(v) for v in origins[k])
+        out[k] = full[k][np.ix_((oz + np.arange(bz)) % Nz, (oy + np.arange(by)) % Ny, (ox + np.arange(bx)) % Nx)]
+    return out
+
+
+def orbitals_torch(wl: Workload, device="cpu", dtype=None, origins=None):
+    """All orbitals as a torch tensor [n][Nz][Ny][Nx] on `device`, or on the
+    workload's boxes [n][bz][by][bx] given the box origins [n_orb][3].
 
     Values are evaluated in float64 with the same formula as
     :func:`orbital_values_np` and cast to `dtype` at the end.
@@ -135,21 +168,23 @@ def orbitals_torch(wl: Workload, device="cpu", dtype=None):
     dtype = dtype or (torch.float64 if wl.orbital_dtype == "f64" else torch.float32)
     orbs = wl.orbitals
     Nx, Ny, Nz = wl.n_grid
+    bx, by, bz = wl.box if origins is not None else (Nx, Ny, Nz)
     h = wl.h
-    out = torch.empty((orbs.n, Nz, Ny, Nx), dtype=dtype, device=device)
-    ax = torch.arange(Nx, dtype=f64, device=device) * h[0]
-    ay = torch.arange(Ny, dtype=f64, device=device) * h[1]
-    az = torch.arange(Nz, dtype=f64, device=device) * h[2]
+    out = torch.empty((orbs.n, bz, by, bx), dtype=dtype, device=device)
 
     def mi(coord, c, L):
         d = coord - c
         return d - L * torch.round(d / L)
 
+    def axis(o, b, N, hh):
+        return ((o + torch.arange(b, device=device)) % N).to(f64) * hh
+
     for k in range(orbs.n):
         c = orbs.centers[k]
-        dx = mi(ax, float(c[0]), wl.cell[0]).view(1, 1, Nx)
-        dy = mi(ay, float(c[1]), wl.cell[1]).view(1, Ny, 1)
-        dz = mi(az, float(c[2]), wl.cell[2]).view(Nz, 1, 1)
+        o = origins[k] if origins is not None else (0, 0, 0)
+        dx = mi(axis(int(o[0]), bx, Nx, h[0]), float(c[0]), wl.cell[0]).view(1, 1, bx)
+        dy = mi(axis(int(o[1]), by, Ny, h[1]), float(c[1]), wl.cell[1]).view(1, by, 1)
+        dz = mi(axis(int(o[2]), bz, Nz, h[2]), float(c[2]), wl.cell[2]).view(bz, 1, 1)
         al = float(orbs.alpha[k])
         g = torch.exp(-al * dx * dx) * torch.exp(-al * dy * dy) * torch.exp(-al * dz * dz)
         if orbs.kind[k] == 1:
@@ -253,11 +288,24 @@ def c4_water128(seed: int = 128) -> Workload:
 
 
 def c5_water512(seed: int = 512) -> Workload:
-    """512 H2O (2048 orbitals), 24.8 A cube, 256^3, FP32 orbitals, two subdomain classes."""
+    """512 H2O (2048 orbitals), 24.8 A cube, 256^3, FP32 orbitals on 160^3
+    local boxes, two subdomain classes."""
     rpe_ns = 4.0 * ANG * 5.0 / 6.0
     return _water("water512-256^3-uneven", 8, 24.8, 256, False, seed,
                   r_pe=(4.0 * ANG, rpe_ns), r_me=(5.0 * ANG, rpe_ns + 1.0 * ANG),
-                  orbital_dtype="f32", precision="fp32_refine", md_steps=5)
+                  orbital_dtype="f32", precision="fp32_refine", md_steps=5, box=(160, 160, 160))
+
+
+def c1_boxed(seed: int = 4321) -> Workload:
+    """16 orbitals in a 20 A cube (96^3 grid, the small workload's spacing),
+    R_pair 4.5 A, stored on 76^3 local boxes: the small-scale check of
+    box storage."""
+    L = 20.0 * ANG
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(0.0, L, size=(16, 3))
+    orbs = draw_orbital_shapes(rng, C)
+    return Workload("boxed16-96^3", (96, 96, 96), (L, L, L), orbs, 4.5 * ANG, (4.0 * ANG, 4.0 * ANG),
+                    (5.0 * ANG, 5.0 * ANG), seed=seed, box=(76, 76, 76))
 
 
 def md_displace(orbs: OrbitalSet, L: float, rng, sigma_ang: float = 0.02) -> OrbitalSet:
