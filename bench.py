@@ -38,7 +38,21 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def cpu_baseline(wl, pi, pj, n_sample, threads, seed=0):
+def oracle_orbitals(wl, idx, origins):
+    """The orbitals the GPU sees, as full FP64 grids for the oracle: box
+    values placed into zero grids (box storage), rounded to FP32 first when
+    the workload stores FP32."""
+    from paper_1911_10630_amd import synth as S
+    if origins is None:
+        vals = S.orbitals_np(wl, idx)
+    else:
+        vals = S.embed_boxes(S.orbitals_np(wl, idx, origins=origins), [origins[k] for k in idx], wl.n_grid)
+    if wl.orbital_dtype == "f32":
+        vals = vals.astype(np.float32).astype(np.float64)
+    return vals
+
+
+def cpu_baseline(wl, pi, pj, n_sample, threads, seed=0, origins=None):
     """FP64 oracle on a stratified sample of the workload's pairs."""
     from oracle import oracle as O
     from paper_1911_10630_amd import synth as S
@@ -49,7 +63,7 @@ def cpu_baseline(wl, pi, pj, n_sample, threads, seed=0):
     pick = np.concatenate([rng.choice(self_idx, n_self, replace=False),
                            rng.choice(ns_idx, n_sample - n_self, replace=False)])
     orbs = sorted(set(pi[pick].tolist()) | set(pj[pick].tolist()))
-    phis = dict(zip(orbs, S.orbitals_np(wl, orbs)))
+    phis = dict(zip(orbs, oracle_orbitals(wl, orbs, origins)))
     t0 = time.perf_counter()
     res = O.solve_pairs(wl.n_grid, wl.cell, wl.r_pe, wl.r_me, wl.orbitals.centers, phis, pi[pick], pj[pick],
                         tol=wl.cg_rtol, nthreads=threads)
@@ -74,8 +88,8 @@ def train_model(args, wl, ctx):
         wl_k = S.WORKLOADS[args.workload](seed=9001 + k)
         if args.precision:
             wl_k.precision = args.precision
-        phi = S.orbitals_torch(wl_k, device=dev)
         n = ctx.pairs(wl_k.orbitals.centers)
+        phi = S.orbitals_torch(wl_k, device=dev, origins=ctx.box_origins() if wl_k.box else None)
         ctx.step(phi)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -109,18 +123,25 @@ def md_run(args, wl):
     steps = []
     t_all = 0.0
     n_all = 0
+    # orbitals and D first: the pair waves are sized from the memory left
+    shape = (orbs.n,) + tuple(reversed(wl.box or wl.n_grid))
+    phi = torch.empty(shape, dtype=torch.float64 if wl.orbital_dtype == "f64" else torch.float32, device=dev)
+    dxx = torch.empty_like(phi)
     for k in range(args.md_steps):
         wl_k = S.Workload(wl.name, wl.n_grid, wl.cell, orbs, wl.r_pair, wl.r_pe, wl.r_me,
-                          orbital_dtype=wl.orbital_dtype, precision=wl.precision)
-        phi = S.orbitals_torch(wl_k, device=dev)
-        dxx = torch.empty_like(phi)
+                          orbital_dtype=wl.orbital_dtype, precision=wl.precision, box=wl.box)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         n = ctx.pairs(orbs.centers)
+        t_pairs = time.perf_counter() - t0
+        # the step's orbitals (input, not timed): on their boxes when stored so
+        S.orbitals_torch(wl_k, device=dev, origins=ctx.box_origins() if wl.box else None, out=phi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         ctx.solve(phi, stream)
         E = ctx.energy_potential(dxx, stream)
         torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        dt = t_pairs + time.perf_counter() - t0
         st = ctx.stats()
         steps.append(dict(step=k, n_pairs=n, seconds=round(dt, 3), iters_mean=round(st["iters_total"] / n, 2),
                           outer_mean=round(st["outer_total"] / n, 2), cg_ms=round(st["cg_ms"], 1),
@@ -130,7 +151,6 @@ def md_run(args, wl):
             t_all += dt
             n_all += n
         orbs = S.md_displace(orbs, wl.cell[0], rng)
-        del phi, dxx
     line = dict(metric="pair Poisson solves/s (MD steps 1..)", value=round(n_all / t_all, 2) if t_all else None,
                 unit="pair Poisson solves/s", n_gpus=1, steps=args.md_steps, warmup=1, higher_is_better=True,
                 dtype="f64" if wl.precision == "fp64" else "f32+f64", data="synthetic",
@@ -196,15 +216,21 @@ def main():
     if args.md_steps:
         return md_run(args, wl)
     dev = torch.device("cuda:0")
-    log(f"[bench] workload {wl.name}: generating {wl.orbitals.n} orbitals on {dev}")
-    phi = S.orbitals_torch(wl, device=dev)
     guess = "learned" if args.guess == "learned" else "zero"
     ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols, inner_rtol=args.inner_rtol,
                               guess=guess, graph=args.graph)
     learned = train_model(args, wl, ctx) if guess == "learned" else None
-    n_pairs = ctx.pairs(wl.orbitals.centers)
-    info = ctx.pair_info(results=False)
+    # orbitals and D first: the pair waves are sized from the memory left
+    shape = (wl.orbitals.n,) + tuple(reversed(wl.box or wl.n_grid))
+    fdt = torch.float64 if wl.orbital_dtype == "f64" else torch.float32
+    phi = torch.empty(shape, dtype=fdt, device=dev)
     dxx = torch.empty_like(phi)
+    n_pairs = ctx.pairs(wl.orbitals.centers)
+    origins = ctx.box_origins() if wl.box else None
+    log(f"[bench] workload {wl.name}: generating {wl.orbitals.n} orbitals on {dev}"
+        + (f" on {wl.box} boxes" if wl.box else ""))
+    S.orbitals_torch(wl, device=dev, origins=origins, out=phi)
+    info = ctx.pair_info(results=False)
     stream = torch.cuda.current_stream(dev)
     log(f"[bench] {n_pairs} pairs; warmup {args.warmup}")
     for _ in range(args.warmup):
@@ -268,7 +294,7 @@ def main():
         n_sample = args.cpu_sample or 2 * threads
         n_sample = min(n_sample, n_pairs)
         log(f"[bench] CPU oracle baseline: {n_sample} pairs on {threads} threads")
-        cb, pick, res = cpu_baseline(wl, info["i"], info["j"], n_sample, threads)
+        cb, pick, res = cpu_baseline(wl, info["i"], info["j"], n_sample, threads, origins=origins)
         line["cpu_baseline"] = cb
         pinfo = ctx.pair_info()
         rel = np.abs(pinfo["e"][pick] - res["e"]) / np.abs(res["e"])

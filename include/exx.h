@@ -120,6 +120,7 @@ typedef struct {
     int64_t dxx_bytes;       /* algorithmic bytes of the D kernel               */
     int64_t device_bytes;    /* device memory held by the context              */
     int32_t n_waves;         /* pair waves of the last solve (1 = one launch)   */
+    int32_t wave_n;          /* pairs per wave (the last wave may hold fewer)   */
     int32_t guess_pairs;     /* pairs whose CG started from a non-zero guess    */
     double  guess_ms;        /* last solve: guess kernels / model inference     */
     int32_t tuned;           /* CG variants the set-up autotuner timed (0: none) */
@@ -144,8 +145,9 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out);
  * ordered by (i, j), the pair origins (grid point nearest the minimum-image
  * midpoint, Step III) and per-orbital pair lists, and sizes the per-pair
  * device buffers.  centers: host, [n_orb][3] bohr, copied.  *n_pairs
- * receives the pair count.  EXX_ENOMEM if the per-pair potentials do not fit
- * on the device. */
+ * receives the pair count.  The pairs are split into waves sized from the
+ * device memory free at this call (2 GiB kept free): allocate the orbital
+ * and D buffers before it.  EXX_ENOMEM if not even one pair fits. */
 exx_status exx_pairs(exx_ctx *ctx, int32_t n_orb, const double *centers, int64_t *n_pairs);
 
 /* Box origins chosen by exx_pairs, host [n_orb][3] grid points: origin =

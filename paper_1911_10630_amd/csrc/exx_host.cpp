@@ -1280,6 +1280,7 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     st->dxx_bytes += (int64_t)c->n_orb * c->box_vol * sphi;
     float ms = 0.f;
     st->n_waves = c->n_waves;
+    st->wave_n = c->wave_n;
     if (hipEventElapsedTime(&ms, c->ev[0], c->ev[1]) == hipSuccess) st->solve_ms = ms;
     st->prep_ms = st->cg_ms = st->guess_ms = -1.0;
     st->guess_pairs = c->guess_pairs;

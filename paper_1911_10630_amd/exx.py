@@ -48,7 +48,7 @@ class ExxStats(C.Structure):
                 ("solve_grid", C.c_int32), ("solve_block", C.c_int32), ("cg_cols", C.c_int32),
                 ("cg_bands", C.c_int32 * 2), ("outer_total", C.c_int64), ("n_pe", C.c_int64 * 2),
                 ("n_me", C.c_int64 * 2), ("cg_bytes", C.c_int64), ("solve_bytes", C.c_int64),
-                ("dxx_bytes", C.c_int64), ("device_bytes", C.c_int64), ("n_waves", C.c_int32),
+                ("dxx_bytes", C.c_int64), ("device_bytes", C.c_int64), ("n_waves", C.c_int32), ("wave_n", C.c_int32),
                 ("guess_pairs", C.c_int32), ("guess_ms", C.c_double), ("tuned", C.c_int32),
                 ("tune_ms", C.c_double), ("graph_builds", C.c_int32), ("graph_launches", C.c_int32)]
 

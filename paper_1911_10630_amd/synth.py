@@ -156,9 +156,10 @@ def extract_boxes(full: np.ndarray, origins, box) -> np.ndarray:
     return out
 
 
-def orbitals_torch(wl: Workload, device="cpu", dtype=None, origins=None):
+def orbitals_torch(wl: Workload, device="cpu", dtype=None, origins=None, out=None):
     """All orbitals as a torch tensor [n][Nz][Ny][Nx] on `device`, or on the
-    workload's boxes [n][bz][by][bx] given the box origins [n_orb][3].
+    workload's boxes [n][bz][by][bx] given the box origins [n_orb][3];
+    written into `out` when given.
 
     Values are evaluated in float64 with the same formula as
     :func:`orbital_values_np` and cast to `dtype` at the end.
@@ -170,7 +171,8 @@ def orbitals_torch(wl: Workload, device="cpu", dtype=None, origins=None):
     Nx, Ny, Nz = wl.n_grid
     bx, by, bz = wl.box if origins is not None else (Nx, Ny, Nz)
     h = wl.h
-    out = torch.empty((orbs.n, bz, by, bx), dtype=dtype, device=device)
+    if out is None:
+        out = torch.empty((orbs.n, bz, by, bx), dtype=dtype, device=device)
 
     def mi(coord, c, L):
         d = coord - c

@@ -50,7 +50,7 @@ int main(void) {
   O(exx_stats_t, relres_max) O(exx_stats_t, cg_ms) O(exx_stats_t, n_pe) O(exx_stats_t, n_me)
   O(exx_stats_t, cg_bytes) O(exx_stats_t, n_waves) O(exx_stats_t, cg_bands) O(exx_stats_t, outer_total)
   O(exx_stats_t, guess_pairs) O(exx_stats_t, guess_ms) O(exx_stats_t, tuned) O(exx_stats_t, tune_ms)
-  O(exx_stats_t, graph_builds) O(exx_stats_t, graph_launches)
+  O(exx_stats_t, graph_builds) O(exx_stats_t, graph_launches) O(exx_stats_t, wave_n)
   return 0;
 }
 '''
@@ -72,7 +72,7 @@ def test_struct_layout_matches_header():
               "keep_intermediates", "autotune", "graph", "box_dims"]:
         assert lay[f] == getattr(X.ExxParams, f).offset, f
     for f in ["relres_max", "cg_ms", "n_pe", "n_me", "cg_bytes", "n_waves", "cg_bands", "outer_total",
-              "guess_pairs", "guess_ms", "tuned", "tune_ms", "graph_builds", "graph_launches"]:
+              "guess_pairs", "guess_ms", "tuned", "tune_ms", "graph_builds", "graph_launches", "wave_n"]:
         assert lay[f] == getattr(X.ExxStats, f).offset, f
 
 

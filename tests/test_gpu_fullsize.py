@@ -121,3 +121,72 @@ def test_c2_potential_accumulation_at_sampled_points(c2_run):
     scale = np.max(np.abs(ref))
     assert scale > 0
     assert np.max(np.abs(got - ref)) <= 1e-12 * scale
+
+
+# ---------------------------------------------------------------------------
+# 512-water workload: 2048 FP32 orbitals on 160^3 boxes of a 256^3 grid, two
+# subdomain classes, FP32 CG with FP64 reliable updates, pairs in waves
+# ---------------------------------------------------------------------------
+
+def _oracle_orbitals(wl, idx, origins):
+    """What the GPU reads, as FP64 grids: FP32 box values placed into zeros."""
+    vals = S.orbitals_np(wl, idx, origins=origins).astype(np.float32).astype(np.float64)
+    return S.embed_boxes(vals, [origins[k] for k in idx], wl.n_grid)
+
+
+@pytest.fixture(scope="module")
+def c5_run():
+    wl = S.c5_water512()
+    _say("[gpu] 512-water workload, full step")
+    ctx = X.Exx.from_workload(wl)
+    # orbitals and D first: the pair waves are sized from the memory left
+    phi = torch.empty((2048,) + tuple(reversed(wl.box)), dtype=torch.float32, device="cuda:0")
+    D = torch.empty_like(phi)
+    n = ctx.pairs(wl.orbitals.centers)
+    org = ctx.box_origins()
+    S.orbitals_torch(wl, device="cuda:0", origins=org, out=phi)
+    E, D = ctx.step(phi, D)
+    torch.cuda.synchronize()
+    _say(f"[gpu] {n} pairs in {ctx.stats()['n_waves']} waves, E = {E}")
+    return wl, ctx, n, org, E, D, ctx.pair_info()
+
+
+def test_c5_all_pairs_converged_and_energy_sum(c5_run):
+    wl, ctx, n, org, E, D, info = c5_run
+    st = ctx.stats()
+    assert n > 70000 and st["n_pe"][0] > st["n_pe"][1]
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-9
+    w = np.where(info["i"] == info["j"], 1.0, 2.0)
+    assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
+    assert D.dtype == torch.float32 and tuple(D.shape) == (2048, 160, 160, 160)
+    for k in range(0, D.shape[0], 16):                   # in slices: little device memory is left
+        assert bool(torch.isfinite(D[k:k + 16]).all()), k
+
+
+def test_c5_sampled_pairs_vs_oracle(c5_run):
+    """Pair energies from the first and the last wave, and the potentials of
+    last-wave pairs (the earlier waves' potentials are released)."""
+    wl, ctx, n, org, E, D, info = c5_run
+    st = ctx.stats()
+    last0 = (st["n_waves"] - 1) * st["wave_n"]          # first pair of the last wave
+    self_p = np.nonzero(info["i"] == info["j"])[0]
+    other_p = np.nonzero(info["i"] != info["j"])[0]
+    late_other = other_p[other_p >= last0]
+    pick = [int(self_p[0]), int(other_p[0]), int(late_other[-1]), int(self_p[-1])]
+    subs = [O.Subdomain(wl.n_grid, wl.cell, wl.r_pe[c], wl.r_me[c]) for c in (0, 1)]
+    orbs = sorted({int(info["i"][p]) for p in pick} | {int(info["j"][p]) for p in pick})
+    phis = dict(zip(orbs, _oracle_orbitals(wl, orbs, org)))
+
+    def ref(p):
+        i, j = int(info["i"][p]), int(info["j"][p])
+        return subs[0 if i == j else 1].solve_pair(phis[i], phis[j], info["origin"][p])
+
+    _say(f"[gpu] oracle on sampled pairs {pick} (last wave starts near {last0})")
+    with cf.ThreadPoolExecutor(len(pick)) as ex:
+        refs = list(ex.map(ref, pick))
+    for p, r in zip(pick, refs):
+        assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
+        if p >= last0:
+            sub = subs[0 if info["i"][p] == info["j"][p] else 1]
+            got = ctx.debug_pair(p, sub.n_pe, sub.n_shell)
+            assert np.max(np.abs(got["x"] - r["x"])) <= 1e-7 * np.max(np.abs(r["x"])), p
