@@ -106,7 +106,8 @@ typedef struct {
     double  relres_max;      /* max true relative residual over pairs          */
     double  solve_ms;        /* last exx_solve: all its kernels, HIP events     */
     double  prep_ms;         /* last exx_solve: pair-preparation kernel         */
-    double  cg_ms;           /* last exx_solve: persistent CG kernel            */
+    double  cg_ms;           /* last exx_solve: persistent CG kernel, summed over
+                                waves (HIP events around each launch)          */
     double  dxx_ms;          /* last exx_energy_potential: D kernel, HIP events */
     double  energy_ms;       /* last exx_energy_potential: E reduction          */
     int32_t solve_grid;      /* persistent work-groups launched                 */

@@ -575,15 +575,24 @@ struct PDir {
     __device__ __forceinline__ void output(int, R u, R Au) { pap += (double)u * (double)Au; }
 };
 
-// update pass: u = p, x += alpha p (load time), r = rsrc - alpha Ap (output time); sum r.r
-template <typename R, int K, int KH>
+// update pass: u = p, r = rsrc - alpha Ap (output time), sum r.r; and the
+// iterate at load time, by mode XM:
+//   XM_STEP  x += alpha p                      (every iteration)
+//   XM_SKIP  x untouched: alpha p is owed      (first of two iterations)
+//   XM_PAIR  x += alpha2 q + alpha p           (second: q = the previous p)
+// Pairing the iterate updates reads and writes x every other iteration:
+// 7.5 vector passes per CG iteration instead of 8.
+enum { XM_STEP = 0, XM_SKIP = 1, XM_PAIR = 2 };
+template <typename R, int K, int KH, int XM = XM_STEP>
 struct PUpd {
     const R *p, *rsrc;
     R *x, *r, *sink;
     R alpha;
     bool load_x;
+    const R *q = nullptr;       // XM_PAIR: the previous direction
+    R alpha2 = (R)0;
     double rr = 0.0;
-    R fp[K], fx[K];
+    R fp[K], fx[K], fq[K];
     int fa[K];
     R hp[KH];
     int ha[KH];
@@ -593,12 +602,14 @@ struct PUpd {
     {
         fa[k] = a;
         fp[k] = raw_load(p, a);
-        fx[k] = load_x ? raw_load(x, a) : (R)0;
+        if constexpr (XM != XM_SKIP) fx[k] = load_x ? raw_load(x, a) : (R)0;
+        if constexpr (XM == XM_PAIR) fq[k] = raw_load(q, a);
     }
     __device__ __forceinline__ R fin_own(int k)
     {
         const R pv = fa[k] >= 0 ? fp[k] : (R)0;
-        *sel_ptr(x, fa[k], sink) = fx[k] + alpha * pv;
+        if constexpr (XM == XM_STEP) *sel_ptr(x, fa[k], sink) = fx[k] + alpha * pv;
+        if constexpr (XM == XM_PAIR) *sel_ptr(x, fa[k], sink) = fx[k] + alpha2 * fq[k] + alpha * pv;
         return pv;
     }
     __device__ __forceinline__ void fetch_halo(int j, int a)
@@ -754,11 +765,26 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         } else if (rr <= stop) {
             conv = 1;
         } else {
+            // x is updated every other iteration (PUpd XM_SKIP / XM_PAIR);
+            // `owed` is the step alpha p not yet in x, with p in pnew
+            double owed = 0.0;
+            bool pending = false;
             for (;;) {
                 const double alpha = rr / pap;
-                PUpd<double, K, KH> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, guess || it > 0};
-                zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
-                const double rn = block_sum<T>(pu.rr, red);
+                double rn;
+                if (!pending) {
+                    PUpd<double, K, KH, XM_SKIP> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, false};
+                    zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
+                    rn = block_sum<T>(pu.rr, red);
+                    owed = alpha;
+                    pending = true;
+                } else {
+                    PUpd<double, K, KH, XM_PAIR> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, guess || it > 1, pold,
+                                                   owed};
+                    zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
+                    rn = block_sum<T>(pu.rr, red);
+                    pending = false;
+                }
                 ++it;
                 const double beta = rn / rr;
                 rr = rn;
@@ -769,6 +795,13 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 PDir<double, K, KH> pd{r, pold, pnew, pnew + a.slot_n - 1, beta, true, false};
                 zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
+            }
+            if (pending) {
+                // the last iteration's step (its p is still in pnew); x holds
+                // a value once a paired update has run or a guess was given
+                const bool xv = guess || it > 2;
+                for (int q = tid; q < g.n_pe; q += T) x[q] = (xv ? x[q] : 0.0) + owed * pnew[q];
+                __syncthreads();
             }
         }
     } else {
@@ -824,6 +857,9 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
             rmax = rr_true;
             have_d = false;
             beta = beta_eff;
+            // d is updated every other iteration, as x in the FP64 loop
+            float owed = 0.f;
+            bool pending = false;
             for (;;) {
                 double pap;
                 {
@@ -834,11 +870,22 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 }
                 first = false;
                 const float alpha = (float)(rr_s / pap);
-                PUpd<float, K32, KH32> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, have_d};
-                zmarch<float, T, K32, KH32>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
-                const double rn_s = block_sum<T>(pu.rr, red);
+                double rn_s;
+                if (!pending) {
+                    PUpd<float, K32, KH32, XM_SKIP> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, false};
+                    zmarch<float, T, K32, KH32>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
+                    rn_s = block_sum<T>(pu.rr, red);
+                    owed = alpha;
+                    pending = true;
+                } else {
+                    PUpd<float, K32, KH32, XM_PAIR> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, have_d, pold,
+                                                      owed};
+                    zmarch<float, T, K32, KH32>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
+                    rn_s = block_sum<T>(pu.rr, red);
+                    have_d = true;
+                    pending = false;
+                }
                 ++it;
-                have_d = true;
                 const double rr_un = rn_s * sigma * sigma;
                 if (rr_un <= stop_rel2 * bb || rr_un <= 0.01 * rmax || it >= a.maxit || !(rn_s == rn_s)) {
                     // replace the residual: rr_s keeps |r_k|^2 of the step just taken,
@@ -847,6 +894,12 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 }
                 beta = rn_s / rr_s;
                 rr_s = rn_s;
+            }
+            if (pending) {
+                // the owed step of the last iteration (its p is still in pnew)
+                for (int q = tid; q < g.n_pe; q += T) d32[q] = (have_d ? d32[q] : 0.f) + owed * pnew[q];
+                __syncthreads();
+                have_d = true;
             }
         }
     }
