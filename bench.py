@@ -255,9 +255,12 @@ def main():
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         tr = json.load(open(PROFILE_TRAFFIC))
-        if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name
-                and tr.get("variant") == [st["solve_block"], st["cg_cols"]]):
-            traffic = tr.get("bytes_per_launch")
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name and guess == "zero":
+            for v in tr.get("variants", []):
+                if v["variant"] == [st["solve_block"], st["cg_cols"]]:
+                    # measured HBM bytes of the same launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
+                    # calibrated on a device copy); FP64 iteration counts are deterministic
+                    traffic = int(v["bytes_per_launch"])
     roofline = dict(bound="hbm", achieved=round(achieved, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                     frac=round(achieved / HBM_PEAK_GBS, 4), traffic=traffic)
 
