@@ -553,7 +553,7 @@ struct Candidate {
     long score;
 };
 
-// Measured choice among the candidates: each runs kTuneIters CG iterations
+// Measured choice among the candidates: each runs kTuneIters (60) CG iterations
 // on every pair of a synthetic batch (non-self class, constant right-hand
 // side, residual target 0 so no pair stops early; two pairs per resident
 // work-group of the widest grid), after one untimed launch; the fastest
@@ -561,7 +561,7 @@ struct Candidate {
 // cannot hold the batch.
 int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
 {
-    constexpr int kTuneIters = 20;
+    constexpr int kTuneIters = 60;
     const HostClass &k = c->cls[1];
     int max_grid = 0;
     for (const Candidate &q : cands) max_grid = std::max(max_grid, q.per_cu * c->n_cu);
