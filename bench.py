@@ -179,6 +179,8 @@ def main():
     ap.add_argument("--md-steps", type=int, default=0,
                     help="run a synthetic MD trajectory of this many steps instead (initial-guess comparison)")
     ap.add_argument("--guess", default="zero", choices=["zero", "previous", "extrap", "learned"])
+    ap.add_argument("--precond", default="none", choices=["none", "mg"],
+                    help="FP64 CG preconditioner: none (the paper's CG) or a multigrid V-cycle")
     ap.add_argument("--graph", action="store_true",
                     help="launch each solve as a captured HIP graph (the CG kernel is then timed with the whole solve)")
     ap.add_argument("--coarsen", type=int, default=2, help="learned guess: grid points per coarse cell edge")
@@ -218,7 +220,7 @@ def main():
     dev = torch.device("cuda:0")
     guess = "learned" if args.guess == "learned" else "zero"
     ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols, inner_rtol=args.inner_rtol,
-                              guess=guess, graph=args.graph)
+                              guess=guess, graph=args.graph, precond=args.precond)
     learned = train_model(args, wl, ctx) if guess == "learned" else None
     # orbitals and D first: the pair waves are sized from the memory left
     shape = (wl.orbitals.n,) + tuple(reversed(wl.box or wl.n_grid))
@@ -255,7 +257,8 @@ def main():
     traffic = None
     if os.path.exists(PROFILE_TRAFFIC):
         tr = json.load(open(PROFILE_TRAFFIC))
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name and guess == "zero":
+        if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name and guess == "zero"
+                and tr.get("precond", "none") == args.precond):
             for v in tr.get("variants", []):
                 if v["variant"] == [st["solve_block"], st["cg_cols"]]:
                     # measured HBM bytes of the same launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
@@ -287,6 +290,8 @@ def main():
                             cg_cols=st["cg_cols"], cg_bands=st["cg_bands"], outer_total=st["outer_total"],
                             inner_rtol=args.inner_rtol if wl.precision != "fp64" else None,
                             kernel_hash=kernel_hash()))
+    if args.precond != "none":
+        line["config"]["precond"] = args.precond
     if learned:
         line["config"]["guess"] = "learned"
         learned["guess_ms"] = round(st["guess_ms"], 2)

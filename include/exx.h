@@ -63,6 +63,15 @@ enum { EXX_F64 = 0, EXX_F32 = 1 };                          /* orbital dtype  */
  * converged result. */
 enum { EXX_GUESS_ZERO = 0, EXX_GUESS_PREVIOUS = 1, EXX_GUESS_EXTRAP = 2, EXX_GUESS_LEARNED = 3 };
 
+/* Preconditioner of the pair CG.  The paper iterates plain CG (Step IV) and
+ * names preconditioning as the way to fewer iterations (Sec. VI).
+ * EXX_PRECOND_MG: a symmetric multigrid V-cycle (damped Jacobi on the
+ * 6th-order operator on the PE sphere, 7-point Laplacians on masked coarse
+ * boxes of 2^l h, piecewise-constant transfers); FP64 only.  The stopping
+ * rule ||b - A x|| <= cg_rtol ||b|| is unchanged, so results agree with the
+ * plain iteration to the CG tolerance. */
+enum { EXX_PRECOND_NONE = 0, EXX_PRECOND_MG = 1 };
+
 typedef struct {
     int32_t n_grid[3];      /* Nx, Ny, Nz                                       */
     double  cell[3];        /* orthorhombic cell lengths |L_a| (bohr)           */
@@ -95,6 +104,7 @@ typedef struct {
                                0 = the whole grid.  Orbital k (and D^k) is
                                stored on the periodic box starting at
                                exx_box_origins()[k] and is zero outside it */
+    int32_t precond;        /* EXX_PRECOND_NONE (default) | EXX_PRECOND_MG      */
 } exx_params;
 
 typedef struct {

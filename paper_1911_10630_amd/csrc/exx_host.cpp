@@ -40,6 +40,15 @@ struct HostClass {
     int4 *d_pe_rows = nullptr, *d_me_rows = nullptr;
     int *d_pe_xyz = nullptr, *d_sh_xyz = nullptr, *d_cols = nullptr, *d_bands = nullptr;
     int *d_colz = nullptr, *d_pe_off = nullptr, *d_bands32 = nullptr;
+    // multigrid coarse levels: dims and masks (host), device masks, offsets
+    int mg_levels = 0;
+    int mg_n[MG_MAX][3] = {};
+    std::vector<unsigned char> mg_mask[MG_MAX];
+    unsigned char *d_mg_mask[MG_MAX] = {};
+    long long mg_off[MG_MAX] = {};
+    long long mg_doubles = 0;   // f, e, t of every level, the dense box and its sink
+    long long mg_dense_off = 0;
+    int64_t mg_cells_bytes = 0; // algorithmic bytes of one V-cycle
 };
 
 template <typename T>
@@ -76,6 +85,7 @@ struct exx_ctx {
     DevBuf<double> d_vout, d_q, d_e, d_relres, d_scratch, d_E, d_rhs, d_rho_keep;
     DevBuf<int> d_iters, d_outer, d_conv, d_counter;
     DevBuf<float> d_scratch32;
+    DevBuf<double> d_mg_scratch;
 
     // orbital boxes
     int box[3] = {0, 0, 0};
@@ -352,6 +362,69 @@ exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
     return EXX_OK;
 }
 
+// Coarse levels of the multigrid preconditioner: level 1 cells are 2x2x2
+// blocks of the PE bounding box, each level halves the previous; a cell is
+// in the domain if any child is, and stores which children are.  Levels stop
+// at an edge of at most 6 cells.  Per slot the scratch holds f, e, t of every
+// level, then the fine residual on the even-padded PE box and a sink element.
+exx_status build_mg_levels(exx_ctx *c, HostClass &k)
+{
+    const int pny = k.pyhi - k.pylo + 1;
+    std::vector<unsigned char> prev;   // level l - 1 child bits
+    int pn[3] = {k.pxhi - k.pxlo + 1, pny, k.pzhi - k.pzlo + 1};
+    k.mg_levels = 0;
+    k.mg_doubles = 0;
+    k.mg_cells_bytes = 0;
+    while (k.mg_levels < MG_MAX) {
+        const int l = k.mg_levels;
+        int m[3];
+        for (int d = 0; d < 3; ++d) m[d] = (pn[d] + 1) / 2;
+        std::vector<unsigned char> cm((size_t)m[0] * m[1] * m[2], 0);
+        int64_t in = 0;
+        for (int z = 0; z < m[2]; ++z)
+            for (int y = 0; y < m[1]; ++y)
+                for (int x = 0; x < m[0]; ++x) {
+                    unsigned bits = 0;
+                    for (int t = 0; t < 8; ++t) {
+                        const int cx = 2 * x + (t & 1), cy = 2 * y + ((t >> 1) & 1), cz = 2 * z + (t >> 2);
+                        if (cx >= pn[0] || cy >= pn[1] || cz >= pn[2]) continue;
+                        bool any;
+                        if (l == 0) {
+                            const int4 r = k.pe_rows[(size_t)cz * pny + cy];
+                            any = r.y <= r.z && k.pxlo + cx >= r.y && k.pxlo + cx <= r.z;
+                        } else {
+                            any = prev[((size_t)cz * pn[1] + cy) * pn[0] + cx] != 0;
+                        }
+                        if (any) bits |= 1u << t;
+                    }
+                    cm[((size_t)z * m[1] + y) * m[0] + x] = (unsigned char)bits;
+                    in += bits ? 1 : 0;
+                }
+        for (int d = 0; d < 3; ++d) k.mg_n[l][d] = m[d];
+        k.mg_off[l] = k.mg_doubles;
+        const long long n = (long long)m[0] * m[1] * m[2];
+        k.mg_doubles += (3 * n + 1) / 2 * 2;   // even: the dense box after the levels is 16-byte aligned
+        // algorithmic bytes per V-cycle: level 1 restriction (8 dense doubles,
+        // child bits, f) and the correction its POST pass gathers; per level
+        // the down pass (f, bits) and the up pass (f, the coarser e, bits, e)
+        if (l == 0) k.mg_cells_bytes += in * (64 + 1 + 8 + 8);
+        k.mg_cells_bytes += in * (8 + 1 + 8 + 8 + 1 + 8);
+        if (k.d_mg_mask[l]) { (void)hipFree(k.d_mg_mask[l]); k.d_mg_mask[l] = nullptr; }
+        HIPCHK(c, hipMalloc((void **)&k.d_mg_mask[l], cm.size()));
+        HIPCHK(c, hipMemcpy(k.d_mg_mask[l], cm.data(), cm.size(), hipMemcpyHostToDevice));
+        k.mg_mask[l] = std::move(cm);
+        prev = k.mg_mask[l];
+        for (int d = 0; d < 3; ++d) pn[d] = m[d];
+        ++k.mg_levels;
+        if (std::max({m[0], m[1], m[2]}) <= 6) break;
+    }
+    k.mg_dense_off = k.mg_doubles;
+    k.mg_doubles += 8LL * k.mg_n[0][0] * k.mg_n[0][1] * k.mg_n[0][2] + 2;
+    return EXX_OK;
+}
+
+long long mg_slot_doubles(const exx_ctx *c) { return std::max(c->cls[0].mg_doubles, c->cls[1].mg_doubles); }
+
 ClassDev class_dev(const HostClass &k)
 {
     ClassDev d{};
@@ -493,6 +566,8 @@ void free_class(HostClass &k)
         if (p) (void)hipFree(p);
     k.d_pe_rows = k.d_me_rows = nullptr;
     k.d_pe_xyz = k.d_sh_xyz = k.d_cols = k.d_bands = k.d_colz = k.d_pe_off = k.d_bands32 = nullptr;
+    for (auto &m : k.d_mg_mask)
+        if (m) { (void)hipFree(m); m = nullptr; }
 }
 
 double fact(int n) { double f = 1; for (int i = 2; i <= n; ++i) f *= i; return f; }
@@ -559,9 +634,33 @@ struct Candidate {
 // work-group of the widest grid), after one untimed launch; the fastest
 // wins.  Returns the index of the winner, or -1 (heuristic) when the device
 // cannot hold the batch.
+// Multigrid arguments of the CG kernel: the levels of both classes and the
+// per-slot coarse scratch.
+void mg_args(const exx_ctx *c, SolveArgs &a, double *scratch)
+{
+    a.mg = c->prm.precond == EXX_PRECOND_MG;
+    if (!a.mg) return;
+    for (int k = 0; k < 2; ++k) {
+        const HostClass &hc = c->cls[k];
+        a.mgc[k].levels = hc.mg_levels;
+        a.mgc[k].dense_off = hc.mg_dense_off;
+        for (int l = 0; l < hc.mg_levels; ++l)
+            a.mgc[k].lv[l] = MgLevel{hc.mg_n[l][0], hc.mg_n[l][1], hc.mg_n[l][2], hc.d_mg_mask[l], hc.mg_off[l]};
+    }
+    a.mg_scratch = scratch;
+    a.mg_slot_n = mg_slot_doubles(c);
+    // damping: the fine Jacobi step keeps M positive definite for
+    // omega < 2 diag(A) / lambda_max(A) ~ 0.90 (the sixth-order stencil's
+    // largest eigenvalue is ~2.22 diag); the coarse one needs omega_c < 1
+    a.mg_omega = 0.8;
+    a.mg_omega_c = 0.9;
+    a.mg_coarse_sweeps = 8;
+}
+
 int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
 {
-    constexpr int kTuneIters = 60;
+    // a preconditioned iteration costs about four plain ones
+    const int kTuneIters = c->prm.precond == EXX_PRECOND_MG ? 15 : 60;
     const HostClass &k = c->cls[1];
     int max_grid = 0;
     for (const Candidate &q : cands) max_grid = std::max(max_grid, q.per_cu * c->n_cu);
@@ -570,8 +669,10 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
     const long long per_pair = (long long)k.n_pe + k.n_sh;
     const size_t ngrid = (size_t)c->prm.n_grid[0] * c->prm.n_grid[1] * c->prm.n_grid[2];
     const bool mixed = c->prm.precision == EXX_FP32_REFINE;
-    const size_t need = (size_t)n * (slot_n + per_pair) * 8 + (size_t)max_grid * slot_n * (3 * 8 + (mixed ? 16 : 0)) +
-                        ngrid * 8 + (size_t)n * (NLM * 8 + 64);
+    const bool mg = c->prm.precond == EXX_PRECOND_MG;
+    const int nvec = mg ? 4 : 3;
+    const size_t need = (size_t)n * (slot_n + per_pair) * 8 + (size_t)max_grid * slot_n * (nvec * 8 + (mixed ? 16 : 0)) +
+                        (mg ? (size_t)max_grid * mg_slot_doubles(c) * 8 : 0) + ngrid * 8 + (size_t)n * (NLM * 8 + 64);
     size_t freeb = 0, totalb = 0;
     if (hipMemGetInfo(&freeb, &totalb) != hipSuccess || need + ((size_t)2 << 30) > freeb) return -1;
     std::vector<void *> allocs;
@@ -583,8 +684,9 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
     };
     auto release = [&]() { for (void *p : allocs) (void)hipFree(p); allocs.clear(); };
     double *phi = (double *)dev(ngrid * 8), *rhs = (double *)dev((size_t)n * slot_n * 8);
-    double *vout = (double *)dev((size_t)n * per_pair * 8), *scr = (double *)dev((size_t)max_grid * 3 * slot_n * 8);
+    double *vout = (double *)dev((size_t)n * per_pair * 8), *scr = (double *)dev((size_t)max_grid * nvec * slot_n * 8);
     float *scr32 = mixed ? (float *)dev((size_t)max_grid * 4 * slot_n * 4) : nullptr;
+    double *mgs = mg ? (double *)dev((size_t)max_grid * mg_slot_doubles(c) * 8) : nullptr;
     double *q = (double *)dev((size_t)n * NLM * 8), *e = (double *)dev((size_t)n * 8), *rr = (double *)dev((size_t)n * 8);
     int *it = (int *)dev((size_t)n * 4), *ou = (int *)dev((size_t)n * 4), *cv = (int *)dev((size_t)n * 4);
     int *counter = (int *)dev(4);
@@ -595,7 +697,7 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
     hipEvent_t ev[2] = {};
     int best = -1;
     float best_ms = 0.f;
-    if (allocs.size() != (size_t)(mixed ? 16 : 15) || hipEventCreate(&ev[0]) != hipSuccess ||
+    if (allocs.size() != (size_t)(15 + (mixed ? 1 : 0) + (mg ? 1 : 0)) || hipEventCreate(&ev[0]) != hipSuccess ||
         hipEventCreate(&ev[1]) != hipSuccess) {
         release();
         for (auto &x : ev) if (x) (void)hipEventDestroy(x);
@@ -645,6 +747,7 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
     a.inner_tol = c->prm.inner_rtol;
     a.maxit = kTuneIters;
     ylm_norms(a.ylm_norm);
+    mg_args(c, a, mgs);
     for (size_t i = 0; ok && i < cands.size(); ++i) {
         if (install_variant(c, cands[i].v, cands[i].lds) != EXX_OK) { ok = false; break; }
         a.cls[0] = class_dev(c->cls[0]);
@@ -677,7 +780,7 @@ exx_status select_variant(exx_ctx *c)
     const int nv = cg_variants(vs, 32);
     std::vector<Candidate> cands;
     std::vector<int> b0, b1;
-    const int mode = cg_mode(c->prm.precision, c->prm.guess != EXX_GUESS_ZERO);
+    const int mode = cg_mode(c->prm.precision, c->prm.guess != EXX_GUESS_ZERO, c->prm.precond == EXX_PRECOND_MG);
     bool flat = false;
     for (int i = 0; i < nv; ++i) {
         const CgVariant &v = vs[i];
@@ -767,6 +870,10 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         return fail(nullptr, EXX_EINVAL, "unknown orbital_dtype %d", p->orbital_dtype);
     if (p->guess < EXX_GUESS_ZERO || p->guess > EXX_GUESS_LEARNED)
         return fail(nullptr, EXX_EINVAL, "unknown guess %d", p->guess);
+    if (p->precond != EXX_PRECOND_NONE && p->precond != EXX_PRECOND_MG)
+        return fail(nullptr, EXX_EINVAL, "unknown precond %d", p->precond);
+    if (p->precond == EXX_PRECOND_MG && p->precision != EXX_FP64)
+        return fail(nullptr, EXX_EINVAL, "precond = EXX_PRECOND_MG runs in FP64 (precision = EXX_FP64)");
     for (int a = 0; a < 3; ++a)
         if (p->box_dims[a] < 0 || p->box_dims[a] > p->n_grid[a])
             return fail(nullptr, EXX_EINVAL, "box_dims[%d] = %d outside [0, n_grid]", a, p->box_dims[a]);
@@ -806,6 +913,7 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
     for (int k = 0; k < 2; ++k) {
         exx_status st = build_class(c, c->cls[k], p->r_pe[k], p->r_me[k]);
         if (st != EXX_OK) return bail(st);
+        if (p->precond == EXX_PRECOND_MG && (st = build_mg_levels(c, c->cls[k])) != EXX_OK) return bail(st);
     }
     {
         exx_status st = select_variant(c);
@@ -921,7 +1029,7 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     if ((st = dev_reserve(c, c->d_E, 1)) != EXX_OK) return st;
     // persistent grid and per-slot scratch
     int per_cu = 0;
-    HIPCHK(c, cg_occupancy(c->var, cg_mode(c->prm.precision, c->prm.guess != EXX_GUESS_ZERO), c->lds_bytes, &per_cu));
+    HIPCHK(c, cg_occupancy(c->var, cg_mode(c->prm.precision, c->prm.guess != EXX_GUESS_ZERO, c->prm.precond == EXX_PRECOND_MG), c->lds_bytes, &per_cu));
     per_cu = std::max(per_cu, 1);
     c->grid = (int)std::min<int64_t>(c->n_pairs, (int64_t)per_cu * c->n_cu);
     c->grid = std::max(c->grid, 1);
@@ -933,7 +1041,11 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
         if (!c->var.zmarch) return fail(c, EXX_EINVAL, "FP32 refinement needs a z-march CG kernel");
         if ((st = dev_reserve(c, c->d_scratch32, (size_t)c->slots * 4 * c->slot_n)) != EXX_OK) return st;
     }
-    if ((st = dev_reserve(c, c->d_scratch, (size_t)c->slots * 3 * c->slot_n)) != EXX_OK) return st;
+    const bool mg = c->prm.precond == EXX_PRECOND_MG;
+    if (mg && !c->var.zmarch) return fail(c, EXX_EINVAL, "the multigrid preconditioner needs a z-march CG kernel");
+    if ((st = dev_reserve(c, c->d_scratch, (size_t)c->slots * (mg ? 4 : 3) * c->slot_n)) != EXX_OK) return st;
+    if (mg && (st = dev_reserve(c, c->d_mg_scratch, (size_t)c->slots * mg_slot_doubles(c))) != EXX_OK)
+        return st;
     // Waves of pairs: each wave holds its pairs' right-hand sides and
     // potentials.  One wave when everything fits; otherwise D is summed wave
     // by wave into FP64 partial sums (so the result does not depend on the
@@ -1037,6 +1149,7 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
     a.inner_tol = c->prm.inner_rtol;
     a.maxit = c->prm.cg_max_iter;
     ylm_norms(a.ylm_norm);
+    mg_args(c, a, c->d_mg_scratch.p);
     // initial guess from earlier steps: constant, linear or quadratic
     // extrapolation over the consecutive levels that hold the same (i, j);
     // or from the learned model
@@ -1267,6 +1380,7 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     st->iters_min = np ? it[0] : 0;
     const int sphi = c->prm.orbital_dtype == EXX_F32 ? 4 : 8;
     const int scg = c->prm.precision == EXX_FP32_REFINE ? 4 : 8;
+    const bool mg = c->prm.precond == EXX_PRECOND_MG;
     for (size_t p = 0; p < np; ++p) {
         const HostClass &k = c->cls[c->gc[p].w];
         st->iters_total += it[p];
@@ -1280,7 +1394,12 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
         // closing residual pass (x, b in); the pair energy reads x and the
         // two orbitals, the preparation the two orbitals (and writes b and
         // the shell potential)
-        const int64_t cg = (int64_t)k.n_pe * ((int64_t)it[p] * 8 * scg + (int64_t)ou[p] * 32 + 16);
+        // With the multigrid preconditioner an iteration moves 104 B per
+        // unknown (smoothing passes 16 and 24: r in, the dense residual out;
+        // r twice in, z out; direction 24, update 40) plus the V-cycle's
+        // bytes per coarse cell in the domain.
+        const int64_t per_it = mg ? (int64_t)k.n_pe * 104 + k.mg_cells_bytes : (int64_t)k.n_pe * 8 * scg;
+        const int64_t cg = (int64_t)it[p] * per_it + (int64_t)k.n_pe * ((int64_t)ou[p] * 32 + 16);
         st->cg_bytes += cg;
         st->solve_bytes += cg + (int64_t)k.n_pe * (2 * sphi + 8) + (int64_t)k.n_sh * 8 + (int64_t)k.n_pe * (8 + 2 * sphi);
         const int m = c->ij[p].x == c->ij[p].y ? 1 : 2;
@@ -1499,6 +1618,7 @@ void exx_destroy(exx_ctx *c)
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
     dev_free(c->d_bnd[0]); dev_free(c->d_bnd[1]);
+    dev_free(c->d_mg_scratch);
     dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_outer); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
     if (c->have_events)
         for (auto &e : c->ev)

@@ -98,6 +98,25 @@ __device__ __forceinline__ double load_orb(const void *phi, int f32, const OrbBo
     return in ? v : 0.0;
 }
 
+// Multigrid preconditioner: coarse levels of one subdomain class, each a
+// dense box of cells (level 1 cell c covers the fine offsets
+// plo + 2c + {0, 1} per axis, level l + 1 cell C the level-l cells
+// 2C + {0, 1}).  cm[c] has bit kx + 2 ky + 4 kz set when child (kx, ky, kz)
+// lies in the domain of the finer level (PE for level 1); a cell is in the
+// domain when cm[c] != 0.
+constexpr int MG_MAX = 6;
+struct MgLevel {
+    int nx, ny, nz;
+    const unsigned char *cm;    // [nz][ny][nx] child bits
+    long long off;              // f, e, t at off, off + n, off + 2n of a slot's coarse scratch
+};
+struct MgClass {
+    int levels;
+    MgLevel lv[MG_MAX];
+    long long dense_off;        // the fine residual on the PE box padded to even
+                                // edges, [2 nz1][2 ny1][2 nx1], then one sink element
+};
+
 struct SolveArgs {
     ClassDev cls[2];
     const int4 *pair_gc;        // [n_pairs] {gx, gy, gz, class}
@@ -131,6 +150,15 @@ struct SolveArgs {
     double inner_tol;           // FP32 inner solve target
     int maxit;
     double ylm_norm[NLM];       // normalization of the real solid harmonics
+    // multigrid-preconditioned CG (FP64): two more fine vectors per slot
+    // (scratch holds 5 per slot) and per-slot coarse arrays
+    int mg;
+    MgClass mgc[2];             // coarse levels per class
+    double *mg_scratch;         // per slot: mg_slot_n doubles
+    long long mg_slot_n;
+    double mg_omega;            // damping of the fine Jacobi smoother
+    double mg_omega_c;          // damping of the coarse Jacobi smoother
+    int mg_coarse_sweeps;       // Jacobi sweeps on the coarsest level
 };
 
 // Initial guess of one pair from up to three earlier steps (Sec. III.C Step IV:
@@ -186,9 +214,9 @@ struct CgVariant {
     int wpe;      // minimum resident waves per SIMD the kernel is compiled for
 };
 int cg_variants(CgVariant *out, int max_n);
-// Kernel mode for a precision (EXX_FP64 / EXX_FP32_REFINE) and whether CG
-// starts from a guess in vout.
-int cg_mode(int precision, int guess);
+// Kernel mode for a precision (EXX_FP64 / EXX_FP32_REFINE), whether CG
+// starts from a guess in vout, and the multigrid preconditioner.
+int cg_mode(int precision, int guess, int mg);
 hipError_t cg_occupancy(const CgVariant &v, int mode, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t lds_bytes, hipStream_t s);
 // D from the pairs [pair_lo, pair_hi): written to dxx (accumulate = 0) or

@@ -15,6 +15,7 @@
 #include "exx_internal.h"
 
 #include <algorithm>
+#include <type_traits>
 
 namespace exx {
 
@@ -396,6 +397,12 @@ __device__ __forceinline__ T raw_load(const T *p, int a)
     return p[a >= 0 ? a : 0];
 }
 
+// policies that declare kXYZ receive each point's local offsets
+template <class P, class = void>
+struct wants_xyz : std::false_type {};
+template <class P>
+struct wants_xyz<P, std::void_t<decltype(P::kXYZ)>> : std::true_type {};
+
 template <typename T>
 __device__ __forceinline__ T *sel_ptr(T *p, int a, T *sink)
 {
@@ -461,14 +468,24 @@ __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, double *l
 #pragma unroll
         for (int k = 0; k < K; ++k) ad[k] = addr(zl, cxr[k], czr[k]);
 #pragma unroll
-        for (int k = 0; k < K; ++k) pol.fetch_own(k, ad[k]);
+        for (int k = 0; k < K; ++k) {
+            if constexpr (wants_xyz<P>::value)
+                pol.fetch_own_at(k, ad[k], (cxr[k] & 0xffff) - 512, g.pylo + (cxr[k] >> 16), zl);
+            else
+                pol.fetch_own(k, ad[k]);
+        }
     };
     auto fetch_halo = [&](int z) {
         int ad[KH];
 #pragma unroll
         for (int j = 0; j < KH; ++j) ad[j] = addr(z, hxr[j], hzr[j]);
 #pragma unroll
-        for (int j = 0; j < KH; ++j) pol.fetch_halo(j, ad[j]);
+        for (int j = 0; j < KH; ++j) {
+            if constexpr (wants_xyz<P>::value)
+                pol.fetch_halo_at(j, ad[j], (hxr[j] & 0xffff) - 512, g.pylo + (hxr[j] >> 16), z);
+            else
+                pol.fetch_halo(j, ad[j]);
+        }
     };
     auto fetch_out = [&](int z) {
         const int gz = wrap_n(pg.z + z, nz);
@@ -476,9 +493,13 @@ __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, double *l
 #pragma unroll
         for (int k = 0; k < K; ++k) ad[k] = addr(z, cxr[k], czr[k]);
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            pol.fetch_out(k, ad[k], wrap_n(pg.x + (cxr[k] & 0xffff) - 512, nx),
-                          wrap_n(pg.y + g.pylo + (cxr[k] >> 16), ny), gz);
+        for (int k = 0; k < K; ++k) {
+            if constexpr (wants_xyz<P>::value)
+                pol.fetch_out_at(k, ad[k], (cxr[k] & 0xffff) - 512, g.pylo + (cxr[k] >> 16), z);
+            else
+                pol.fetch_out(k, ad[k], wrap_n(pg.x + (cxr[k] & 0xffff) - 512, nx),
+                              wrap_n(pg.y + g.pylo + (cxr[k] >> 16), ny), gz);
+        }
     };
 
     R q[K][7];
@@ -717,10 +738,278 @@ struct PFin {
     }
 };
 
+
+// ---------------------------------------------------------------------------
+// multigrid preconditioner (symmetric V-cycle; not in the paper, which
+// uses plain CG: the preconditioned iteration stops on the same residual)
+// ---------------------------------------------------------------------------
+//
+// z = M r with M = S + (I - S A) P C R (I - A S): S = (omega / diag A) I is
+// one damped Jacobi step of the fine operator A on the z-march, R averages a
+// fine 2x2x2 block onto its level-1 cell, P injects a cell's value back
+// (R = P^T / 8), and C is a V-cycle on masked dense boxes with the 7-point
+// Laplacian at spacing 2^l h (Dirichlet zero outside the mask) and one damped
+// Jacobi sweep before and after each coarsening, several on the coarsest
+// box.  Every part is symmetric, so M is too and plain PCG applies.
+
+// fine passes on the z-march:
+//   MG_PRE:  t = r - c A r on PE, stored in the dense, even-padded PE box
+//            (the residual left by the smoothing step S r)
+//   MG_POST: u = c r + e_1(cell of the point) (S r plus the prolonged coarse
+//            correction), z = u + c (r - A u) on PE, rho += r . z
+enum { MG_PRE = 0, MG_POST = 1 };
+template <int K, int KH, int MODE>
+struct PMg {
+    static constexpr bool kXYZ = true;  // the z-march passes each point's offsets
+    const double *r;                    // the vector M is applied to
+    const double *e1;                   // level-1 correction (MG_POST)
+    double *out, *sink;                 // MG_PRE: dense box; MG_POST: z (packed)
+    double c;
+    int pxlo, pylo, pzlo;
+    int dnx, dnxy;                      // dense box pitches (MG_PRE)
+    int nx1, nxy1;                      // level-1 pitches (MG_POST)
+    bool acc_bb;
+    double rho = 0.0, bb = 0.0;
+    double fr[K], fe[K];
+    int fa[K];
+    double hr[KH], he[KH];
+    int ha[KH];
+    double ob[K];
+    int oa[K];
+    __device__ __forceinline__ int cell(int a, int x, int y, int z) const
+    {
+        return a >= 0 ? ((z - pzlo) >> 1) * nxy1 + ((y - pylo) >> 1) * nx1 + ((x - pxlo) >> 1) : 0;
+    }
+    __device__ __forceinline__ void fetch_own_at(int k, int a, int x, int y, int z)
+    {
+        fa[k] = a;
+        fr[k] = raw_load(r, a);
+        if constexpr (MODE == MG_POST) fe[k] = e1[cell(a, x, y, z)];
+    }
+    __device__ __forceinline__ double fin_own(int k)
+    {
+        if constexpr (MODE == MG_POST) return fa[k] >= 0 ? c * fr[k] + fe[k] : 0.0;
+        return fa[k] >= 0 ? fr[k] : 0.0;
+    }
+    __device__ __forceinline__ void fetch_halo_at(int j, int a, int x, int y, int z)
+    {
+        ha[j] = a;
+        hr[j] = raw_load(r, a);
+        if constexpr (MODE == MG_POST) he[j] = e1[cell(a, x, y, z)];
+    }
+    __device__ __forceinline__ double fin_halo(int j)
+    {
+        if constexpr (MODE == MG_POST) return ha[j] >= 0 ? c * hr[j] + he[j] : 0.0;
+        return ha[j] >= 0 ? hr[j] : 0.0;
+    }
+    __device__ __forceinline__ void fetch_out_at(int k, int a, int x, int y, int z)
+    {
+        if constexpr (MODE == MG_POST) {
+            oa[k] = a;
+            ob[k] = raw_load(r, a);
+        } else {
+            oa[k] = a >= 0 ? ((z - pzlo) * dnxy + (y - pylo) * dnx + (x - pxlo)) : -1;
+        }
+    }
+    __device__ __forceinline__ void output(int k, double uu, double Au)
+    {
+        const bool ok = oa[k] >= 0;
+        double tv;
+        if constexpr (MODE == MG_PRE) {
+            tv = uu - c * Au;
+            if (acc_bb) bb += ok ? uu * uu : 0.0;
+        } else {
+            tv = ok ? uu + c * (ob[k] - Au) : 0.0;
+            rho += ok ? ob[k] * tv : 0.0;
+        }
+        *sel_ptr(out, oa[k], sink) = tv;
+    }
+};
+
+// Cells c = threadIdx.x + k T of a level in order, with their (x, y, z)
+// stepped without divisions.
+struct CellWalk {
+    int c, x, y, z, sx, sy, sz, nx, ny;
+    __device__ __forceinline__ CellWalk(const MgLevel &L, int T)
+    {
+        c = threadIdx.x;
+        x = c % L.nx;
+        y = (c / L.nx) % L.ny;
+        z = c / (L.nx * L.ny);
+        sx = T % L.nx;
+        sy = (T / L.nx) % L.ny;
+        sz = T / (L.nx * L.ny);
+        nx = L.nx;
+        ny = L.ny;
+    }
+    __device__ __forceinline__ void next(int T)
+    {
+        c += T;
+        x += sx;
+        if (x >= nx) { x -= nx; ++y; }
+        y += sy;
+        if (y >= ny) { y -= ny; ++z; }
+        z += sz;
+    }
+};
+
+// Branch-free loop over the cells of a level: each thread takes U cells
+// (stride T) at a time, evaluates body(c, x, y, z) for all U (loads of the U
+// cells in flight together), then stores the U results to out[c].  Cells
+// past the end evaluate cell 0 and store nothing.
+template <int T, int U, class F>
+__device__ __forceinline__ void mg_cells(const MgLevel &L, double *out, F body)
+{
+    const int n = L.nx * L.ny * L.nz;
+    CellWalk w(L, T);
+    while (w.c < n) {
+        int cc[U];
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool ok = w.c < n;
+            cc[u] = ok ? w.c : -1;
+            v[u] = body(ok ? w.c : 0, ok ? w.x : 0, ok ? w.y : 0, ok ? w.z : 0);
+            w.next(T);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (cc[u] >= 0) out[cc[u]] = v[u];
+    }
+}
+
+// sum over the six neighbours of cell (x, y, z) of s_a v(neighbour), zero
+// outside the box (branch-free: a missing neighbour reads the cell itself)
+__device__ __forceinline__ double mg_nbsum(const MgLevel &L, const double *v, int c, int x, int y, int z,
+                                           const double (&s)[3])
+{
+    const int sxy = L.nx * L.ny;
+    const bool xm = x > 0, xp = x + 1 < L.nx, ym = y > 0, yp = y + 1 < L.ny, zm = z > 0, zp = z + 1 < L.nz;
+    const double a0 = v[xm ? c - 1 : c], a1 = v[xp ? c + 1 : c];
+    const double b0 = v[ym ? c - L.nx : c], b1 = v[yp ? c + L.nx : c];
+    const double d0 = v[zm ? c - sxy : c], d1 = v[zp ? c + sxy : c];
+    return s[0] * ((xm ? a0 : 0.0) + (xp ? a1 : 0.0)) + s[1] * ((ym ? b0 : 0.0) + (yp ? b1 : 0.0)) +
+           s[2] * ((zm ? d0 : 0.0) + (zp ? d1 : 0.0));
+}
+
+__device__ __forceinline__ void mg_spacing(const SolveArgs &a, int l, double (&s)[3])
+{
+    const double f = (double)(2 << l);      // level l + 1 has spacing 2^(l+1) h
+#pragma unroll
+    for (int d = 0; d < 3; ++d) s[d] = 1.0 / ((f * a.h[d]) * (f * a.h[d]));
+}
+
+constexpr int MG_U = 4;     // cells per thread in flight
+
+// level-1 right-hand side: the average of each cell's fine residuals, read
+// from the dense PE box (children outside PE hold stale values; cm masks
+// them; cells outside the domain read the box's first line and yield zero)
+template <int T>
+__device__ void mg_restrict_dense(const MgLevel &L, const double *__restrict__ t, double *__restrict__ f)
+{
+    const int dnx = 2 * L.nx, dnxy = 4 * L.nx * L.ny;
+    mg_cells<T, MG_U>(L, f, [&](int c, int x, int y, int z) -> double {
+        const int m = L.cm[c];
+        const double *p = t + (m ? (long long)(2 * z) * dnxy + (2 * y) * dnx + 2 * x : 0);
+        const double2 v0 = *reinterpret_cast<const double2 *>(p);
+        const double2 v1 = *reinterpret_cast<const double2 *>(p + dnx);
+        const double2 v2 = *reinterpret_cast<const double2 *>(p + dnxy);
+        const double2 v3 = *reinterpret_cast<const double2 *>(p + dnxy + dnx);
+        const double sum = ((m & 1) ? v0.x : 0.0) + ((m & 2) ? v0.y : 0.0) + ((m & 4) ? v1.x : 0.0) +
+                           ((m & 8) ? v1.y : 0.0) + ((m & 16) ? v2.x : 0.0) + ((m & 32) ? v2.y : 0.0) +
+                           ((m & 64) ? v3.x : 0.0) + ((m & 128) ? v3.y : 0.0);
+        return 0.125 * sum;
+    });
+    __syncthreads();
+}
+
+// V-cycle on the coarse levels: e_1 ~ C f_1, the right-hand side f of each
+// level zero outside its domain.  Per level: f at off, e at off + n, t at
+// off + 2n; the result e_1 is returned.
+template <int T>
+__device__ const double *mg_vcycle(const SolveArgs &a, const MgClass &M, double *ms)
+{
+    const int nl = M.levels;
+    const double wc = a.mg_omega_c;
+    // down: the residual after one damped Jacobi step from zero,
+    // f(c) - L(wc D^-1 f)(c) = (1 - wc) f(c) + wc d sum_a s_a (f(c - e_a) + f(c + e_a)),
+    // averaged over the children in the domain of each coarser cell
+    for (int l = 0; l + 1 < nl; ++l) {
+        const MgLevel L = M.lv[l], Lc = M.lv[l + 1];
+        const double *f = ms + L.off;
+        double s[3];
+        mg_spacing(a, l, s);
+        const double wd = wc / (2.0 * (s[0] + s[1] + s[2]));
+        mg_cells<T, 2>(Lc, ms + Lc.off, [&](int C, int X, int Y, int Z) -> double {
+            const int m = Lc.cm[C];
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool in = (m >> k) & 1;
+                const int x = in ? 2 * X + (k & 1) : 0, y = in ? 2 * Y + ((k >> 1) & 1) : 0,
+                          z = in ? 2 * Z + (k >> 2) : 0;
+                const int c = (z * L.ny + y) * L.nx + x;
+                const double t = (1.0 - wc) * f[c] + wd * mg_nbsum(L, f, c, x, y, z, s);
+                sum += in ? t : 0.0;
+            }
+            return 0.125 * sum;
+        });
+        __syncthreads();
+    }
+    // coarsest: damped Jacobi sweeps from zero, e and t in turn
+    const double *ec;
+    {
+        const MgLevel L = M.lv[nl - 1];
+        const int n = L.nx * L.ny * L.nz;
+        const double *f = ms + L.off;
+        double *e = ms + L.off + n, *t = e + n;
+        double s[3];
+        mg_spacing(a, nl - 1, s);
+        const double wd = wc / (2.0 * (s[0] + s[1] + s[2]));
+        for (int c = threadIdx.x; c < n; c += T) e[c] = wd * f[c];
+        __syncthreads();
+        for (int sw = 1; sw < a.mg_coarse_sweeps; ++sw) {
+            const double *eo = e;
+            mg_cells<T, 1>(L, t, [&](int c, int x, int y, int z) -> double {
+                const double v = (1.0 - wc) * eo[c] + wd * (f[c] + mg_nbsum(L, eo, c, x, y, z, s));
+                return L.cm[c] ? v : 0.0;
+            });
+            __syncthreads();
+            double *u = e; e = t; t = u;
+        }
+        ec = e;
+    }
+    // up: u(c) = wc d f(c) + e_coarse(parent of c) on the domain, then one
+    // damped Jacobi sweep, e(c) = (1 - wc) u(c) + wc d (f(c) + sum_a s_a u(neighbours))
+    for (int l = nl - 2; l >= 0; --l) {
+        const MgLevel L = M.lv[l], Lc = M.lv[l + 1];
+        const int n = L.nx * L.ny * L.nz;
+        const double *f = ms + L.off;
+        double *e = ms + L.off + n, *u = e + n;
+        double s[3];
+        mg_spacing(a, l, s);
+        const double wd = wc / (2.0 * (s[0] + s[1] + s[2]));
+        const double *ecl = ec;
+        mg_cells<T, MG_U>(L, u, [&](int c, int x, int y, int z) -> double {
+            const double v = wd * f[c] + ecl[((z >> 1) * Lc.ny + (y >> 1)) * Lc.nx + (x >> 1)];
+            return L.cm[c] ? v : 0.0;
+        });
+        __syncthreads();
+        mg_cells<T, MG_U>(L, e, [&](int c, int x, int y, int z) -> double {
+            const double v = (1.0 - wc) * u[c] + wd * (f[c] + mg_nbsum(L, u, c, x, y, z, s));
+            return L.cm[c] ? v : 0.0;
+        });
+        __syncthreads();
+        ec = e;
+    }
+    return ec;
+}
+
 // Kernel modes: FP64 CG from zero, FP64 CG from the guess in vout (one more
 // pass type, so more registers), FP32 CG with FP64 reliable updates (guess
+// read at run time), FP64 CG preconditioned by the multigrid V-cycle (guess
 // read at run time).
-enum { CG_FP64 = 0, CG_FP64_GUESS = 1, CG_MIXED = 2 };
+enum { CG_FP64 = 0, CG_FP64_GUESS = 1, CG_MIXED = 2, CG_MG = 3 };
 
 // One pair: FP64 CG, or FP32 CG with FP64 iterative refinement.
 template <int T, int K, int KH, int K32, int KH32, int MODE>
@@ -735,11 +1024,83 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     double *x = a.vout + a.out_off[pair];
     const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
     const StencilW<double> w64 = stencil_w<double>(a);
-    const bool guess = MIXED ? a.guess != 0 : MODE == CG_FP64_GUESS;
+    const bool guess = (MIXED || MODE == CG_MG) ? a.guess != 0 : MODE == CG_FP64_GUESS;
     int it = 0, conv = 0, outer = 0;
     double bb = 0.0;
 
-    if constexpr (!MIXED) {
+    if constexpr (MODE == CG_MG) {
+        // PCG with the multigrid V-cycle as M: r, two direction buffers and
+        // z = M r per slot; x from zero or the guess
+        double *r = a.scratch + slot * 4 * a.slot_n;
+        double *pold = r + a.slot_n, *pnew = pold + a.slot_n, *zv = pnew + a.slot_n;
+        double *ms = a.mg_scratch + slot * a.mg_slot_n;
+        const MgClass &M = a.mgc[pg.w];
+        const MgLevel L1 = M.lv[0];
+        double *dense = ms + M.dense_off;
+        const double cfine = a.mg_omega / (-w64.c);
+        const double *rsrc = b;
+        double rr = 0.0;
+        bool need_bb = true;
+        if (guess) {
+            PRes<K, KH, double, double> pr{x, x, b, r, r + a.slot_n - 1, false, 0.0};
+            zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
+            ++outer;
+            rr = block_sum<T>(pr.rr, red);
+            bb = block_sum<T>(pr.bb, red);
+            rsrc = r;
+            need_bb = false;
+        }
+        // z = M rs; returns rs . z
+        auto precond = [&](const double *rs) -> double {
+            PMg<K, KH, MG_PRE> pre{rs, nullptr, dense, dense + 8LL * L1.nx * L1.ny * L1.nz, cfine, g.pxlo, g.pylo, g.pzlo,
+                                   2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny, need_bb};
+            zmarch<double, T, K, KH>(g, lds, par, pre, w64, pg, a.nx, a.ny, a.nz);
+            if (need_bb) {
+                bb = rr = block_sum<T>(pre.bb, red);
+                need_bb = false;
+            }
+            __syncthreads();                        // the dense residual of every band is written
+            mg_restrict_dense<T>(L1, dense, ms + L1.off);
+            const double *e1 = mg_vcycle<T>(a, M, ms);
+            PMg<K, KH, MG_POST> post{rs, e1, zv, zv + a.slot_n - 1, cfine, g.pxlo, g.pylo, g.pzlo,
+                                     2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny, false};
+            zmarch<double, T, K, KH>(g, lds, par, post, w64, pg, a.nx, a.ny, a.nz);
+            return block_sum<T>(post.rho, red);
+        };
+        double rho = precond(rsrc);
+        const double stop = a.tol * a.tol * bb;
+        if (bb == 0.0) {
+            for (int q = tid; q < g.n_pe; q += T) x[q] = 0.0;
+            __syncthreads();
+            conv = 1;
+        } else if (rr <= stop) {
+            conv = 1;
+        } else {
+            double pap;
+            {
+                PDir<double, K, KH> pd{zv, pold, pnew, pnew + a.slot_n - 1, 0.0, false, false};
+                zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
+                pap = block_sum<T>(pd.pap, red);
+            }
+            for (;;) {
+                const double alpha = rho / pap;
+                PUpd<double, K, KH, XM_STEP> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, guess || it > 0};
+                zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
+                rr = block_sum<T>(pu.rr, red);
+                ++it;
+                rsrc = r;
+                if (rr <= stop) { conv = 1; break; }
+                if (it >= a.maxit) break;
+                const double rho_new = precond(r);
+                const double beta = rho_new / rho;
+                rho = rho_new;
+                double *t = pold; pold = pnew; pnew = t;
+                PDir<double, K, KH> pd{zv, pold, pnew, pnew + a.slot_n - 1, beta, true, false};
+                zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
+                pap = block_sum<T>(pd.pap, red);
+            }
+        }
+    } else if constexpr (!MIXED) {
         double *r = a.scratch + slot * 3 * a.slot_n;
         double *pold = r + a.slot_n, *pnew = pold + a.slot_n;
         const double *rsrc = b;
@@ -1152,14 +1513,18 @@ static hipError_t zm_occ(size_t lds, int *per_cu)
 #define EXX_MATCH(v, T, K, KH, K32, KH32, W) \
     ((v).block == T && (v).cols == K && (v).halo == KH && (v).cols32 == K32 && (v).halo32 == KH32 && (v).wpe == W)
 
-int cg_mode(int precision, int guess) { return precision ? CG_MIXED : guess ? CG_FP64_GUESS : CG_FP64; }
+int cg_mode(int precision, int guess, int mg)
+{
+    return mg ? CG_MG : precision ? CG_MIXED : guess ? CG_FP64_GUESS : CG_FP64;
+}
 
 hipError_t cg_occupancy(const CgVariant &v, int mode, size_t lds, int *blocks_per_cu)
 {
     if (!v.zmarch) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_solve<256>, 256, 0);
 #define EXX_V(T, K, KH, K32, KH32, W)                                                           \
     if (EXX_MATCH(v, T, K, KH, K32, KH32, W))                                                    \
-        return mode == CG_MIXED        ? zm_occ<T, K, KH, K32, KH32, W, CG_MIXED>(lds, blocks_per_cu)      \
+        return mode == CG_MG           ? zm_occ<T, K, KH, K32, KH32, W, CG_MG>(lds, blocks_per_cu)         \
+               : mode == CG_MIXED      ? zm_occ<T, K, KH, K32, KH32, W, CG_MIXED>(lds, blocks_per_cu)      \
                : mode == CG_FP64_GUESS ? zm_occ<T, K, KH, K32, KH32, W, CG_FP64_GUESS>(lds, blocks_per_cu) \
                                        : zm_occ<T, K, KH, K32, KH32, W, CG_FP64>(lds, blocks_per_cu);
     EXX_ZM_VARIANTS(EXX_V)
@@ -1175,7 +1540,9 @@ hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t ld
     }
 #define EXX_V(T, K, KH, K32, KH32, W)                                                                          \
     if (EXX_MATCH(v, T, K, KH, K32, KH32, W)) {                                                                 \
-        if (a.precision)                                                                                        \
+        if (a.mg)                                                                                               \
+            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_MG>), dim3(grid), dim3(T), lds, s, a);    \
+        else if (a.precision)                                                                                   \
             hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_MIXED>), dim3(grid), dim3(T), lds, s, a); \
         else if (a.guess)                                                                                       \
             hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_FP64_GUESS>), dim3(grid), dim3(T), lds, s, \

@@ -21,6 +21,7 @@ _STATUS = {0: "EXX_OK", -1: "EXX_EINVAL", -2: "EXX_ENOMEM", -3: "EXX_EDEVICE", -
 PRECISION = {"fp64": 0, "fp32_refine": 1}
 ORBITAL_DTYPE = {"f64": 0, "f32": 1}
 GUESS = {"zero": 0, "previous": 1, "extrap": 2, "learned": 3}
+PRECOND = {"none": 0, "mg": 1}
 NLM = 49
 
 EXPORTS = ["exx_default_params", "exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats",
@@ -37,7 +38,7 @@ class ExxParams(C.Structure):
                 ("inner_rtol", C.c_double), ("block_threads", C.c_int32), ("cg_cols", C.c_int32),
                 ("wave_pairs", C.c_int64),
                 ("keep_intermediates", C.c_int32), ("autotune", C.c_int32), ("graph", C.c_int32),
-                ("box_dims", C.c_int32 * 3)]
+                ("box_dims", C.c_int32 * 3), ("precond", C.c_int32)]
 
 
 class ExxStats(C.Structure):
@@ -122,7 +123,7 @@ class Exx:
 
     def __init__(self, n_grid, cell, r_pair, r_pe, r_me, *, cg_rtol=1e-10, cg_max_iter=20000,
                  precision="fp64", orbital_dtype="f64", guess="zero", inner_rtol=1e-5, block_threads=0,
-                 cg_cols=0, wave_pairs=0, keep_intermediates=False, autotune=True, graph=False, box=None, device=0):
+                 cg_cols=0, wave_pairs=0, keep_intermediates=False, autotune=True, graph=False, box=None, precond="none", device=0):
         L = load()
         p = ExxParams()
         L.exx_default_params(C.byref(p))
@@ -146,6 +147,7 @@ class Exx:
         p.keep_intermediates = 1 if keep_intermediates else 0
         p.autotune = 1 if autotune else 0
         p.graph = 1 if graph else 0
+        p.precond = PRECOND[precond]
         if box is not None:
             for a in range(3):
                 p.box_dims[a] = int(box[a])

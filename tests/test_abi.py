@@ -45,7 +45,7 @@ int main(void) {
   O(exx_params, fd_half_width) O(exx_params, l_max) O(exx_params, cg_rtol) O(exx_params, cg_max_iter)
   O(exx_params, precision) O(exx_params, orbital_dtype) O(exx_params, guess) O(exx_params, inner_rtol)
   O(exx_params, block_threads) O(exx_params, cg_cols) O(exx_params, wave_pairs) O(exx_params, keep_intermediates)
-  O(exx_params, autotune) O(exx_params, graph) O(exx_params, box_dims)
+  O(exx_params, autotune) O(exx_params, graph) O(exx_params, box_dims) O(exx_params, precond)
   printf("stats %zu\n", sizeof(exx_stats_t));
   O(exx_stats_t, relres_max) O(exx_stats_t, cg_ms) O(exx_stats_t, n_pe) O(exx_stats_t, n_me)
   O(exx_stats_t, cg_bytes) O(exx_stats_t, n_waves) O(exx_stats_t, cg_bands) O(exx_stats_t, outer_total)
@@ -69,7 +69,7 @@ def test_struct_layout_matches_header():
     assert lay["stats"] == C.sizeof(X.ExxStats)
     for f in ["n_grid", "cell", "r_pair", "r_pe", "r_me", "fd_half_width", "l_max", "cg_rtol", "cg_max_iter",
               "precision", "orbital_dtype", "guess", "inner_rtol", "block_threads", "cg_cols", "wave_pairs",
-              "keep_intermediates", "autotune", "graph", "box_dims"]:
+              "keep_intermediates", "autotune", "graph", "box_dims", "precond"]:
         assert lay[f] == getattr(X.ExxParams, f).offset, f
     for f in ["relres_max", "cg_ms", "n_pe", "n_me", "cg_bytes", "n_waves", "cg_bands", "outer_total",
               "guess_pairs", "guess_ms", "tuned", "tune_ms", "graph_builds", "graph_launches", "wave_n"]:
@@ -119,6 +119,8 @@ def _setup_status(**over):
     (dict(cg_rtol=0.0), "cg_rtol"),
     (dict(n_grid=(4, 48, 48)), "n_grid"),
     (dict(box_dims=(49, 0, 0)), "box_dims"),
+    (dict(precond=2), "precond"),
+    (dict(precond=1, precision=1), "precond"),
 ])
 def test_setup_rejects_bad_parameters(over, needle):
     st, msg = _setup_status(**over)

@@ -1,0 +1,127 @@
+"""FP64 CG preconditioned by the multigrid V-cycle, through the C ABI,
+against the FP64 CPU oracle (which runs the paper's plain CG).
+
+Both stop at ||b - A x|| <= 1e-10 ||b||, so the preconditioner changes the
+iteration count but not what is solved: E_xx to 1e-8 relative, pair
+energies to 1e-8, D_xx to gamma <= 1e-7, as for plain CG.
+"""
+import concurrent.futures as cf
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import oracle as O  # noqa: E402
+from paper_1911_10630_amd import exx as X  # noqa: E402
+from paper_1911_10630_amd import synth as S  # noqa: E402
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gamma(D_ref, D):
+    num = np.abs(D_ref - D).reshape(D.shape[0], -1).sum(axis=1)
+    return num / np.abs(D_ref).reshape(D.shape[0], -1).sum(axis=1)
+
+
+@pytest.fixture(scope="module")
+def c1():
+    wl = S.c1_small()
+    phi = S.orbitals_np(wl)
+    E, D, out = O.exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, wl.orbitals.centers, phi)
+    return wl, phi, E, D, out
+
+
+def test_mg_c1_matches_the_oracle(c1):
+    wl, phi, E, D, out = c1
+    _say("[gpu] small config, multigrid-preconditioned CG")
+    ctx = X.Exx.from_workload(wl, precond="mg")
+    n = ctx.pairs(wl.orbitals.centers)
+    Eg, Dg = ctx.step(torch.from_numpy(phi).cuda())
+    info = ctx.pair_info()
+    assert n == len(out["e"])
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert abs(Eg - E) <= 1e-8 * abs(E), (Eg, E)
+    rel = np.abs(info["e"] - out["e"]) / np.abs(out["e"])
+    assert rel.max() <= 1e-8, rel.max()
+    assert gamma(D, Dg.cpu().numpy()).max() <= 1e-7
+    # far fewer iterations than the oracle's plain CG on every pair
+    assert np.all(info["iters"] <= 0.5 * out["iters"]), (info["iters"], out["iters"])
+
+
+def test_mg_c1_previous_guess(c1):
+    """From the previous step's potential: converged at once or in a few
+    iterations, same energy."""
+    wl, phi, E, D, out = c1
+    ctx = X.Exx.from_workload(wl, precond="mg", guess="previous")
+    ctx.pairs(wl.orbitals.centers)
+    phit = torch.from_numpy(phi).cuda()
+    E1, _ = ctx.step(phit)
+    it1 = ctx.pair_info()["iters"].mean()
+    E2, _ = ctx.step(phit)
+    info = ctx.pair_info()
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert abs(E2 - E) <= 1e-8 * abs(E) and abs(E1 - E) <= 1e-8 * abs(E)
+    assert info["iters"].mean() < 0.5 * it1
+
+
+def test_mg_c1_waves_match_one_wave(c1):
+    wl, phi, *_ = c1
+    phit = torch.from_numpy(phi).cuda()
+    a = X.Exx.from_workload(wl, precond="mg")
+    a.pairs(wl.orbitals.centers)
+    E1, D1 = a.step(phit)
+    b = X.Exx.from_workload(wl, precond="mg", wave_pairs=7)
+    b.pairs(wl.orbitals.centers)
+    E2, D2 = b.step(phit)
+    assert b.stats()["n_waves"] > 1
+    assert E2 == E1 and torch.equal(D2, D1)
+
+
+def test_mg_c2_sampled_pairs_vs_oracle():
+    """The 64-water workload in full (9,966 pairs): every pair converged, the
+    sampled pairs' energies and potentials equal the oracle's, and the mean
+    iteration count is far below plain CG's."""
+    wl = S.c2_water64()
+    _say("[gpu] 64-water workload, multigrid-preconditioned CG")
+    phi = S.orbitals_torch(wl, device="cuda:0")
+    ctx = X.Exx.from_workload(wl, precond="mg")
+    n = ctx.pairs(wl.orbitals.centers)
+    E, D = ctx.step(phi)
+    info = ctx.pair_info()
+    st = ctx.stats()
+    _say(f"[gpu] {n} pairs, mean iterations {info['iters'].mean():.1f}, cg {st['cg_ms']:.1f} ms")
+    assert n == 9966
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    w = np.where(info["i"] == info["j"], 1.0, 2.0)
+    assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
+    assert info["iters"].mean() < 100
+    other = np.nonzero(info["i"] != info["j"])[0]
+    pick = [int(np.nonzero(info["i"] == info["j"])[0][2]), int(other[321]),
+            int(other[np.argmax(info["iters"][other])])]
+    subs = [O.Subdomain(wl.n_grid, wl.cell, wl.r_pe[c], wl.r_me[c]) for c in (0, 1)]
+    orbs = sorted({int(info["i"][p]) for p in pick} | {int(info["j"][p]) for p in pick})
+    phis = dict(zip(orbs, S.orbitals_np(wl, orbs)))
+
+    def ref(p):
+        i, j = int(info["i"][p]), int(info["j"][p])
+        return subs[0 if i == j else 1].solve_pair(phis[i], phis[j], info["origin"][p])
+
+    _say(f"[gpu] oracle on sampled pairs {pick}")
+    with cf.ThreadPoolExecutor(len(pick)) as ex:
+        refs = list(ex.map(ref, pick))
+    for p, r in zip(pick, refs):
+        sub = subs[0 if info["i"][p] == info["j"][p] else 1]
+        got = ctx.debug_pair(p, sub.n_pe, sub.n_shell)
+        assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
+        assert np.max(np.abs(got["x"] - r["x"])) <= 1e-7 * np.max(np.abs(r["x"])), p
+        assert info["iters"][p] < 0.3 * r["iters"], (p, info["iters"][p], r["iters"])
+    ctx.close()
