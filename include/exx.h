@@ -64,12 +64,13 @@ enum { EXX_F64 = 0, EXX_F32 = 1 };                          /* orbital dtype  */
 enum { EXX_GUESS_ZERO = 0, EXX_GUESS_PREVIOUS = 1, EXX_GUESS_EXTRAP = 2, EXX_GUESS_LEARNED = 3 };
 
 /* Preconditioner of the pair CG.  The paper iterates plain CG (Step IV) and
- * names preconditioning as the way to fewer iterations (Sec. VI).
- * EXX_PRECOND_MG: a symmetric multigrid V-cycle (damped Jacobi on the
- * 6th-order operator on the PE sphere, 7-point Laplacians on masked coarse
- * boxes of 2^l h, piecewise-constant transfers); FP64 only.  The stopping
- * rule ||b - A x|| <= cg_rtol ||b|| is unchanged, so results agree with the
- * plain iteration to the CG tolerance. */
+ * points to preconditioners as the way to cut the CG cost (Sec. IV B).
+ * EXX_PRECOND_MG: a symmetric multigrid V-cycle (one damped Jacobi step of
+ * the 6th-order operator on the PE sphere before and after; 7-point
+ * Laplacians on masked coarse boxes of spacing 2^l h with damped Jacobi
+ * smoothing; piecewise-constant transfers); FP64 only.  The stopping rule
+ * ||b - A x|| <= cg_rtol ||b|| is unchanged, so results agree with the plain
+ * iteration to the CG tolerance. */
 enum { EXX_PRECOND_NONE = 0, EXX_PRECOND_MG = 1 };
 
 typedef struct {
