@@ -366,7 +366,7 @@ exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
 // blocks of the PE bounding box, each level halves the previous; a cell is
 // in the domain if any child is, and stores which children are.  Levels stop
 // at an edge of at most 6 cells.  Per slot the scratch holds f, e, t of every
-// level, then the fine residual on the even-padded PE box and a sink element.
+// level, then the fine residual (FP32) on the even-padded PE box and a sink.
 exx_status build_mg_levels(exx_ctx *c, HostClass &k)
 {
     const int pny = k.pyhi - k.pylo + 1;
@@ -404,10 +404,11 @@ exx_status build_mg_levels(exx_ctx *c, HostClass &k)
         k.mg_off[l] = k.mg_doubles;
         const long long n = (long long)m[0] * m[1] * m[2];
         k.mg_doubles += (3 * n + 1) / 2 * 2;   // even: the dense box after the levels is 16-byte aligned
-        // algorithmic bytes per V-cycle: level 1 restriction (8 dense doubles,
-        // child bits, f) and the correction its POST pass gathers; per level
-        // the down pass (f, bits) and the up pass (f, the coarser e, bits, e)
-        if (l == 0) k.mg_cells_bytes += in * (64 + 1 + 8 + 8);
+        // algorithmic bytes per V-cycle: level 1 restriction (8 FP32 values
+        // of the dense box, child bits, f) and the correction its POST pass
+        // gathers; per level the down pass (f, bits) and the up pass (f, the
+        // coarser e, bits, e)
+        if (l == 0) k.mg_cells_bytes += in * (32 + 1 + 8 + 8);
         k.mg_cells_bytes += in * (8 + 1 + 8 + 8 + 1 + 8);
         if (k.d_mg_mask[l]) { (void)hipFree(k.d_mg_mask[l]); k.d_mg_mask[l] = nullptr; }
         HIPCHK(c, hipMalloc((void **)&k.d_mg_mask[l], cm.size()));
@@ -419,7 +420,7 @@ exx_status build_mg_levels(exx_ctx *c, HostClass &k)
         if (std::max({m[0], m[1], m[2]}) <= 6) break;
     }
     k.mg_dense_off = k.mg_doubles;
-    k.mg_doubles += 8LL * k.mg_n[0][0] * k.mg_n[0][1] * k.mg_n[0][2] + 2;
+    k.mg_doubles += 4LL * k.mg_n[0][0] * k.mg_n[0][1] * k.mg_n[0][2] + 2;   // FP32 box and sink
     return EXX_OK;
 }
 
@@ -1394,11 +1395,12 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
         // closing residual pass (x, b in); the pair energy reads x and the
         // two orbitals, the preparation the two orbitals (and writes b and
         // the shell potential)
-        // With the multigrid preconditioner an iteration moves 104 B per
-        // unknown (smoothing passes 16 and 24: r in, the dense residual out;
-        // r twice in, z out; direction 24, update 40) plus the V-cycle's
-        // bytes per coarse cell in the domain.
-        const int64_t per_it = mg ? (int64_t)k.n_pe * 104 + k.mg_cells_bytes : (int64_t)k.n_pe * 8 * scg;
+        // With the multigrid preconditioner an iteration moves 80 B per
+        // unknown (r, x FP64; the dense residual, z, p FP32): smoothing
+        // passes 12 (r in, the dense residual out) and 20 (r twice in, z
+        // out), direction 12 (z, p in, p out), update 36 (p, x, r in, x, r
+        // out); plus the V-cycle's bytes per coarse cell in the domain.
+        const int64_t per_it = mg ? (int64_t)k.n_pe * 80 + k.mg_cells_bytes : (int64_t)k.n_pe * 8 * scg;
         const int64_t cg = (int64_t)it[p] * per_it + (int64_t)k.n_pe * ((int64_t)ou[p] * 32 + 16);
         st->cg_bytes += cg;
         st->solve_bytes += cg + (int64_t)k.n_pe * (2 * sphi + 8) + (int64_t)k.n_sh * 8 + (int64_t)k.n_pe * (8 + 2 * sphi);

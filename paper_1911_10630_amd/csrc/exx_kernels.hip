@@ -752,24 +752,38 @@ struct PFin {
 // Jacobi sweep before and after each coarsening, several on the coarsest
 // box.  Every part is symmetric, so M is too and plain PCG applies.
 
-// fine passes on the z-march:
-//   MG_PRE:  t = r - c A r on PE, stored in the dense, even-padded PE box
-//            (the residual left by the smoothing step S r)
+// Storage of the preconditioned iteration: r and x in FP64; the dense
+// residual, z and the directions p in FP32, scaled by a power of two sigma
+// (the RMS of the residual rounded down to 2^k, so scaling is exact and the
+// values stay inside the FP32 range as the residual falls).  p is rounded
+// before the direction pass applies A, and the update pass recomputes Ap from
+// the stored p, so x and r stay consistent in FP64; the rounding of z and p
+// only perturbs M, like an inexact preconditioner.
+__device__ __forceinline__ double pow2_scale(double rr, double n)
+{
+    int e;
+    (void)frexp(sqrt(rr / n), &e);
+    return ldexp(1.0, e - 1);
+}
+
+// fine passes on the z-march (each takes each point's offsets):
+//   MG_PRE:  t = r - c A r on PE, stored / sigma in the dense, even-padded
+//            PE box (the residual left by the smoothing step S r)
 //   MG_POST: u = c r + e_1(cell of the point) (S r plus the prolonged coarse
-//            correction), z = u + c (r - A u) on PE, rho += r . z
+//            correction), z = u + c (r - A u) on PE stored / sigma,
+//            rho += r . z (of the stored z)
 enum { MG_PRE = 0, MG_POST = 1 };
 template <int K, int KH, int MODE>
 struct PMg {
-    static constexpr bool kXYZ = true;  // the z-march passes each point's offsets
+    static constexpr bool kXYZ = true;
     const double *r;                    // the vector M is applied to
     const double *e1;                   // level-1 correction (MG_POST)
-    double *out, *sink;                 // MG_PRE: dense box; MG_POST: z (packed)
-    double c;
+    float *out, *sink;                  // MG_PRE: dense box; MG_POST: z (packed)
+    double c, sigma, inv_sigma;
     int pxlo, pylo, pzlo;
     int dnx, dnxy;                      // dense box pitches (MG_PRE)
     int nx1, nxy1;                      // level-1 pitches (MG_POST)
-    bool acc_bb;
-    double rho = 0.0, bb = 0.0;
+    double rho = 0.0;
     double fr[K], fe[K];
     int fa[K];
     double hr[KH], he[KH];
@@ -813,16 +827,107 @@ struct PMg {
     }
     __device__ __forceinline__ void output(int k, double uu, double Au)
     {
-        const bool ok = oa[k] >= 0;
-        double tv;
         if constexpr (MODE == MG_PRE) {
-            tv = uu - c * Au;
-            if (acc_bb) bb += ok ? uu * uu : 0.0;
+            *sel_ptr(out, oa[k], sink) = (float)((uu - c * Au) * inv_sigma);
         } else {
-            tv = ok ? uu + c * (ob[k] - Au) : 0.0;
-            rho += ok ? ob[k] * tv : 0.0;
+            const bool ok = oa[k] >= 0;
+            const float zs = (float)((uu + c * (ob[k] - Au)) * inv_sigma);
+            rho += ok ? ob[k] * ((double)zs * sigma) : 0.0;
+            *sel_ptr(out, oa[k], sink) = zs;
         }
-        *sel_ptr(out, oa[k], sink) = tv;
+    }
+};
+
+// direction pass of the preconditioned iteration: u = z + beta p_old
+// (z at scale sz, p_old at scale sp), rounded to the stored p_new (scale sz)
+// before A is applied; sums p.Ap
+template <int K, int KH>
+struct PMgDir {
+    const float *z, *pold;
+    float *pnew, *sink;
+    double beta, sz, sp, inv_sz;
+    bool load_p;
+    double pap = 0.0;
+    float fz[K], fp[K];
+    int fa[K];
+    float hz[KH], hp[KH];
+    int ha[KH];
+    __device__ __forceinline__ float round_p(float zz, float pp) const
+    {
+        return (float)(((double)zz * sz + beta * ((double)pp * sp)) * inv_sz);
+    }
+    __device__ __forceinline__ void fetch_own(int k, int a)
+    {
+        fa[k] = a;
+        fz[k] = raw_load(z, a);
+        fp[k] = load_p ? raw_load(pold, a) : 0.f;
+    }
+    __device__ __forceinline__ double fin_own(int k)
+    {
+        const bool ok = fa[k] >= 0;
+        const float ps = ok ? round_p(fz[k], fp[k]) : 0.f;
+        *sel_ptr(pnew, fa[k], sink) = ps;
+        return (double)ps * sz;
+    }
+    __device__ __forceinline__ void fetch_halo(int j, int a)
+    {
+        ha[j] = a;
+        hz[j] = raw_load(z, a);
+        hp[j] = load_p ? raw_load(pold, a) : 0.f;
+    }
+    __device__ __forceinline__ double fin_halo(int j)
+    {
+        return ha[j] >= 0 ? (double)round_p(hz[j], hp[j]) * sz : 0.0;
+    }
+    __device__ __forceinline__ void fetch_out(int, int, int, int, int) {}
+    __device__ __forceinline__ void output(int, double u, double Au) { pap += u * Au; }
+};
+
+// update pass of the preconditioned iteration: p = sz * stored p;
+// x += alpha p at load time, r = rsrc - alpha A p at output time, sums r.r
+template <int K, int KH>
+struct PMgUpd {
+    const float *p;
+    const double *rsrc;
+    double *x, *r, *sink;
+    double alpha, sz;
+    bool load_x;
+    double rr = 0.0;
+    float fp[K];
+    double fx[K];
+    int fa[K];
+    float hp[KH];
+    int ha[KH];
+    double orr[K];
+    int oa[K];
+    __device__ __forceinline__ void fetch_own(int k, int a)
+    {
+        fa[k] = a;
+        fp[k] = raw_load(p, a);
+        fx[k] = load_x ? raw_load(x, a) : 0.0;
+    }
+    __device__ __forceinline__ double fin_own(int k)
+    {
+        const double pv = fa[k] >= 0 ? (double)fp[k] * sz : 0.0;
+        *sel_ptr(x, fa[k], sink) = fx[k] + alpha * pv;
+        return pv;
+    }
+    __device__ __forceinline__ void fetch_halo(int j, int a)
+    {
+        ha[j] = a;
+        hp[j] = raw_load(p, a);
+    }
+    __device__ __forceinline__ double fin_halo(int j) { return ha[j] >= 0 ? (double)hp[j] * sz : 0.0; }
+    __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
+    {
+        oa[k] = a;
+        orr[k] = raw_load(rsrc, a);
+    }
+    __device__ __forceinline__ void output(int k, double, double Au)
+    {
+        const double t = oa[k] >= 0 ? orr[k] - alpha * Au : 0.0;
+        *sel_ptr(r, oa[k], sink) = t;
+        rr += t * t;
     }
 };
 
@@ -902,23 +1007,26 @@ __device__ __forceinline__ void mg_spacing(const SolveArgs &a, int l, double (&s
 constexpr int MG_U = 4;     // cells per thread in flight
 
 // level-1 right-hand side: the average of each cell's fine residuals, read
-// from the dense PE box (children outside PE hold stale values; cm masks
-// them; cells outside the domain read the box's first line and yield zero)
+// from the dense PE box (stored / sigma in FP32; children outside PE hold
+// stale values and cm masks them; cells outside the domain read the box's
+// first line and yield zero)
 template <int T>
-__device__ void mg_restrict_dense(const MgLevel &L, const double *__restrict__ t, double *__restrict__ f)
+__device__ void mg_restrict_dense(const MgLevel &L, const float *__restrict__ t, double sigma, double *__restrict__ f)
 {
     const int dnx = 2 * L.nx, dnxy = 4 * L.nx * L.ny;
+    const double w = 0.125 * sigma;
     mg_cells<T, MG_U>(L, f, [&](int c, int x, int y, int z) -> double {
         const int m = L.cm[c];
-        const double *p = t + (m ? (long long)(2 * z) * dnxy + (2 * y) * dnx + 2 * x : 0);
-        const double2 v0 = *reinterpret_cast<const double2 *>(p);
-        const double2 v1 = *reinterpret_cast<const double2 *>(p + dnx);
-        const double2 v2 = *reinterpret_cast<const double2 *>(p + dnxy);
-        const double2 v3 = *reinterpret_cast<const double2 *>(p + dnxy + dnx);
-        const double sum = ((m & 1) ? v0.x : 0.0) + ((m & 2) ? v0.y : 0.0) + ((m & 4) ? v1.x : 0.0) +
-                           ((m & 8) ? v1.y : 0.0) + ((m & 16) ? v2.x : 0.0) + ((m & 32) ? v2.y : 0.0) +
-                           ((m & 64) ? v3.x : 0.0) + ((m & 128) ? v3.y : 0.0);
-        return 0.125 * sum;
+        const float *p = t + (m ? (long long)(2 * z) * dnxy + (2 * y) * dnx + 2 * x : 0);
+        const float2 v0 = *reinterpret_cast<const float2 *>(p);
+        const float2 v1 = *reinterpret_cast<const float2 *>(p + dnx);
+        const float2 v2 = *reinterpret_cast<const float2 *>(p + dnxy);
+        const float2 v3 = *reinterpret_cast<const float2 *>(p + dnxy + dnx);
+        const double sum = ((m & 1) ? (double)v0.x : 0.0) + ((m & 2) ? (double)v0.y : 0.0) +
+                           ((m & 4) ? (double)v1.x : 0.0) + ((m & 8) ? (double)v1.y : 0.0) +
+                           ((m & 16) ? (double)v2.x : 0.0) + ((m & 32) ? (double)v2.y : 0.0) +
+                           ((m & 64) ? (double)v3.x : 0.0) + ((m & 128) ? (double)v3.y : 0.0);
+        return w * sum;
     });
     __syncthreads();
 }
@@ -1029,18 +1137,20 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     double bb = 0.0;
 
     if constexpr (MODE == CG_MG) {
-        // PCG with the multigrid V-cycle as M: r, two direction buffers and
-        // z = M r per slot; x from zero or the guess
+        // PCG with the multigrid V-cycle as M: per slot r (FP64), then z and
+        // two direction buffers (FP32, scaled); x from zero or the guess
         double *r = a.scratch + slot * 4 * a.slot_n;
-        double *pold = r + a.slot_n, *pnew = pold + a.slot_n, *zv = pnew + a.slot_n;
+        float *zv = reinterpret_cast<float *>(r + a.slot_n);
+        float *pold = zv + a.slot_n, *pnew = pold + a.slot_n;
         double *ms = a.mg_scratch + slot * a.mg_slot_n;
         const MgClass &M = a.mgc[pg.w];
         const MgLevel L1 = M.lv[0];
-        double *dense = ms + M.dense_off;
+        float *dense = reinterpret_cast<float *>(ms + M.dense_off);
+        float *dsink = dense + 8LL * L1.nx * L1.ny * L1.nz;
         const double cfine = a.mg_omega / (-w64.c);
+        const double n_el = (double)g.n_pe;
         const double *rsrc = b;
         double rr = 0.0;
-        bool need_bb = true;
         if (guess) {
             PRes<K, KH, double, double> pr{x, x, b, r, r + a.slot_n - 1, false, 0.0};
             zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
@@ -1048,26 +1158,24 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
             rr = block_sum<T>(pr.rr, red);
             bb = block_sum<T>(pr.bb, red);
             rsrc = r;
-            need_bb = false;
+        } else {
+            double s2 = 0.0;
+            for (int q = tid; q < g.n_pe; q += T) s2 += b[q] * b[q];
+            bb = rr = block_sum<T>(s2, red);
         }
-        // z = M rs; returns rs . z
-        auto precond = [&](const double *rs) -> double {
-            PMg<K, KH, MG_PRE> pre{rs, nullptr, dense, dense + 8LL * L1.nx * L1.ny * L1.nz, cfine, g.pxlo, g.pylo, g.pzlo,
-                                   2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny, need_bb};
+        // z = M rs at scale sz (stored / sz); returns rs . z
+        auto precond = [&](const double *rs, double sz) -> double {
+            PMg<K, KH, MG_PRE> pre{rs, nullptr, dense, dsink, cfine, sz, 1.0 / sz, g.pxlo, g.pylo, g.pzlo,
+                                   2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny};
             zmarch<double, T, K, KH>(g, lds, par, pre, w64, pg, a.nx, a.ny, a.nz);
-            if (need_bb) {
-                bb = rr = block_sum<T>(pre.bb, red);
-                need_bb = false;
-            }
             __syncthreads();                        // the dense residual of every band is written
-            mg_restrict_dense<T>(L1, dense, ms + L1.off);
+            mg_restrict_dense<T>(L1, dense, sz, ms + L1.off);
             const double *e1 = mg_vcycle<T>(a, M, ms);
-            PMg<K, KH, MG_POST> post{rs, e1, zv, zv + a.slot_n - 1, cfine, g.pxlo, g.pylo, g.pzlo,
-                                     2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny, false};
+            PMg<K, KH, MG_POST> post{rs, e1, zv, zv + a.slot_n - 1, cfine, sz, 1.0 / sz, g.pxlo, g.pylo, g.pzlo,
+                                     2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny};
             zmarch<double, T, K, KH>(g, lds, par, post, w64, pg, a.nx, a.ny, a.nz);
             return block_sum<T>(post.rho, red);
         };
-        double rho = precond(rsrc);
         const double stop = a.tol * a.tol * bb;
         if (bb == 0.0) {
             for (int q = tid; q < g.n_pe; q += T) x[q] = 0.0;
@@ -1076,28 +1184,33 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         } else if (rr <= stop) {
             conv = 1;
         } else {
+            double sz = pow2_scale(rr, n_el);
+            double rho = precond(rsrc, sz);
             double pap;
             {
-                PDir<double, K, KH> pd{zv, pold, pnew, pnew + a.slot_n - 1, 0.0, false, false};
+                PMgDir<K, KH> pd{zv, pold, pnew, pnew + a.slot_n - 1, 0.0, sz, sz, 1.0 / sz, false};
                 zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
             }
+            double sp = sz;                         // scale of the stored direction
             for (;;) {
                 const double alpha = rho / pap;
-                PUpd<double, K, KH, XM_STEP> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, guess || it > 0};
+                PMgUpd<K, KH> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, sp, guess || it > 0};
                 zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
                 rr = block_sum<T>(pu.rr, red);
                 ++it;
                 rsrc = r;
                 if (rr <= stop) { conv = 1; break; }
                 if (it >= a.maxit) break;
-                const double rho_new = precond(r);
+                sz = pow2_scale(rr, n_el);
+                const double rho_new = precond(r, sz);
                 const double beta = rho_new / rho;
                 rho = rho_new;
-                double *t = pold; pold = pnew; pnew = t;
-                PDir<double, K, KH> pd{zv, pold, pnew, pnew + a.slot_n - 1, beta, true, false};
+                float *t = pold; pold = pnew; pnew = t;
+                PMgDir<K, KH> pd{zv, pold, pnew, pnew + a.slot_n - 1, beta, sz, sp, 1.0 / sz, true};
                 zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
+                sp = sz;
             }
         }
     } else if constexpr (!MIXED) {
