@@ -1399,7 +1399,8 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
         // unknown (r, x FP64; the dense residual, z, p FP32): smoothing
         // passes 12 (r in, the dense residual out) and 20 (r twice in, z
         // out), direction 12 (z, p in, p out), update 36 (p, x, r in, x, r
-        // out); plus the V-cycle's bytes per coarse cell in the domain.
+        // out; the kernel pairs the iterate updates and moves 30 on average);
+        // plus the V-cycle's bytes per coarse cell in the domain.
         const int64_t per_it = mg ? (int64_t)k.n_pe * 80 + k.mg_cells_bytes : (int64_t)k.n_pe * 8 * scg;
         const int64_t cg = (int64_t)it[p] * per_it + (int64_t)k.n_pe * ((int64_t)ou[p] * 32 + 16);
         st->cg_bytes += cg;

@@ -884,16 +884,20 @@ struct PMgDir {
 };
 
 // update pass of the preconditioned iteration: p = sz * stored p;
-// x += alpha p at load time, r = rsrc - alpha A p at output time, sums r.r
-template <int K, int KH>
+// r = rsrc - alpha A p at output time, sums r.r; the iterate at load time by
+// mode XM as in the plain iteration (XM_PAIR adds alpha2 sq q + alpha p, q
+// the previous direction at its scale sq)
+template <int K, int KH, int XM>
 struct PMgUpd {
     const float *p;
     const double *rsrc;
     double *x, *r, *sink;
     double alpha, sz;
     bool load_x;
+    const float *q = nullptr;
+    double alpha2 = 0.0, sq = 0.0;
     double rr = 0.0;
-    float fp[K];
+    float fp[K], fq[K];
     double fx[K];
     int fa[K];
     float hp[KH];
@@ -904,12 +908,15 @@ struct PMgUpd {
     {
         fa[k] = a;
         fp[k] = raw_load(p, a);
-        fx[k] = load_x ? raw_load(x, a) : 0.0;
+        if constexpr (XM != XM_SKIP) fx[k] = load_x ? raw_load(x, a) : 0.0;
+        if constexpr (XM == XM_PAIR) fq[k] = raw_load(q, a);
     }
     __device__ __forceinline__ double fin_own(int k)
     {
         const double pv = fa[k] >= 0 ? (double)fp[k] * sz : 0.0;
-        *sel_ptr(x, fa[k], sink) = fx[k] + alpha * pv;
+        if constexpr (XM == XM_STEP) *sel_ptr(x, fa[k], sink) = fx[k] + alpha * pv;
+        if constexpr (XM == XM_PAIR)
+            *sel_ptr(x, fa[k], sink) = fx[k] + alpha2 * ((double)fq[k] * sq) + alpha * pv;
         return pv;
     }
     __device__ __forceinline__ void fetch_halo(int j, int a)
@@ -1193,11 +1200,26 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 pap = block_sum<T>(pd.pap, red);
             }
             double sp = sz;                         // scale of the stored direction
+            // x is updated every other iteration; `owed` alpha p (p in pnew at
+            // scale s_owed) is not yet in x
+            double owed = 0.0, s_owed = 0.0;
+            bool pending = false;
             for (;;) {
                 const double alpha = rho / pap;
-                PMgUpd<K, KH> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, sp, guess || it > 0};
-                zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
-                rr = block_sum<T>(pu.rr, red);
+                if (!pending) {
+                    PMgUpd<K, KH, XM_SKIP> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, sp, false};
+                    zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
+                    rr = block_sum<T>(pu.rr, red);
+                    owed = alpha;
+                    s_owed = sp;
+                    pending = true;
+                } else {
+                    PMgUpd<K, KH, XM_PAIR> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, sp, guess || it > 1,
+                                              pold, owed, s_owed};
+                    zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
+                    rr = block_sum<T>(pu.rr, red);
+                    pending = false;
+                }
                 ++it;
                 rsrc = r;
                 if (rr <= stop) { conv = 1; break; }
@@ -1211,6 +1233,14 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
                 sp = sz;
+            }
+            if (pending) {
+                // the last iteration's step (its p is still in pnew); x holds a
+                // value once a paired update has run or a guess was given
+                const bool xv = guess || it > 2;
+                const double w = owed * s_owed;
+                for (int q = tid; q < g.n_pe; q += T) x[q] = (xv ? x[q] : 0.0) + w * (double)pnew[q];
+                __syncthreads();
             }
         }
     } else if constexpr (!MIXED) {
