@@ -74,8 +74,11 @@ def test_waves_sum_D_bitwise(boxed):
     and equals the one-wave result bit for bit; E too."""
     wl, ctx, n, org, phi_box, *_ = boxed
     phit = torch.from_numpy(phi_box).cuda()
+    # the same kernel variant as the fixture's context (the variant fixes the
+    # reduction order; the autotuner may choose differently per context)
     E1, D1 = ctx.step(phit)
-    w = X.Exx.from_workload(wl, wave_pairs=5)
+    w = X.Exx.from_workload(wl, wave_pairs=5, block_threads=ctx.stats()["solve_block"],
+                            cg_cols=ctx.stats()["cg_cols"])
     w.pairs(wl.orbitals.centers)
     E2, D2 = w.step(phit)
     assert w.stats()["n_waves"] == (n + 4) // 5
