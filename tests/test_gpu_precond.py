@@ -127,3 +127,47 @@ def test_mg_c2_sampled_pairs_vs_oracle():
         assert np.max(np.abs(got["x"] - r["x"])) <= 1e-7 * np.max(np.abs(r["x"])), p
         assert info["iters"][p] < 0.3 * r["iters"], (p, info["iters"][p], r["iters"])
     ctx.close()
+
+
+def test_mg_c5_full_size_two_classes_in_waves():
+    """The 512-water workload with the preconditioner (FP64; FP32 orbitals on
+    160^3 boxes; 79,753 pairs in waves; self and non-self pairs have PE
+    spheres of different sizes, so two level hierarchies run in one launch):
+    every pair converged, the energy sum, and sampled pair energies of both
+    classes, from the first and the last wave, against the oracle."""
+    wl = S.c5_water512()
+    wl.precision = "fp64"
+    _say("[gpu] 512-water workload, multigrid-preconditioned FP64 CG")
+    ctx = X.Exx.from_workload(wl, precond="mg")
+    phi = torch.empty((2048,) + tuple(reversed(wl.box)), dtype=torch.float32, device="cuda:0")
+    D = torch.empty_like(phi)
+    n = ctx.pairs(wl.orbitals.centers)
+    org = ctx.box_origins()
+    S.orbitals_torch(wl, device="cuda:0", origins=org, out=phi)
+    E, D = ctx.step(phi, D)
+    info = ctx.pair_info()
+    st = ctx.stats()
+    _say(f"[gpu] {n} pairs in {st['n_waves']} waves, mean iterations {info['iters'].mean():.1f}")
+    assert st["n_waves"] > 1 and st["n_pe"][0] > st["n_pe"][1]
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert info["iters"].mean() < 60
+    w = np.where(info["i"] == info["j"], 1.0, 2.0)
+    assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
+    self_p = np.nonzero(info["i"] == info["j"])[0]
+    other_p = np.nonzero(info["i"] != info["j"])[0]
+    pick = [int(self_p[-1]), int(other_p[0]), int(other_p[-1])]
+    subs = [O.Subdomain(wl.n_grid, wl.cell, wl.r_pe[c], wl.r_me[c]) for c in (0, 1)]
+    orbs = sorted({int(info["i"][p]) for p in pick} | {int(info["j"][p]) for p in pick})
+    vals = S.orbitals_np(wl, orbs, origins=org).astype(np.float32).astype(np.float64)
+    phis = dict(zip(orbs, S.embed_boxes(vals, [org[k] for k in orbs], wl.n_grid)))
+
+    def ref(p):
+        i, j = int(info["i"][p]), int(info["j"][p])
+        return subs[0 if i == j else 1].solve_pair(phis[i], phis[j], info["origin"][p])
+
+    _say(f"[gpu] oracle on sampled pairs {pick}")
+    with cf.ThreadPoolExecutor(len(pick)) as ex:
+        refs = list(ex.map(ref, pick))
+    for p, r in zip(pick, refs):
+        assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
+    ctx.close()
