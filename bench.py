@@ -26,7 +26,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "cg_traffic.json")
+PROFILE_TRAFFIC = {"none": os.path.join(ROOT, "profiles", "cg_traffic.json"),
+                   "mg": os.path.join(ROOT, "profiles", "cg_traffic_mg.json")}
 KERNEL_SRC = os.path.join(ROOT, "paper_1911_10630_amd", "csrc", "exx_kernels.hip")
 
 
@@ -255,10 +256,10 @@ def main():
     cg_ms = st["cg_ms"] if st["cg_ms"] > 0 else st["solve_ms"]
     achieved = st["cg_bytes"] / (cg_ms * 1e-3) / 1e9
     traffic = None
-    if os.path.exists(PROFILE_TRAFFIC):
-        tr = json.load(open(PROFILE_TRAFFIC))
-        if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name and guess == "zero"
-                and tr.get("precond", "none") == args.precond):
+    ptr = PROFILE_TRAFFIC[args.precond]
+    if os.path.exists(ptr):
+        tr = json.load(open(ptr))
+        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name and guess == "zero":
             for v in tr.get("variants", []):
                 if v["variant"] == [st["solve_block"], st["cg_cols"]]:
                     # measured HBM bytes of the same launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
