@@ -154,13 +154,27 @@ void exx_default_params(exx_params *p);
 exx_status exx_setup(const exx_params *p, int device, exx_ctx **out);
 
 /* Builds the unique pair list {i <= j : i == j or |C_i - C_j| < r_pair}
- * ordered by (i, j), the pair origins (grid point nearest the minimum-image
- * midpoint, Step III) and per-orbital pair lists, and sizes the per-pair
- * device buffers.  centers: host, [n_orb][3] bohr, copied.  *n_pairs
- * receives the pair count.  The pairs are split into waves sized from the
- * device memory free at this call (2 GiB kept free): allocate the orbital
- * and D buffers before it.  EXX_ENOMEM if not even one pair fits. */
+ * (minimum image; Step II) ordered by (i, j), the pair origins (grid point
+ * nearest the minimum-image midpoint, Step III) and per-orbital pair lists,
+ * and sizes the per-pair device buffers.  The pair search runs on the GPU
+ * through a periodic cell list and equals the plain double loop bit for bit.
+ * centers: host, [n_orb][3] bohr, copied.  *n_pairs receives the pair count.
+ * The pairs are split into waves sized from the device memory free at this
+ * call (2 GiB kept free): allocate the orbital and D buffers before it.
+ * EXX_ENOMEM if not even one pair fits. */
 exx_status exx_pairs(exx_ctx *ctx, int32_t n_orb, const double *centers, int64_t *n_pairs);
+
+/* Owner of each pair of the current list under Alg. 1 (the refinement of
+ * the non-unique list L0 to the unique list Lu that balances the pairs over
+ * the orbitals, Sec. III C).  L0 row i holds every orbital overlapping i,
+ * itself included, in ascending minimum-image distance from i (squared FP64
+ * distance; ties by index).  owner: host, [n_pairs], receives i or j for
+ * pair (i, j) in exx_pair_info order (the self pair's owner is i).
+ * *sweeps (may be NULL) receives the number of sweeps, the last of which
+ * removed nothing.  Computed on the host on first request after exx_pairs
+ * (sequential by construction: each removal changes the rows later orbitals
+ * scan).  EXX_ESTATE before exx_pairs, EXX_EINVAL if owner is NULL. */
+exx_status exx_pair_owners(exx_ctx *ctx, int32_t *owner, int32_t *sweeps);
 
 /* Box origins chosen by exx_pairs, host [n_orb][3] grid points: origin =
  * nearest grid point of the centre minus box_dims / 2 (mod N), or 0 along

@@ -6,6 +6,7 @@ the benchmark's CPU-baseline leg.  The product path never imports it.
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 from typing import Optional, Sequence
@@ -104,6 +105,68 @@ def pair_list(centers, cell, r_pair):
     pj = np.zeros(np_, np.int32)
     L.o_pair_list(n, Cc.ravel(), _d3(cell), float(r_pair), np_, _ptr(pi), _ptr(pj))
     return pi, pj
+
+
+def _nint(v: float) -> int:
+    """Nearest integer, halves away from zero (as the C oracle's o_nint)."""
+    return int(math.floor(v + 0.5)) if v >= 0.0 else -int(math.floor(-v + 0.5))
+
+
+def min_image_d2(ci, cj, cell) -> float:
+    """Squared minimum-image distance |C_j - C_i|^2: per axis d = C_j - C_i,
+    d -= L nint(d / L), summed over x, y, z in that order (plain FP64)."""
+    s = 0.0
+    for a in range(3):
+        d = float(cj[a]) - float(ci[a])
+        d -= float(cell[a]) * float(_nint(d / float(cell[a])))
+        s += d * d
+    return s
+
+
+def unique_pair_owners(centers, cell, r_pair, by_distance=True):
+    """Alg. 1 (Sec. III C): refinement of the non-unique pair list L0 to the
+    unique list Lu.
+
+    L0 row i lists every orbital that overlaps i (the pair criterion of
+    Step II), i itself included, in ascending distance from i; distances are
+    compared as the squared minimum-image length, ties by index (the paper
+    sorts by |C_i - C_j| and does not say how ties fall).  A sweep visits
+    i = 0, 1, ..., n-1; orbital i walks its current row and, at the first
+    j != i whose row still contains i, deletes i from row j and ends its turn.
+    Sweeps repeat until one deletes nothing.  The pair (i, j) then belongs to
+    the orbital whose row still holds the other.
+
+    by_distance=False keeps each row in index order instead, the ordering
+    the paper warns against (it unbalances the owners).
+
+    Returns (owner, sweeps): owner[p] for the pairs of pair_list() in its
+    order, and the number of sweeps including the last, empty one.
+    """
+    Cc = np.asarray(centers, dtype=np.float64)
+    pi, pj = pair_list(Cc, cell, r_pair)
+    n = Cc.shape[0]
+    rows = [[] for _ in range(n)]
+    for i, j in zip(pi.tolist(), pj.tolist()):
+        d2 = min_image_d2(Cc[i], Cc[j], cell)
+        rows[i].append((d2, j))
+        if j != i:
+            rows[j].append((d2, i))
+    L = [[j for _, j in (sorted(r) if by_distance else sorted(r, key=lambda t: t[1]))] for r in rows]
+    member = [set(r) for r in L]
+    sweeps = 0
+    removed = True
+    while removed:
+        removed = False
+        sweeps += 1
+        for i in range(n):
+            for j in L[i]:
+                if j != i and i in member[j]:
+                    L[j].remove(i)
+                    member[j].discard(i)
+                    removed = True
+                    break
+    owner = np.array([i if j in member[i] else j for i, j in zip(pi.tolist(), pj.tolist())], np.int32)
+    return owner, sweeps
 
 
 def pair_origin(ci, cj, cell, n):

@@ -82,6 +82,15 @@ struct exx_ctx {
     DevBuf<int4> d_gc;
     DevBuf<long long> d_off;
     DevBuf<int> d_orb_ptr, d_orb_pairs;
+    // pair-list construction
+    DevBuf<double> d_pC;
+    DevBuf<int> d_cell_of, d_cell_start, d_cell_items, d_pcount;
+    DevBuf<long long> d_pstart;
+    DevBuf<int2> d_pij;
+    DevBuf<int4> d_pgc;
+    std::vector<double> centers;  // [n_orb][3] of the current pair list
+    std::vector<int> owner;     // Alg. 1 owner per pair (filled on request)
+    int owner_sweeps = 0;
     DevBuf<double> d_vout, d_q, d_e, d_relres, d_scratch, d_E, d_rhs, d_rho_keep;
     DevBuf<int> d_iters, d_outer, d_conv, d_counter;
     DevBuf<float> d_scratch32;
@@ -928,6 +937,142 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
     return EXX_OK;
 }
 
+// The pair list and origins (Step II, Step III) on the GPU: the host bins the
+// centres into a periodic cell list (cells at least R_pair wide, with a
+// relative margin of 1e-9 so rounding in the binning cannot separate a pair
+// by two cells), the kernels count, fill and sort each orbital's partners.
+exx_status build_pair_list(exx_ctx *c, int n_orb, const double *C)
+{
+    const double *L = c->prm.cell;
+    PairArgs a{};
+    a.n_orb = n_orb;
+    for (int k = 0; k < 3; ++k) {
+        a.L[k] = L[k];
+        a.h[k] = c->h[k];
+        a.N[k] = c->prm.n_grid[k];
+        a.nc[k] = std::max(1, (int)std::floor(L[k] / (c->prm.r_pair * (1.0 + 1e-9))));
+        a.nc[k] = std::min(a.nc[k], 1024);
+    }
+    a.r2 = c->prm.r_pair * c->prm.r_pair;
+    const int ncell = a.nc[0] * a.nc[1] * a.nc[2];
+    std::vector<int> cell_of((size_t)n_orb), start((size_t)ncell + 1, 0), items((size_t)n_orb);
+    for (int i = 0; i < n_orb; ++i) {
+        int ci[3];
+        for (int k = 0; k < 3; ++k) {
+            const double u = C[3 * i + k] - L[k] * std::floor(C[3 * i + k] / L[k]);
+            ci[k] = std::min(std::max((int)(u / (L[k] / a.nc[k])), 0), a.nc[k] - 1);
+        }
+        cell_of[i] = (ci[2] * a.nc[1] + ci[1]) * a.nc[0] + ci[0];
+        start[cell_of[i] + 1]++;
+    }
+    for (int k = 0; k < ncell; ++k) start[k + 1] += start[k];
+    {
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        for (int i = 0; i < n_orb; ++i) items[fill[cell_of[i]]++] = i;
+    }
+    exx_status st;
+    if ((st = dev_reserve(c, c->d_pC, (size_t)3 * n_orb)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_cell_of, (size_t)n_orb)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_cell_start, (size_t)ncell + 1)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_cell_items, (size_t)n_orb)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_pcount, (size_t)n_orb)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_pstart, (size_t)n_orb)) != EXX_OK) return st;
+    HIPCHK(c, hipMemcpy(c->d_pC.p, C, sizeof(double) * 3 * n_orb, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_cell_of.p, cell_of.data(), sizeof(int) * n_orb, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_cell_start.p, start.data(), sizeof(int) * (ncell + 1), hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->d_cell_items.p, items.data(), sizeof(int) * n_orb, hipMemcpyHostToDevice));
+    a.C = c->d_pC.p;
+    a.cell_of = c->d_cell_of.p;
+    a.cell_start = c->d_cell_start.p;
+    a.cell_items = c->d_cell_items.p;
+    a.count = c->d_pcount.p;
+    HIPCHK(c, launch_pair_count(a, 0));
+    std::vector<int> cnt((size_t)n_orb);
+    HIPCHK(c, hipMemcpy(cnt.data(), c->d_pcount.p, sizeof(int) * n_orb, hipMemcpyDeviceToHost));
+    std::vector<long long> pst((size_t)n_orb);
+    long long np = 0;
+    for (int i = 0; i < n_orb; ++i) {
+        pst[i] = np;
+        np += cnt[i];
+    }
+    if (np > (long long)INT32_MAX) return fail(c, EXX_EINVAL, "%lld pairs exceed the supported 2^31 - 1", np);
+    if ((st = dev_reserve(c, c->d_pij, (size_t)np)) != EXX_OK) return st;
+    if ((st = dev_reserve(c, c->d_pgc, (size_t)np)) != EXX_OK) return st;
+    HIPCHK(c, hipMemcpy(c->d_pstart.p, pst.data(), sizeof(long long) * n_orb, hipMemcpyHostToDevice));
+    a.start = c->d_pstart.p;
+    a.ij = c->d_pij.p;
+    a.gc = c->d_pgc.p;
+    HIPCHK(c, launch_pair_fill(a, 0));
+    c->ij.resize((size_t)np);
+    c->gc.resize((size_t)np);
+    HIPCHK(c, hipMemcpy(c->ij.data(), c->d_pij.p, sizeof(int2) * np, hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(c->gc.data(), c->d_pgc.p, sizeof(int4) * np, hipMemcpyDeviceToHost));
+    return EXX_OK;
+}
+
+// Alg. 1: refinement of the non-unique pair list L0 (row i: every orbital
+// overlapping i, itself included, in ascending distance from i) to the
+// unique list Lu.  Sweeps over i = 0..n-1: i takes the first j != i of its
+// current row whose row still holds i, and removes i from row j; repeated
+// until a sweep removes nothing.  The pair (i, j) is then owned by the
+// orbital whose row kept the other.  Distances are compared as the squared
+// minimum-image length, ties by index.
+void unique_pair_owners(exx_ctx *c)
+{
+    const int n = c->n_orb;
+    const size_t np = c->ij.size();
+    const double *L = c->prm.cell;
+    // rows: (d^2, partner, pair) per orbital, self first
+    std::vector<int> rs((size_t)n + 1, 0);
+    for (const int2 &q : c->ij) {
+        rs[q.x + 1]++;
+        if (q.y != q.x) rs[q.y + 1]++;
+    }
+    for (int i = 0; i < n; ++i) rs[i + 1] += rs[i];
+    struct Ent { double d2; int j; int p; };
+    std::vector<Ent> row((size_t)rs[n]);
+    {
+        std::vector<int> fill(rs.begin(), rs.end() - 1);
+        for (size_t p = 0; p < np; ++p) {
+            const int i = c->ij[p].x, j = c->ij[p].y;
+            double dd = 0.0;
+            for (int a = 0; a < 3; ++a) {
+                double v = c->centers[3 * j + a] - c->centers[3 * i + a];
+                v -= L[a] * (double)nint_away(v / L[a]);
+                dd += v * v;
+            }
+            row[fill[i]++] = Ent{dd, j, (int)p};
+            if (j != i) row[fill[j]++] = Ent{dd, i, (int)p};
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        std::sort(row.begin() + rs[i], row.begin() + rs[i + 1], [](const Ent &u, const Ent &v) {
+            return u.d2 < v.d2 || (u.d2 == v.d2 && u.j < v.j);
+        });
+    // in_row[2p + s]: pair p still listed in the row of its i (s = 0) / j (s = 1)
+    std::vector<unsigned char> in_row(2 * np, 1);
+    auto listed = [&](int orb, int p) { return in_row[2 * p + (c->ij[p].x == orb ? 0 : 1)] != 0; };
+    bool any = true;
+    int sweeps = 0;
+    while (any) {
+        any = false;
+        ++sweeps;
+        for (int i = 0; i < n; ++i)
+            for (int t = rs[i]; t < rs[i + 1]; ++t) {
+                const Ent &e = row[t];
+                if (e.j == i || !listed(i, e.p)) continue;
+                if (listed(e.j, e.p)) {
+                    in_row[2 * e.p + (c->ij[e.p].x == e.j ? 0 : 1)] = 0;   // i leaves row j
+                    any = true;
+                    break;
+                }
+            }
+    }
+    c->owner.assign(np, 0);
+    for (size_t p = 0; p < np; ++p) c->owner[p] = in_row[2 * p] ? c->ij[p].x : c->ij[p].y;
+    c->owner_sweeps = sweeps;
+}
+
 exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pairs)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_pairs: ctx is NULL");
@@ -938,33 +1083,14 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     const int *N = c->prm.n_grid;
     for (int i = 0; i < 3 * n_orb; ++i)
         if (!std::isfinite(C[i])) return fail(c, EXX_EINVAL, "centre coordinate %d is not finite", i);
-    c->ij.clear();
-    c->gc.clear();
     c->out_off.clear();
-    c->n_self = 0;
-    const double r2 = c->prm.r_pair * c->prm.r_pair;
-    long long off = 0;
-    for (int i = 0; i < n_orb; ++i)
-        for (int j = i; j < n_orb; ++j) {
-            double d[3], dd = 0.0;
-            for (int a = 0; a < 3; ++a) {
-                d[a] = C[3 * j + a] - C[3 * i + a];
-                d[a] -= L[a] * (double)nint_away(d[a] / L[a]);
-                dd += d[a] * d[a];
-            }
-            if (i != j && !(dd < r2)) continue;
-            int g[3];
-            for (int a = 0; a < 3; ++a) {
-                double m = C[3 * i + a] + 0.5 * d[a];
-                m -= L[a] * std::floor(m / L[a]);
-                g[a] = mod_pos(nint_away(m / c->h[a]), N[a]);
-            }
-            const int cl = i == j ? 0 : 1;
-            c->ij.push_back(int2{i, j});
-            c->gc.push_back(int4{g[0], g[1], g[2], cl});
-            off += c->cls[cl].n_pe + c->cls[cl].n_sh;
-            if (i == j) ++c->n_self;
-        }
+    c->owner.clear();
+    c->centers.assign(C, C + 3 * (size_t)n_orb);
+    {
+        exx_status st = build_pair_list(c, n_orb, C);
+        if (st != EXX_OK) return st;
+    }
+    c->n_self = n_orb;
     c->n_pairs = (int64_t)c->ij.size();
     c->n_orb = n_orb;
     // orbital boxes: origin = nearest grid point of the centre minus half the
@@ -1437,6 +1563,17 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     return EXX_OK;
 }
 
+exx_status exx_pair_owners(exx_ctx *c, int32_t *owner, int32_t *sweeps)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_pair_owners: ctx is NULL");
+    if (c->state < 2) return fail(c, EXX_ESTATE, "exx_pair_owners before exx_pairs");
+    if (!owner) return fail(c, EXX_EINVAL, "exx_pair_owners: owner is NULL");
+    if (c->owner.size() != c->ij.size()) unique_pair_owners(c);
+    std::copy(c->owner.begin(), c->owner.end(), owner);
+    if (sweeps) *sweeps = c->owner_sweeps;
+    return EXX_OK;
+}
+
 exx_status exx_pair_info(exx_ctx *c, int32_t *pi, int32_t *pj, int32_t *origin, double *e, int32_t *iters,
                          int32_t *converged, double *relres)
 {
@@ -1621,6 +1758,8 @@ void exx_destroy(exx_ctx *c)
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
     dev_free(c->d_bnd[0]); dev_free(c->d_bnd[1]);
+    dev_free(c->d_pC); dev_free(c->d_cell_of); dev_free(c->d_cell_start); dev_free(c->d_cell_items);
+    dev_free(c->d_pcount); dev_free(c->d_pstart); dev_free(c->d_pij); dev_free(c->d_pgc);
     dev_free(c->d_mg_scratch);
     dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_outer); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
     if (c->have_events)

@@ -202,6 +202,28 @@ struct DxxArgs {
 hipError_t launch_prep(const SolveArgs &a, hipStream_t s);
 // e_ij = h^3 sum rho x for the pairs of the wave (after their CG).
 hipError_t launch_pair_energy(const SolveArgs &a, hipStream_t s);
+
+// Pair list (exx_pairs.hip): centres binned into a periodic cell list with
+// cells at least R_pair wide; count[i] = 1 + partners j > i within R_pair;
+// the fill writes, from start[i], the self pair and the partners in
+// ascending j with their origins and classes.
+struct PairArgs {
+    const double *C;            // [n_orb][3] centres
+    int n_orb;
+    double L[3], h[3];
+    double r2;                  // R_pair^2
+    int N[3];
+    int nc[3];                  // cells per axis
+    const int *cell_of;         // [n_orb]
+    const int *cell_start;      // [cells + 1]
+    const int *cell_items;      // orbital indices grouped by cell
+    int *count;                 // [n_orb]
+    const long long *start;     // [n_orb]
+    int2 *ij;                   // [n_pairs]
+    int4 *gc;                   // [n_pairs] {gx, gy, gz, class}
+};
+hipError_t launch_pair_count(const PairArgs &a, hipStream_t s);
+hipError_t launch_pair_fill(const PairArgs &a, hipStream_t s);
 // Persistent CG kernels: "flat" (any sphere) and "zmarch" (register queue,
 // needs the LDS plane to fit).  Variants are (block, columns per thread).
 struct CgVariant {

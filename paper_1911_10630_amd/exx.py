@@ -27,7 +27,7 @@ NLM = 49
 EXPORTS = ["exx_default_params", "exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats",
            "exx_pair_info", "exx_debug_pair", "exx_last_error", "exx_destroy", "exx_model_init", "exx_model_train",
            "exx_model_save", "exx_load_model", "exx_model_edge", "exx_model_conv", "exx_model_wgrad",
-           "exx_box_origins"]
+           "exx_box_origins", "exx_pair_owners"]
 
 
 class ExxParams(C.Structure):
@@ -87,6 +87,7 @@ def load() -> C.CDLL:
     L.exx_destroy.argtypes = [vp]
     L.exx_destroy.restype = None
     L.exx_box_origins.argtypes = [vp, vp]
+    L.exx_pair_owners.argtypes = [vp, vp, vp]
     L.exx_model_init.argtypes = [vp, i32, C.c_uint64]
     L.exx_model_train.argtypes = [vp, i32, i32, C.c_double, C.c_uint64, dp, vp]
     L.exx_model_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
@@ -238,6 +239,13 @@ class Exx:
                                          _ptr(d.get("e")), _ptr(d.get("iters")), _ptr(d.get("converged")),
                                          _ptr(d.get("relres"))))
         return d
+
+    def pair_owners(self):
+        """Alg. 1 owner (i or j) of each pair in pair_info order, and the sweep count."""
+        out = np.zeros(self.n_pairs, np.int32)
+        sw = np.zeros(1, np.int32)
+        self._check(load().exx_pair_owners(self._h, _ptr(out), _ptr(sw)))
+        return out, int(sw[0])
 
     def debug_pair(self, pair: int, n_pe: int, n_shell: int, intermediates: bool = False) -> dict:
         d = dict(x=np.zeros(n_pe), vsh=np.zeros(max(n_shell, 1)), Q=np.zeros(NLM))

@@ -84,6 +84,56 @@ def test_pair_list_minimum_image_and_strict_cutoff():
     assert list(pi) == sorted(pi)
 
 
+def test_alg1_hand_worked_examples():
+    """Alg. 1 on two cases worked by hand (tests/golden/alg1_unique_pairs.json)."""
+    import json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "alg1_unique_pairs.json")))
+    for case in g["cases"]:
+        C = np.array(case["centers"], float)
+        pi, pj = O.pair_list(C, case["cell"], case["r_pair"])
+        assert [[int(a), int(b)] for a, b in zip(pi, pj)] == case["pairs"], case["name"]
+        owner, sweeps = O.unique_pair_owners(C, case["cell"], case["r_pair"])
+        assert owner.tolist() == case["owner"], case["name"]
+        assert sweeps == case["sweeps"], case["name"]
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_alg1_assigns_every_pair_once(seed):
+    """Whatever the order of removals, Lu holds each unique pair exactly once
+    (in the row of i or of j), every self pair stays with its orbital, and the
+    rows that are left hold no pair twice (Sec. III C: all redundancies are
+    removed)."""
+    rng = np.random.default_rng(seed)
+    C = rng.uniform(-5.0, 25.0, size=(60, 3))
+    owner, sweeps = O.unique_pair_owners(C, [20.0, 20.0, 20.0], 6.0)
+    pi, pj = O.pair_list(C, [20.0, 20.0, 20.0], 6.0)
+    assert len(owner) == len(pi) and sweeps >= 2
+    assert np.all((owner == pi) | (owner == pj))
+    assert np.all(owner[pi == pj] == pi[pi == pj])
+    rows = {}
+    for p in range(len(pi)):
+        other = pj[p] if owner[p] == pi[p] else pi[p]
+        rows.setdefault(int(owner[p]), []).append(int(other))
+    for i, r in rows.items():
+        assert len(r) == len(set(r))
+        for j in r:
+            if j != i:
+                assert i not in rows.get(j, []), (i, j)
+
+
+def test_alg1_distance_order_balances_the_owners():
+    """The paper: sorting each row by distance is what keeps the owners
+    balanced; in index order the sweeps pile the pairs onto a few orbitals.
+    On the 64-water centres the most-loaded owner has within 10 % of the mean
+    with distance order, and well over 1.5x the mean in index order."""
+    wl = S.c2_water64()
+    for by_distance, bound in ((True, 1.1), (False, 1.5)):
+        owner, _ = O.unique_pair_owners(wl.orbitals.centers, wl.cell, wl.r_pair, by_distance=by_distance)
+        load = np.bincount(owner, minlength=wl.orbitals.n) - 1       # non-self pairs owned
+        ratio = load.max() / load.mean()
+        assert (ratio <= bound) if by_distance else (ratio > bound), (by_distance, ratio)
+
+
 def test_pair_origin_wraps_and_rounds():
     L, N = 10.0, 20                                    # h = 0.5
     # midpoint 0.1 -> grid 0
