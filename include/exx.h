@@ -106,7 +106,20 @@ typedef struct {
                                stored on the periodic box starting at
                                exx_box_origins()[k] and is zero outside it */
     int32_t precond;        /* EXX_PRECOND_NONE (default) | EXX_PRECOND_MG      */
+    /* Per-pair subdomains (the spread- and overlap-dependent domains the paper
+     * outlines for its next version, Sec. IV A): n_classes = 0 (default) keeps
+     * the two classes above (self pairs on r_pe[0] / r_me[0], all others on
+     * r_pe[1] / r_me[1]) and exx_pairs.  n_classes in [2, EXX_MAX_CLASSES]
+     * uses the classes class_r_pe[k] / class_r_me[k] (r_pe strictly
+     * ascending, r_me - r_pe >= n max(h) each) and exx_pairs_spread, which
+     * puts each pair on the smallest class that covers Omega_ij (see there);
+     * r_pe / r_me are then ignored.  The learned guess needs n_classes = 0. */
+    int32_t n_classes;
+    double  class_r_pe[4], class_r_me[4];
+    double  omega_scale;    /* radius of Omega_i = omega_scale * spread_i      */
 } exx_params;
+
+#define EXX_MAX_CLASSES 4
 
 typedef struct {
     int64_t n_pairs;
@@ -139,6 +152,11 @@ typedef struct {
     double  tune_ms;         /* time of those tuning launches                   */
     int32_t graph_builds;    /* graph mode: captures so far                     */
     int32_t graph_launches;  /* graph mode: solves launched as a graph          */
+    int32_t n_classes;       /* subdomain classes in use (2 with n_classes = 0)  */
+    int64_t class_n_pe[4], class_n_me[4];  /* sizes per class                  */
+    int64_t class_pairs[4];  /* pairs per class in the current list            */
+    int64_t class_capped;    /* pairs whose Omega_ij the largest class does not
+                                cover (exx_pairs_spread; they use that class)  */
 } exx_stats_t;
 
 /* Fills *p with the paper's method defaults (n = 3, l_max = 6, FP64, zero
@@ -163,6 +181,33 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out);
  * call (2 GiB kept free): allocate the orbital and D buffers before it.
  * EXX_ENOMEM if not even one pair fits. */
 exx_status exx_pairs(exx_ctx *ctx, int32_t n_orb, const double *centers, int64_t *n_pairs);
+
+/* The pair list of exx_pairs with per-pair subdomain classes
+ * (params.n_classes >= 2).  spreads: host, [n_orb] bohr, the orbitals'
+ * spreads (for MLWFs, the root of the spread functional's second moment).
+ * Orbital i gets the domain Omega_i, the ball of radius
+ * R_i = omega_scale * spread_i about C_i; pair (i, j) the domain
+ * Omega_ij = Omega_i cap Omega_j (Omega_i for the self pair).  The pair's PE
+ * sphere about its origin g must hold Omega_ij; it is taken to need the
+ * radius |g - c| + rho, (c, rho) the smallest ball that encloses Omega_ij:
+ * with d = |C_j - C_i| (minimum image) and x = (d^2 + R_i^2 - R_j^2) / (2d),
+ *   d >= R_i + R_j:            empty, radius 0 (the smallest class)
+ *   x <= 0 (or d = 0, R_i <= R_j): Omega_i lies in Omega_j up to its cap,
+ *                              c = C_i, rho = R_i
+ *   x >= d:                    c = C_j, rho = R_j
+ *   else:                      c = C_i + x (C_j - C_i) / d,
+ *                              rho = sqrt(R_i^2 - x^2)
+ * The pair goes to the smallest class whose r_pe is at least that radius,
+ * or to the largest class (counted in exx_stats class_capped).  Everything
+ * else is as exx_pairs.  EXX_EINVAL if n_classes < 2, a spread is negative
+ * or not finite, or omega_scale <= 0. */
+exx_status exx_pairs_spread(exx_ctx *ctx, int32_t n_orb, const double *centers, const double *spreads,
+                            int64_t *n_pairs);
+
+/* Subdomain class of each pair of the current list (exx_pair_info order):
+ * 0 self / 1 other with n_classes = 0, the class exx_pairs_spread chose
+ * otherwise.  cls: host, [n_pairs].  EXX_ESTATE before exx_pairs. */
+exx_status exx_pair_class(exx_ctx *ctx, int32_t *cls);
 
 /* Owner of each pair of the current list under Alg. 1 (the refinement of
  * the non-unique list L0 to the unique list Lu that balances the pairs over

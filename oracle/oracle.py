@@ -291,3 +291,117 @@ def solve_pairs(n, cell, r_pe, r_me, centers, phi_by_orbital: dict, pi: Sequence
     if used < 0:
         raise ValueError("o_solve_pairs failed")
     return dict(e=e, iters=it, converged=cv, relres=rr, threads=used)
+
+
+# ---------------------------------------------------------------------------
+# Per-pair subdomains from spreads (the domains Omega_i and Omega_ij that the
+# paper outlines for its next version, Sec. IV A).  Readings: Omega_i is the
+# ball of radius omega_scale * spread_i about C_i; the PE sphere of a pair,
+# centred at its origin g, has to hold Omega_ij = Omega_i cap Omega_j, which
+# is taken to need |g - c| + rho for the smallest ball (c, rho) enclosing the
+# lens; the pair runs on the smallest of a few fixed radius classes that is
+# at least that large (the largest when none is).
+# ---------------------------------------------------------------------------
+
+def lens_enclosing_ball(ci, cj, Ri, Rj, cell):
+    """Smallest ball enclosing B(C_i, R_i) cap B(C_j, R_j), the centres taken
+    under the minimum image.  Returns (f, rho): the ball is centred at
+    C_i + f (C_j - C_i) (f in [0, 1]) with radius rho; None when the
+    intersection is empty (d >= R_i + R_j).
+
+    With d = |C_j - C_i| and x = (d^2 + R_i^2 - R_j^2) / (2 d) the signed
+    distance from C_i to the plane of the two spheres' intersection circle:
+    if x <= 0 the intersection holds a great circle of B_i, so B_i itself is
+    the smallest enclosing ball; if x >= d the same holds for B_j; otherwise
+    both caps are at most hemispheres and the ball on the circle (centre on
+    the plane, radius sqrt(R_i^2 - x^2)) holds both.
+    """
+    dd = min_image_d2(ci, cj, cell)
+    d = math.sqrt(dd)
+    Ri, Rj = float(Ri), float(Rj)
+    if d >= Ri + Rj:
+        return None
+    if d == 0.0:
+        return 0.0, min(Ri, Rj)
+    x = (dd + Ri * Ri - Rj * Rj) / (2.0 * d)
+    if x <= 0.0:
+        return 0.0, Ri
+    if x >= d:
+        return 1.0, Rj
+    return x / d, math.sqrt(Ri * Ri - x * x)
+
+
+def pair_domain_radius(ci, cj, Ri, Rj, g, cell, n, self_pair):
+    """PE radius about the grid point g (pair origin) that holds Omega_ij:
+    |g - c| + rho (Omega_ii = Omega_i for the self pair); 0 when empty."""
+    if self_pair:
+        f, rho = 0.0, float(Ri)
+    else:
+        ball = lens_enclosing_ball(ci, cj, Ri, Rj, cell)
+        if ball is None:
+            return 0.0
+        f, rho = ball
+    e2 = 0.0
+    for a in range(3):
+        L = float(cell[a])
+        h = L / float(n[a])
+        d = float(cj[a]) - float(ci[a])
+        d -= L * float(_nint(d / L))
+        w = float(g[a]) * h - float(ci[a])
+        w -= L * float(_nint(w / L))
+        u = w - f * d
+        e2 += u * u
+    return math.sqrt(e2) + rho
+
+
+def pair_classes(centers, spreads, cell, n, r_pair, omega_scale, class_r_pe):
+    """Class of each pair of pair_list(): the smallest k with
+    class_r_pe[k] >= pair_domain_radius (the last class otherwise).
+    Returns (classes, capped)."""
+    Cc = np.asarray(centers, np.float64)
+    pi, pj = pair_list(Cc, cell, r_pair)
+    out = np.zeros(len(pi), np.int32)
+    capped = 0
+    for p, (i, j) in enumerate(zip(pi.tolist(), pj.tolist())):
+        g = pair_origin(Cc[i], Cc[j], cell, n)
+        r = pair_domain_radius(Cc[i], Cc[j], omega_scale * spreads[i], omega_scale * spreads[j], g, cell, n, i == j)
+        k = 0
+        while k < len(class_r_pe) and class_r_pe[k] < r:
+            k += 1
+        if k == len(class_r_pe):
+            k = len(class_r_pe) - 1
+            capped += 1
+        out[p] = k
+    return out, capped
+
+
+def exx_classed(n, cell, r_pair, classes, pair_class, centers, phi, tol=1e-10):
+    """E_xx and D (Eqs. exx_omega, Dxx_mlwf_omega) with each pair on its own
+    subdomain class: classes = [(r_pe, r_me), ...], pair_class[p] for the
+    pairs of pair_list().  Each pair is solved by the class's Subdomain; its
+    potential v (PE then shell, Alg. 2 order) adds v phi_j to D^i and v phi_i
+    to D^j at the grid points (g + offset) mod N."""
+    Cc = np.asarray(centers, np.float64)
+    phi = np.asarray(phi, np.float64)
+    N = np.asarray(n)
+    pi, pj = pair_list(Cc, cell, r_pair)
+    subs = [Subdomain(n, cell, a, b) for a, b in classes]
+    offs = [s.offsets() for s in subs]
+    D = np.zeros_like(phi)
+    e = np.zeros(len(pi))
+    E = 0.0
+    for p, (i, j) in enumerate(zip(pi.tolist(), pj.tolist())):
+        k = int(pair_class[p])
+        g = pair_origin(Cc[i], Cc[j], cell, n)
+        r = subs[k].solve_pair(phi[i], phi[j], g, tol=tol)
+        e[p] = r["e"]
+        E -= (1.0 if i == j else 2.0) * r["e"]
+        v = np.concatenate([r["x"], r["vsh"]])
+        gx = np.mod(g[None, :] + offs[k], N)
+        flat = (gx[:, 2] * N[1] + gx[:, 1]) * N[0] + gx[:, 0]
+        Di, Dj = D[i].reshape(-1), D[j].reshape(-1)
+        fi, fj = phi[i].reshape(-1), phi[j].reshape(-1)
+        np.add.at(Di, flat, v * fj[flat])
+        if i != j:
+            np.add.at(Dj, flat, v * fi[flat])
+    return E, D, dict(i=pi, j=pj, e=e)

@@ -65,7 +65,9 @@ struct exx_ctx {
     int n_cu = 0;
     double h[3] = {0, 0, 0};
     int c0[3] = {0, 0, 0};
-    HostClass cls[2];
+    HostClass cls[KMAX];
+    int n_cls = 2;            // classes in use (self / non-self unless params.n_classes >= 2)
+    int64_t class_capped = 0; // pairs of the list whose domain the largest class does not cover
     std::string err = "no error";
     int state = 0;  // 1 set up, 2 pairs built, 3 solved
 
@@ -433,7 +435,27 @@ exx_status build_mg_levels(exx_ctx *c, HostClass &k)
     return EXX_OK;
 }
 
-long long mg_slot_doubles(const exx_ctx *c) { return std::max(c->cls[0].mg_doubles, c->cls[1].mg_doubles); }
+long long mg_slot_doubles(const exx_ctx *c)
+{
+    long long m = 0;
+    for (int k = 0; k < c->n_cls; ++k) m = std::max(m, c->cls[k].mg_doubles);
+    return m;
+}
+
+// the class with the most PE points, and the largest PE / PE + shell sizes
+int big_class(const exx_ctx *c)
+{
+    int b = 0;
+    for (int k = 1; k < c->n_cls; ++k)
+        if (c->cls[k].n_pe > c->cls[b].n_pe) b = k;
+    return b;
+}
+long long max_me(const exx_ctx *c)
+{
+    long long m = 0;
+    for (int k = 0; k < c->n_cls; ++k) m = std::max(m, (long long)c->cls[k].n_pe + c->cls[k].n_sh);
+    return m;
+}
 
 ClassDev class_dev(const HostClass &k)
 {
@@ -478,8 +500,7 @@ OrbBox orb_box(const exx_ctx *c)
 DxxArgs dxx_args(const exx_ctx *c, const void *phi, void *dxx)
 {
     DxxArgs d{};
-    d.cls[0] = class_dev(c->cls[0]);
-    d.cls[1] = class_dev(c->cls[1]);
+    for (int k = 0; k < c->n_cls; ++k) d.cls[k] = class_dev(c->cls[k]);
     d.pair_gc = c->d_gc.p;
     d.pair_ij = c->d_ij.p;
     d.out_off = c->d_off.p;
@@ -609,7 +630,8 @@ exx_status install_variant(exx_ctx *c, const CgVariant &v, size_t lds)
 {
     c->var = v;
     c->lds_bytes = v.zmarch ? lds : 0;
-    for (auto &k : c->cls) {
+    for (int kk = 0; kk < c->n_cls; ++kk) {
+        HostClass &k = c->cls[kk];
         if (k.d_bands) { (void)hipFree(k.d_bands); k.d_bands = nullptr; }
         if (k.d_bands32) { (void)hipFree(k.d_bands32); k.d_bands32 = nullptr; }
         k.bands.clear();
@@ -650,7 +672,7 @@ void mg_args(const exx_ctx *c, SolveArgs &a, double *scratch)
 {
     a.mg = c->prm.precond == EXX_PRECOND_MG;
     if (!a.mg) return;
-    for (int k = 0; k < 2; ++k) {
+    for (int k = 0; k < c->n_cls; ++k) {
         const HostClass &hc = c->cls[k];
         a.mgc[k].levels = hc.mg_levels;
         a.mgc[k].dense_off = hc.mg_dense_off;
@@ -671,11 +693,12 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
 {
     // a preconditioned iteration costs about four plain ones
     const int kTuneIters = c->prm.precond == EXX_PRECOND_MG ? 15 : 60;
-    const HostClass &k = c->cls[1];
+    const int kb = big_class(c);               // the synthetic batch runs the largest class
+    const HostClass &k = c->cls[kb];
     int max_grid = 0;
     for (const Candidate &q : cands) max_grid = std::max(max_grid, q.per_cu * c->n_cu);
     const int n = 2 * max_grid;
-    const long long slot_n = ((long long)std::max(c->cls[0].n_pe, c->cls[1].n_pe) + 1 + 63) / 64 * 64;
+    const long long slot_n = ((long long)k.n_pe + 1 + 63) / 64 * 64;
     const long long per_pair = (long long)k.n_pe + k.n_sh;
     const size_t ngrid = (size_t)c->prm.n_grid[0] * c->prm.n_grid[1] * c->prm.n_grid[2];
     const bool mixed = c->prm.precision == EXX_FP32_REFINE;
@@ -713,7 +736,7 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
         for (auto &x : ev) if (x) (void)hipEventDestroy(x);
         return -1;
     }
-    std::vector<int4> hgc((size_t)n, int4{0, 0, 0, 1});
+    std::vector<int4> hgc((size_t)n, int4{0, 0, 0, kb});
     std::vector<int2> hij((size_t)n, int2{0, 0});
     std::vector<long long> hoff((size_t)n);
     for (int p = 0; p < n; ++p) hoff[p] = (long long)p * per_pair;
@@ -760,8 +783,7 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
     mg_args(c, a, mgs);
     for (size_t i = 0; ok && i < cands.size(); ++i) {
         if (install_variant(c, cands[i].v, cands[i].lds) != EXX_OK) { ok = false; break; }
-        a.cls[0] = class_dev(c->cls[0]);
-        a.cls[1] = class_dev(c->cls[1]);
+        for (int kk = 0; kk < c->n_cls; ++kk) a.cls[kk] = class_dev(c->cls[kk]);
         const int grid = std::min(n, cands[i].per_cu * c->n_cu);
         float ms = 0.f;
         for (int rep = 0; rep < 2 && ok; ++rep) {
@@ -789,7 +811,6 @@ exx_status select_variant(exx_ctx *c)
     CgVariant vs[32];
     const int nv = cg_variants(vs, 32);
     std::vector<Candidate> cands;
-    std::vector<int> b0, b1;
     const int mode = cg_mode(c->prm.precision, c->prm.guess != EXX_GUESS_ZERO, c->prm.precond == EXX_PRECOND_MG);
     bool flat = false;
     for (int i = 0; i < nv; ++i) {
@@ -798,20 +819,20 @@ exx_status select_variant(exx_ctx *c)
         if (!v.zmarch) continue;
         if (c->prm.block_threads && v.block != c->prm.block_threads) continue;
         if (c->prm.cg_cols && v.cols != c->prm.cg_cols) continue;
-        int r0 = 0, r1 = 0, s0 = 0, s1 = 0;
-        std::vector<int> f0, f1;
-        if (!make_bands(c->cls[0], v.cols, v.halo, v.block, b0, &r0) ||
-            !make_bands(c->cls[1], v.cols, v.halo, v.block, b1, &r1))
-            continue;
-        if (c->prm.precision == EXX_FP32_REFINE &&
-            (!make_bands(c->cls[0], v.cols32, v.halo32, v.block, f0, &s0) ||
-             !make_bands(c->cls[1], v.cols32, v.halo32, v.block, f1, &s1)))
-            continue;
-        const size_t lds = std::max(zmarch_lds(c->cls[0], r0, s0), zmarch_lds(c->cls[1], r1, s1));
-        if (lds > kMaxLds) continue;
+        bool fits = true;
+        size_t lds = 0;
+        int nb = 0;
+        for (int k = 0; k < c->n_cls && fits; ++k) {
+            int r = 0, r32 = 0;
+            std::vector<int> bk, fk;
+            fits = make_bands(c->cls[k], v.cols, v.halo, v.block, bk, &r) &&
+                   (c->prm.precision != EXX_FP32_REFINE || make_bands(c->cls[k], v.cols32, v.halo32, v.block, fk, &r32));
+            if (fits) lds = std::max(lds, zmarch_lds(c->cls[k], r, r32));
+            nb += (int)bk.size() / 12;
+        }
+        if (!fits || lds > kMaxLds) continue;
         int per_cu = 0;
         if (cg_occupancy(v, mode, lds, &per_cu) != hipSuccess || per_cu < 1) continue;
-        const int nb = (int)(b0.size() + b1.size()) / 12;
         cands.push_back({v, lds, per_cu, (long)per_cu * v.block / 64 * 1000 + per_cu * 100 - nb});
     }
     c->tuned = 0;
@@ -891,11 +912,25 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         return fail(nullptr, EXX_EINVAL, "inner_rtol must lie in (0, 1)");
     double hmax = 0.0;
     for (int a = 0; a < 3; ++a) hmax = std::max(hmax, p->cell[a] / p->n_grid[a]);
-    for (int c = 0; c < 2; ++c) {
-        if (!(p->r_pe[c] > 0.0)) return fail(nullptr, EXX_EINVAL, "r_pe[%d] must be positive", c);
-        if (p->r_me[c] - p->r_pe[c] < 3 * hmax * (1.0 - 1e-12))
-            return fail(nullptr, EXX_EINVAL, "r_me[%d] - r_pe[%d] = %g < n max(h) = %g", c, c, p->r_me[c] - p->r_pe[c],
-                        3 * hmax);
+    if (p->n_classes != 0 && (p->n_classes < 2 || p->n_classes > EXX_MAX_CLASSES))
+        return fail(nullptr, EXX_EINVAL, "n_classes = %d: 0 or 2..%d", p->n_classes, EXX_MAX_CLASSES);
+    const bool classed = p->n_classes >= 2;
+    if (classed && p->guess == EXX_GUESS_LEARNED)
+        return fail(nullptr, EXX_EINVAL, "the learned guess needs n_classes = 0 (two classes)");
+    if (classed && !(p->omega_scale > 0.0 && std::isfinite(p->omega_scale)))
+        return fail(nullptr, EXX_EINVAL, "omega_scale must be positive");
+    const int ncls = classed ? p->n_classes : 2;
+    double rpe[KMAX], rme[KMAX];
+    for (int c = 0; c < ncls; ++c) {
+        rpe[c] = classed ? p->class_r_pe[c] : p->r_pe[c];
+        rme[c] = classed ? p->class_r_me[c] : p->r_me[c];
+        const char *pn = classed ? "class_" : "";
+        if (!(rpe[c] > 0.0)) return fail(nullptr, EXX_EINVAL, "%sr_pe[%d] must be positive", pn, c);
+        if (rme[c] - rpe[c] < 3 * hmax * (1.0 - 1e-12))
+            return fail(nullptr, EXX_EINVAL, "%sr_me[%d] - %sr_pe[%d] = %g < n max(h) = %g", pn, c, pn, c,
+                        rme[c] - rpe[c], 3 * hmax);
+        if (classed && c > 0 && !(rpe[c] > rpe[c - 1]))
+            return fail(nullptr, EXX_EINVAL, "class_r_pe must be strictly ascending");
     }
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
@@ -920,8 +955,9 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         c->box[a] = p->box_dims[a] > 0 ? p->box_dims[a] : p->n_grid[a];
     }
     c->box_vol = (long long)c->box[0] * c->box[1] * c->box[2];
-    for (int k = 0; k < 2; ++k) {
-        exx_status st = build_class(c, c->cls[k], p->r_pe[k], p->r_me[k]);
+    c->n_cls = ncls;
+    for (int k = 0; k < ncls; ++k) {
+        exx_status st = build_class(c, c->cls[k], rpe[k], rme[k]);
         if (st != EXX_OK) return bail(st);
         if (p->precond == EXX_PRECOND_MG && (st = build_mg_levels(c, c->cls[k])) != EXX_OK) return bail(st);
     }
@@ -1073,9 +1109,55 @@ void unique_pair_owners(exx_ctx *c)
     c->owner_sweeps = sweeps;
 }
 
-exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pairs)
+// Radius the PE sphere about the pair origin g needs to hold the pair domain
+// Omega_ij = Omega_i cap Omega_j (balls of radius omega_scale * spread about
+// the centres): |g - c| + rho for the smallest ball (c, rho) enclosing the
+// lens, in the cases the header lists; 0 for an empty domain.
+double pair_domain_radius(const exx_ctx *c, int i, int j, const int4 &g, const double *C, const double *spr)
 {
-    if (!c) return fail(nullptr, EXX_EINVAL, "exx_pairs: ctx is NULL");
+    const double *L = c->prm.cell;
+    const double Ri = c->prm.omega_scale * spr[i], Rj = c->prm.omega_scale * spr[j];
+    const int gg[3] = {g.x, g.y, g.z};
+    double d[3], o[3], dd = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        double v = C[3 * j + a] - C[3 * i + a];
+        v -= L[a] * (double)nint_away(v / L[a]);
+        d[a] = v;
+        dd += v * v;
+        double w = (double)gg[a] * c->h[a] - C[3 * i + a];
+        w -= L[a] * (double)nint_away(w / L[a]);
+        o[a] = w;
+    }
+    const double dist = std::sqrt(dd);
+    double f = 0.0, rho;                 // lens centre at C_i + f (C_j - C_i)
+    if (i == j) {
+        rho = Ri;
+    } else if (dist >= Ri + Rj) {
+        return 0.0;
+    } else if (dist == 0.0) {
+        rho = std::min(Ri, Rj);
+    } else {
+        const double x = (dd + Ri * Ri - Rj * Rj) / (2.0 * dist);
+        if (x <= 0.0) {
+            rho = Ri;
+        } else if (x >= dist) {
+            f = 1.0;
+            rho = Rj;
+        } else {
+            f = x / dist;
+            rho = std::sqrt(Ri * Ri - x * x);
+        }
+    }
+    double e2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+        const double u = o[a] - f * d[a];
+        e2 += u * u;
+    }
+    return std::sqrt(e2) + rho;
+}
+
+exx_status pairs_common(exx_ctx *c, int32_t n_orb, const double *C, const double *spreads, int64_t *n_pairs)
+{
     if (c->state < 1) return fail(c, EXX_ESTATE, "exx_pairs before exx_setup");
     if (n_orb < 1 || !C) return fail(c, EXX_EINVAL, "exx_pairs: need n_orb >= 1 and centers");
     if (hipSetDevice(c->device) != hipSuccess) return fail(c, EXX_EDEVICE, "hipSetDevice failed");
@@ -1092,6 +1174,20 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     }
     c->n_self = n_orb;
     c->n_pairs = (int64_t)c->ij.size();
+    c->class_capped = 0;
+    if (spreads) {
+        // per-pair classes: the smallest class whose PE sphere covers Omega_ij
+        for (size_t p = 0; p < c->ij.size(); ++p) {
+            const double r = pair_domain_radius(c, c->ij[p].x, c->ij[p].y, c->gc[p], C, spreads);
+            int k = 0;
+            while (k < c->n_cls && c->cls[k].r_pe < r) ++k;
+            if (k == c->n_cls) {
+                k = c->n_cls - 1;
+                ++c->class_capped;
+            }
+            c->gc[p].w = k;
+        }
+    }
     c->n_orb = n_orb;
     // orbital boxes: origin = nearest grid point of the centre minus half the
     // box; a box as wide as the grid has origin 0
@@ -1163,7 +1259,7 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     c->slots = c->grid;
     // one spare element past the largest PE vector: the z-march kernels store
     // the values of unused lanes there
-    c->slot_n = ((long long)std::max(c->cls[0].n_pe, c->cls[1].n_pe) + 1 + 63) / 64 * 64;
+    c->slot_n = ((long long)c->cls[big_class(c)].n_pe + 1 + 63) / 64 * 64;
     if (c->prm.precision == EXX_FP32_REFINE) {
         if (!c->var.zmarch) return fail(c, EXX_EINVAL, "FP32 refinement needs a z-march CG kernel");
         if ((st = dev_reserve(c, c->d_scratch32, (size_t)c->slots * 4 * c->slot_n)) != EXX_OK) return st;
@@ -1180,8 +1276,7 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     {
         size_t freeb = 0, totalb = 0;
         HIPCHK(c, hipMemGetInfo(&freeb, &totalb));
-        const long long v_max = std::max<long long>((long long)c->cls[0].n_pe + c->cls[0].n_sh,
-                                                    (long long)c->cls[1].n_pe + c->cls[1].n_sh);
+        const long long v_max = max_me(c);
         const size_t per_pair = (size_t)(c->slot_n + v_max) * sizeof(double);
         const size_t have = (c->d_rhs.n + c->d_vout.n + c->d_dacc.n) * sizeof(double);
         // keep 2 GiB free, and room for the model or the guess history
@@ -1235,6 +1330,24 @@ exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pair
     return EXX_OK;
 }
 
+exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pairs)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_pairs: ctx is NULL");
+    if (c->prm.n_classes >= 2) return fail(c, EXX_EINVAL, "n_classes >= 2: the pair classes need exx_pairs_spread");
+    return pairs_common(c, n_orb, C, nullptr, n_pairs);
+}
+
+exx_status exx_pairs_spread(exx_ctx *c, int32_t n_orb, const double *C, const double *spreads, int64_t *n_pairs)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_pairs_spread: ctx is NULL");
+    if (c->prm.n_classes < 2) return fail(c, EXX_EINVAL, "exx_pairs_spread needs n_classes >= 2");
+    if (!spreads || n_orb < 1) return fail(c, EXX_EINVAL, "exx_pairs_spread: need n_orb >= 1 and spreads");
+    for (int i = 0; i < n_orb; ++i)
+        if (!(spreads[i] >= 0.0) || !std::isfinite(spreads[i]))
+            return fail(c, EXX_EINVAL, "spread %d is negative or not finite", i);
+    return pairs_common(c, n_orb, C, spreads, n_pairs);
+}
+
 exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_solve: ctx is NULL");
@@ -1243,8 +1356,7 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
     SolveArgs a{};
-    a.cls[0] = class_dev(c->cls[0]);
-    a.cls[1] = class_dev(c->cls[1]);
+    for (int k = 0; k < c->n_cls; ++k) a.cls[k] = class_dev(c->cls[k]);
     a.pair_gc = c->d_gc.p;
     a.pair_ij = c->d_ij.p;
     a.out_off = c->d_off.p;
@@ -1306,6 +1418,7 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
                 auto it = h.index.find(key);
                 if (it == h.index.end()) break;
                 const int q = it->second;
+                if (h.gc[q].w != c->gc[p].w) break;   // another class: another PE sphere
                 t.off[k] = h.off[q];
                 int sh[3] = {c->gc[p].x - h.gc[q].x, c->gc[p].y - h.gc[q].y, c->gc[p].z - h.gc[q].z};
                 for (int d = 0; d < 3; ++d) {
@@ -1325,8 +1438,7 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
         }
         exx_status st2 = upload_async(c, c->d_guess, tab, s, true);
         if (st2 != EXX_OK) return st2;
-        ga.cls[0] = a.cls[0];
-        ga.cls[1] = a.cls[1];
+        for (int k = 0; k < c->n_cls; ++k) ga.cls[k] = a.cls[k];
         ga.pair_gc = c->d_gc.p;
         ga.out_off = c->d_off.p;
         ga.guess = c->d_guess.p;
@@ -1379,8 +1491,9 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
             if (events && (e = hipEventRecord(c->ev_cg[2 * wi + 1], st)) != hipSuccess) return e;
             if ((e = launch_pair_energy(a, st)) != hipSuccess) return e;
             if (use_guess &&
-                (e = launch_save_history(c->d_vout.p, c->d_off.p, c->d_hist_off.p, c->d_gc.p, c->cls[0].n_pe,
-                                         c->cls[1].n_pe, a.wave_begin, a.wave_n, nx.v.p, st)) != hipSuccess)
+                (e = launch_save_history(c->d_vout.p, c->d_off.p, c->d_hist_off.p, c->d_gc.p,
+                                         int4{c->cls[0].n_pe, c->cls[1].n_pe, c->cls[2].n_pe, c->cls[3].n_pe},
+                                         a.wave_begin, a.wave_n, nx.v.p, st)) != hipSuccess)
                 return e;
             if (multi) {
                 // this wave's share of D, added to the partial sums in pair order
@@ -1493,6 +1606,13 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
         st->n_pe[k] = c->cls[k].n_pe;
         st->n_me[k] = c->cls[k].n_pe + c->cls[k].n_sh;
     }
+    st->n_classes = c->n_cls;
+    for (int k = 0; k < c->n_cls; ++k) {
+        st->class_n_pe[k] = c->cls[k].n_pe;
+        st->class_n_me[k] = c->cls[k].n_pe + c->cls[k].n_sh;
+    }
+    for (const int4 &q : c->gc) st->class_pairs[q.w]++;
+    st->class_capped = c->class_capped;
     st->device_bytes = (int64_t)(c->d_vout.n * 8 + c->d_scratch.n * 8 + c->d_scratch32.n * 4 + c->d_q.n * 8 +
                                  c->d_rhs.n * 8 + c->d_rho_keep.n * 8);
     if (c->state < 3) return EXX_OK;
@@ -1563,6 +1683,15 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     return EXX_OK;
 }
 
+exx_status exx_pair_class(exx_ctx *c, int32_t *cls)
+{
+    if (!c) return fail(nullptr, EXX_EINVAL, "exx_pair_class: ctx is NULL");
+    if (c->state < 2) return fail(c, EXX_ESTATE, "exx_pair_class before exx_pairs");
+    if (!cls) return fail(c, EXX_EINVAL, "exx_pair_class: cls is NULL");
+    for (size_t p = 0; p < c->gc.size(); ++p) cls[p] = c->gc[p].w;
+    return EXX_OK;
+}
+
 exx_status exx_pair_owners(exx_ctx *c, int32_t *owner, int32_t *sweeps)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_pair_owners: ctx is NULL");
@@ -1624,6 +1753,7 @@ exx_status exx_model_init(exx_ctx *c, int32_t coarsen, uint64_t seed)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_init: ctx is NULL");
     if (coarsen != 2 && coarsen != 4) return fail(c, EXX_EINVAL, "coarsen must be 2 or 4 (got %d)", coarsen);
+    if (c->prm.n_classes >= 2) return fail(c, EXX_EINVAL, "the learned guess needs n_classes = 0 (two classes)");
     HIPCHK(c, hipSetDevice(c->device));
     net_destroy(c->net);
     c->net = nullptr;
@@ -1648,6 +1778,7 @@ exx_status exx_model_init(exx_ctx *c, int32_t coarsen, uint64_t seed)
 exx_status exx_load_model(exx_ctx *c, const void *weights, size_t bytes)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_load_model: ctx is NULL");
+    if (c->prm.n_classes >= 2) return fail(c, EXX_EINVAL, "the learned guess needs n_classes = 0 (two classes)");
     const int f = net_blob_coarsen(weights, bytes);
     if (f < 0)
         return fail(c, EXX_EINVAL, "exx_load_model: not a model blob of %zu bytes (got %zu)", net_model_bytes(), bytes);

@@ -10,6 +10,7 @@ namespace exx {
 constexpr int LMAX = 6;                      // multipole order (Eq. me)
 constexpr int NLM = (LMAX + 1) * (LMAX + 1); // 49 real harmonics
 constexpr int FD_N = 3;                      // stencil half-width (Eq. d2_1)
+constexpr int KMAX = 4;                      // subdomain classes (pair.w indexes them)
 
 // Local offsets (grid units, |o| < 512) packed into one int: 10 bits per axis.
 __host__ __device__ inline int pack_xyz(int x, int y, int z)
@@ -118,7 +119,7 @@ struct MgClass {
 };
 
 struct SolveArgs {
-    ClassDev cls[2];
+    ClassDev cls[KMAX];
     const int4 *pair_gc;        // [n_pairs] {gx, gy, gz, class}
     const int2 *pair_ij;        // [n_pairs] {i, j}
     const long long *out_off;   // [n_pairs] offset of the pair's v in vout (relative to its wave)
@@ -153,7 +154,7 @@ struct SolveArgs {
     // multigrid-preconditioned CG (FP64): two more fine vectors per slot
     // (scratch holds 5 per slot) and per-slot coarse arrays
     int mg;
-    MgClass mgc[2];             // coarse levels per class
+    MgClass mgc[KMAX];          // coarse levels per class
     double *mg_scratch;         // per slot: mg_slot_n doubles
     long long mg_slot_n;
     double mg_omega;            // damping of the fine Jacobi smoother
@@ -170,7 +171,7 @@ struct PairGuess {
 };
 
 struct GuessArgs {
-    ClassDev cls[2];
+    ClassDev cls[KMAX];
     const int4 *pair_gc;
     const long long *out_off;
     const PairGuess *guess;    // [n_pairs]
@@ -180,7 +181,7 @@ struct GuessArgs {
 };
 
 struct DxxArgs {
-    ClassDev cls[2];
+    ClassDev cls[KMAX];
     const int4 *pair_gc;
     const int2 *pair_ij;
     const long long *out_off;
@@ -250,7 +251,7 @@ hipError_t launch_energy(const double *e, const int2 *ij, int n_pairs, double *o
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
 hipError_t launch_guess(const GuessArgs &a, int n_pairs, hipStream_t s);
 hipError_t launch_save_history(const double *vout, const long long *out_off, const long long *hist_off,
-                               const int4 *pair_gc, int n_pe0, int n_pe1, int wave_begin, int wave_n, float *hist,
+                               const int4 *pair_gc, int4 n_pe, int wave_begin, int wave_n, float *hist,
                                hipStream_t s);
 
 // Learned initial guess (exx_net.hip).  The net reads a pair's right-hand

@@ -142,7 +142,7 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep(SolveArgs a)
     const int pair = a.wave_begin + blockIdx.x;
     const int4 pg = a.pair_gc[pair];
     const int2 ij = a.pair_ij[pair];
-    const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
+    const ClassDev g = a.cls[pg.w];
     double *v_sh = a.vout + a.out_off[pair] + g.n_pe;
     double *bv = a.rhs + (long long)blockIdx.x * a.slot_n;
     double *keep = a.rho_keep ? a.rho_keep + (long long)pair * a.slot_n : nullptr;
@@ -237,7 +237,7 @@ __device__ void cg_one_pair(const SolveArgs &a, int pair, long long slot, double
     const int tid = threadIdx.x;
     const int4 pg = a.pair_gc[pair];
     const int2 ij = a.pair_ij[pair];
-    const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
+    const ClassDev g = a.cls[pg.w];
     double *xv = a.vout + a.out_off[pair];
     const double *bv = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
     double *r = a.scratch + slot * 3 * a.slot_n;
@@ -1135,7 +1135,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     const int tid = threadIdx.x;
     const int4 pg = a.pair_gc[pair];
     const int2 ij = a.pair_ij[pair];
-    const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
+    const ClassDev g = a.cls[pg.w];
     double *x = a.vout + a.out_off[pair];
     const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
     const StencilW<double> w64 = stencil_w<double>(a);
@@ -1437,7 +1437,7 @@ __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
         const int cls = a.pair_gc[a.wave_begin + k].w;
         if (cls != last_cls) {
             // the row-offset table of the class lives at the start of LDS
-            const ClassDev g = cls ? a.cls[1] : a.cls[0];
+            const ClassDev g = a.cls[cls];
             int *tbl = reinterpret_cast<int *>(lds_dyn);
             for (int t = threadIdx.x; t < g.pnz * g.pny; t += T) tbl[t] = g.pe_off[t];
             __syncthreads();
@@ -1458,7 +1458,7 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_pair_energy(SolveArgs a)
     const int pair = a.wave_begin + blockIdx.x;
     const int4 pg = a.pair_gc[pair];
     const int2 ij = a.pair_ij[pair];
-    const ClassDev &g = pg.w ? a.cls[1] : a.cls[0];
+    const ClassDev &g = a.cls[pg.w];
     const double *x = a.vout + a.out_off[pair];
     const long long oi = (long long)ij.x * a.box.vol, oj = (long long)ij.y * a.box.vol;
     const int4 org_i = a.box.org[ij.x], org_j = a.box.org[ij.y];
@@ -1515,7 +1515,7 @@ __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
         const int4 pg = a.pair_gc[pair];
         const int2 ij = a.pair_ij[pair];
         const int other = ij.x == k ? ij.y : ij.x;
-        const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
+        const ClassDev g = a.cls[pg.w];
         const double *v = a.vout + a.out_off[pair];
         const long long oo = (long long)other * B.vol;
         const int4 oo_org = B.org[other];
@@ -1569,7 +1569,7 @@ __global__ __launch_bounds__(256) void k_guess(GuessArgs a)
 {
     const int pair = a.wave_begin + blockIdx.x;
     const int4 pg = a.pair_gc[pair];
-    const ClassDev g = pg.w ? a.cls[1] : a.cls[0];
+    const ClassDev g = a.cls[pg.w];
     const PairGuess pgs = a.guess[pair];
     double *x = a.vout + a.out_off[pair];
     for (int q = threadIdx.x; q < g.n_pe; q += 256) {
@@ -1589,11 +1589,12 @@ __global__ __launch_bounds__(256) void k_guess(GuessArgs a)
 
 // hist[hist_off[p] + q] = v_p on PE (FP32), for every pair.
 __global__ __launch_bounds__(256) void k_save_history(const double *vout, const long long *out_off,
-                                                      const long long *hist_off, const int4 *pair_gc, int n_pe0,
-                                                      int n_pe1, int wave_begin, float *hist)
+                                                      const long long *hist_off, const int4 *pair_gc, int4 n_pe,
+                                                      int wave_begin, float *hist)
 {
     const int p = wave_begin + blockIdx.x;
-    const int n = pair_gc[p].w ? n_pe1 : n_pe0;
+    const int w = pair_gc[p].w;
+    const int n = w == 0 ? n_pe.x : w == 1 ? n_pe.y : w == 2 ? n_pe.z : n_pe.w;
     const double *src = vout + out_off[p];
     float *dst = hist + hist_off[p];
     for (int q = threadIdx.x; q < n; q += 256) dst[q] = (float)src[q];
@@ -1747,10 +1748,10 @@ hipError_t launch_guess(const GuessArgs &a, int n_pairs, hipStream_t s)
 }
 
 hipError_t launch_save_history(const double *vout, const long long *out_off, const long long *hist_off,
-                               const int4 *pair_gc, int n_pe0, int n_pe1, int wave_begin, int wave_n, float *hist,
+                               const int4 *pair_gc, int4 n_pe, int wave_begin, int wave_n, float *hist,
                                hipStream_t s)
 {
-    hipLaunchKernelGGL(k_save_history, dim3(wave_n), dim3(256), 0, s, vout, out_off, hist_off, pair_gc, n_pe0, n_pe1,
+    hipLaunchKernelGGL(k_save_history, dim3(wave_n), dim3(256), 0, s, vout, out_off, hist_off, pair_gc, n_pe,
                        wave_begin, hist);
     return hipGetLastError();
 }

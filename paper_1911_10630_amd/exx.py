@@ -27,7 +27,8 @@ NLM = 49
 EXPORTS = ["exx_default_params", "exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats",
            "exx_pair_info", "exx_debug_pair", "exx_last_error", "exx_destroy", "exx_model_init", "exx_model_train",
            "exx_model_save", "exx_load_model", "exx_model_edge", "exx_model_conv", "exx_model_wgrad",
-           "exx_box_origins", "exx_pair_owners"]
+           "exx_box_origins", "exx_pair_owners", "exx_pairs_spread",
+           "exx_pair_class"]
 
 
 class ExxParams(C.Structure):
@@ -38,7 +39,8 @@ class ExxParams(C.Structure):
                 ("inner_rtol", C.c_double), ("block_threads", C.c_int32), ("cg_cols", C.c_int32),
                 ("wave_pairs", C.c_int64),
                 ("keep_intermediates", C.c_int32), ("autotune", C.c_int32), ("graph", C.c_int32),
-                ("box_dims", C.c_int32 * 3), ("precond", C.c_int32)]
+                ("box_dims", C.c_int32 * 3), ("precond", C.c_int32), ("n_classes", C.c_int32),
+                ("class_r_pe", C.c_double * 4), ("class_r_me", C.c_double * 4), ("omega_scale", C.c_double)]
 
 
 class ExxStats(C.Structure):
@@ -51,7 +53,9 @@ class ExxStats(C.Structure):
                 ("n_me", C.c_int64 * 2), ("cg_bytes", C.c_int64), ("solve_bytes", C.c_int64),
                 ("dxx_bytes", C.c_int64), ("device_bytes", C.c_int64), ("n_waves", C.c_int32), ("wave_n", C.c_int32),
                 ("guess_pairs", C.c_int32), ("guess_ms", C.c_double), ("tuned", C.c_int32),
-                ("tune_ms", C.c_double), ("graph_builds", C.c_int32), ("graph_launches", C.c_int32)]
+                ("tune_ms", C.c_double), ("graph_builds", C.c_int32), ("graph_launches", C.c_int32),
+                ("n_classes", C.c_int32), ("class_n_pe", C.c_int64 * 4), ("class_n_me", C.c_int64 * 4),
+                ("class_pairs", C.c_int64 * 4), ("class_capped", C.c_int64)]
 
 
 class ExxError(RuntimeError):
@@ -88,6 +92,8 @@ def load() -> C.CDLL:
     L.exx_destroy.restype = None
     L.exx_box_origins.argtypes = [vp, vp]
     L.exx_pair_owners.argtypes = [vp, vp, vp]
+    L.exx_pairs_spread.argtypes = [vp, i32, vp, vp, C.POINTER(i64)]
+    L.exx_pair_class.argtypes = [vp, vp]
     L.exx_model_init.argtypes = [vp, i32, C.c_uint64]
     L.exx_model_train.argtypes = [vp, i32, i32, C.c_double, C.c_uint64, dp, vp]
     L.exx_model_save.argtypes = [vp, vp, C.POINTER(C.c_size_t)]
@@ -124,7 +130,8 @@ class Exx:
 
     def __init__(self, n_grid, cell, r_pair, r_pe, r_me, *, cg_rtol=1e-10, cg_max_iter=20000,
                  precision="fp64", orbital_dtype="f64", guess="zero", inner_rtol=1e-5, block_threads=0,
-                 cg_cols=0, wave_pairs=0, keep_intermediates=False, autotune=True, graph=False, box=None, precond="none", device=0):
+                 cg_cols=0, wave_pairs=0, keep_intermediates=False, autotune=True, graph=False, box=None, precond="none",
+                 classes=None, omega_scale=0.0, device=0):
         L = load()
         p = ExxParams()
         L.exx_default_params(C.byref(p))
@@ -149,6 +156,12 @@ class Exx:
         p.autotune = 1 if autotune else 0
         p.graph = 1 if graph else 0
         p.precond = PRECOND[precond]
+        if classes is not None:
+            # per-pair subdomain classes: [(r_pe, r_me), ...], r_pe ascending
+            p.n_classes = len(classes)
+            for k, (a, b) in enumerate(classes):
+                p.class_r_pe[k], p.class_r_me[k] = float(a), float(b)
+            p.omega_scale = float(omega_scale)
         if box is not None:
             for a in range(3):
                 p.box_dims[a] = int(box[a])
@@ -182,6 +195,16 @@ class Exx:
         c = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, 3))
         n = C.c_int64()
         self._check(load().exx_pairs(self._h, c.shape[0], _ptr(c), C.byref(n)))
+        self.n_pairs = int(n.value)
+        self.n_orb = c.shape[0]
+        return self.n_pairs
+
+    def pairs_spread(self, centers, spreads) -> int:
+        """The pair list with per-pair classes from the orbitals' spreads (bohr)."""
+        c = np.ascontiguousarray(np.asarray(centers, dtype=np.float64).reshape(-1, 3))
+        sp = np.ascontiguousarray(np.asarray(spreads, dtype=np.float64).reshape(-1))
+        n = C.c_int64()
+        self._check(load().exx_pairs_spread(self._h, c.shape[0], _ptr(c), _ptr(sp), C.byref(n)))
         self.n_pairs = int(n.value)
         self.n_orb = c.shape[0]
         return self.n_pairs
@@ -239,6 +262,12 @@ class Exx:
                                          _ptr(d.get("e")), _ptr(d.get("iters")), _ptr(d.get("converged")),
                                          _ptr(d.get("relres"))))
         return d
+
+    def pair_class(self) -> np.ndarray:
+        """Subdomain class of each pair in pair_info order."""
+        out = np.zeros(self.n_pairs, np.int32)
+        self._check(load().exx_pair_class(self._h, _ptr(out)))
+        return out
 
     def pair_owners(self):
         """Alg. 1 owner (i or j) of each pair in pair_info order, and the sweep count."""

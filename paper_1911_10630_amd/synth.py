@@ -310,6 +310,14 @@ def c1_boxed(seed: int = 4321) -> Workload:
                     (5.0 * ANG, 5.0 * ANG), seed=seed, box=(76, 76, 76))
 
 
+def spreads(orbs: OrbitalSet) -> np.ndarray:
+    """Spread of each orbital (bohr): the root of the second moment of |phi|^2
+    about the centre for the Gaussian factor, 3 / (4 alpha) for s and
+    5 / (4 alpha) for p orbitals (the small polynomial corrections ignored)."""
+    m2 = np.where(orbs.kind == 1, 5.0, 3.0) / (4.0 * orbs.alpha)
+    return np.sqrt(m2)
+
+
 def md_displace(orbs: OrbitalSet, L: float, rng, sigma_ang: float = 0.02) -> OrbitalSet:
     """One synthetic MD step: Gaussian centre displacement, shapes fixed."""
     C = np.mod(orbs.centers + rng.normal(scale=sigma_ang * ANG, size=orbs.centers.shape), L)

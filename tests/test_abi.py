@@ -39,6 +39,7 @@ def _c_layout():
 #include <stddef.h>
 #include "exx.h"
 #define O(T, f) printf("%s %zu\n", #f, offsetof(T, f));
+#define OS(f) printf("s_%s %zu\n", #f, offsetof(exx_stats_t, f));
 int main(void) {
   printf("params %zu\n", sizeof(exx_params));
   O(exx_params, n_grid) O(exx_params, cell) O(exx_params, r_pair) O(exx_params, r_pe) O(exx_params, r_me)
@@ -46,11 +47,11 @@ int main(void) {
   O(exx_params, precision) O(exx_params, orbital_dtype) O(exx_params, guess) O(exx_params, inner_rtol)
   O(exx_params, block_threads) O(exx_params, cg_cols) O(exx_params, wave_pairs) O(exx_params, keep_intermediates)
   O(exx_params, autotune) O(exx_params, graph) O(exx_params, box_dims) O(exx_params, precond)
+  O(exx_params, n_classes) O(exx_params, class_r_pe) O(exx_params, class_r_me) O(exx_params, omega_scale)
   printf("stats %zu\n", sizeof(exx_stats_t));
-  O(exx_stats_t, relres_max) O(exx_stats_t, cg_ms) O(exx_stats_t, n_pe) O(exx_stats_t, n_me)
-  O(exx_stats_t, cg_bytes) O(exx_stats_t, n_waves) O(exx_stats_t, cg_bands) O(exx_stats_t, outer_total)
-  O(exx_stats_t, guess_pairs) O(exx_stats_t, guess_ms) O(exx_stats_t, tuned) O(exx_stats_t, tune_ms)
-  O(exx_stats_t, graph_builds) O(exx_stats_t, graph_launches) O(exx_stats_t, wave_n)
+  OS(relres_max) OS(cg_ms) OS(n_pe) OS(n_me) OS(cg_bytes) OS(n_waves) OS(cg_bands) OS(outer_total)
+  OS(guess_pairs) OS(guess_ms) OS(tuned) OS(tune_ms) OS(graph_builds) OS(graph_launches) OS(wave_n)
+  OS(n_classes) OS(class_n_pe) OS(class_pairs) OS(class_capped)
   return 0;
 }
 '''
@@ -69,11 +70,13 @@ def test_struct_layout_matches_header():
     assert lay["stats"] == C.sizeof(X.ExxStats)
     for f in ["n_grid", "cell", "r_pair", "r_pe", "r_me", "fd_half_width", "l_max", "cg_rtol", "cg_max_iter",
               "precision", "orbital_dtype", "guess", "inner_rtol", "block_threads", "cg_cols", "wave_pairs",
-              "keep_intermediates", "autotune", "graph", "box_dims", "precond"]:
+              "keep_intermediates", "autotune", "graph", "box_dims", "precond", "n_classes", "class_r_pe",
+              "class_r_me", "omega_scale"]:
         assert lay[f] == getattr(X.ExxParams, f).offset, f
     for f in ["relres_max", "cg_ms", "n_pe", "n_me", "cg_bytes", "n_waves", "cg_bands", "outer_total",
-              "guess_pairs", "guess_ms", "tuned", "tune_ms", "graph_builds", "graph_launches", "wave_n"]:
-        assert lay[f] == getattr(X.ExxStats, f).offset, f
+              "guess_pairs", "guess_ms", "tuned", "tune_ms", "graph_builds", "graph_launches", "wave_n",
+              "n_classes", "class_n_pe", "class_pairs", "class_capped"]:
+        assert lay["s_" + f] == getattr(X.ExxStats, f).offset, f
 
 
 def test_default_params():
@@ -121,6 +124,13 @@ def _setup_status(**over):
     (dict(box_dims=(49, 0, 0)), "box_dims"),
     (dict(precond=2), "precond"),
     (dict(precond=1, precision=1), "precond"),
+    (dict(n_classes=1), "n_classes"),
+    (dict(n_classes=5), "n_classes"),
+    (dict(n_classes=2, class_r_pe=(3.0, 2.0, 0, 0), class_r_me=(5.0, 4.0, 0, 0), omega_scale=3.0), "ascending"),
+    (dict(n_classes=2, class_r_pe=(2.0, 3.0, 0, 0), class_r_me=(2.5, 5.0, 0, 0), omega_scale=3.0), "class_r_me[0]"),
+    (dict(n_classes=2, class_r_pe=(2.0, 3.0, 0, 0), class_r_me=(4.0, 5.0, 0, 0), omega_scale=0.0), "omega_scale"),
+    (dict(n_classes=2, class_r_pe=(2.0, 3.0, 0, 0), class_r_me=(4.0, 5.0, 0, 0), omega_scale=3.0, guess=3),
+     "learned"),
 ])
 def test_setup_rejects_bad_parameters(over, needle):
     st, msg = _setup_status(**over)

@@ -1,0 +1,161 @@
+"""Per-pair subdomain classes from the orbitals' spreads (exx_pairs_spread),
+through the C ABI, against the oracle's per-class pipeline.
+
+The class of every pair equals the oracle's (integer, bit for bit); E_xx,
+the pair energies and D_xx on the classes the pairs run on match the oracle
+as for the two fixed classes (E and e_ij to 1e-8 relative, D to gamma 1e-7).
+"""
+import concurrent.futures as cf
+import sys
+import time
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import oracle as O  # noqa: E402
+from paper_1911_10630_amd import exx as X  # noqa: E402
+from paper_1911_10630_amd import synth as S  # noqa: E402
+
+RADII_C1 = [2.5, 3.5, 5.0, 7.56]
+RADII_C2 = [3.5, 4.5, 6.0, 7.56]
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def gamma(D_ref, D):
+    num = np.abs(D_ref - D).reshape(D.shape[0], -1).sum(axis=1)
+    return num / np.abs(D_ref).reshape(D.shape[0], -1).sum(axis=1)
+
+
+def _classes(radii):
+    return [(r, r + 1.9) for r in radii]
+
+
+@pytest.fixture(scope="module")
+def c1():
+    wl = S.c1_small()
+    phi = S.orbitals_np(wl)
+    return wl, phi, S.spreads(wl.orbitals)
+
+
+@pytest.mark.parametrize("kappa", [5.0, 6.0])
+def test_c1_classes_match_the_oracle(c1, kappa):
+    wl, phi, sp = c1
+    ref_cls, ref_cap = O.pair_classes(wl.orbitals.centers, sp, wl.cell, wl.n_grid, wl.r_pair, kappa, RADII_C1)
+    E, D, out = O.exx_classed(wl.n_grid, wl.cell, wl.r_pair, _classes(RADII_C1), ref_cls, wl.orbitals.centers, phi)
+    _say(f"[gpu] small config, 4 classes, omega_scale {kappa}: {np.bincount(ref_cls, minlength=4)}")
+    ctx = X.Exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, classes=_classes(RADII_C1), omega_scale=kappa)
+    n = ctx.pairs_spread(wl.orbitals.centers, sp)
+    assert n == len(ref_cls)
+    assert np.array_equal(ctx.pair_class(), ref_cls)
+    st = ctx.stats()
+    assert st["n_classes"] == 4 and st["class_capped"] == ref_cap
+    assert st["class_pairs"] == np.bincount(ref_cls, minlength=4).tolist()
+    Eg, Dg = ctx.step(torch.from_numpy(phi).cuda())
+    info = ctx.pair_info()
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-9
+    assert abs(Eg - E) <= 1e-8 * abs(E), (Eg, E)
+    rel = np.abs(info["e"] - out["e"]) / np.abs(out["e"])
+    assert rel.max() <= 1e-8, rel.max()
+    assert gamma(D, Dg.cpu().numpy()).max() <= 1e-7
+    ctx.close()
+
+
+def test_c1_classes_multigrid_in_waves(c1):
+    """The multigrid preconditioner on every class (its own level hierarchy
+    each), pairs in waves: the same energy as the plain CG on one wave."""
+    wl, phi, sp = c1
+    phit = torch.from_numpy(phi).cuda()
+    a = X.Exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, classes=_classes(RADII_C1), omega_scale=5.0)
+    a.pairs_spread(wl.orbitals.centers, sp)
+    E1, D1 = a.step(phit)
+    b = X.Exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, classes=_classes(RADII_C1), omega_scale=5.0,
+              precond="mg", wave_pairs=9)
+    b.pairs_spread(wl.orbitals.centers, sp)
+    E2, D2 = b.step(phit)
+    info = b.pair_info()
+    assert b.stats()["n_waves"] > 1
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert abs(E2 - E1) <= 1e-9 * abs(E1)
+    assert gamma(D1.cpu().numpy(), D2.cpu().numpy()).max() <= 1e-7
+    assert info["iters"].mean() < 0.5 * a.pair_info()["iters"].mean()
+
+
+def test_c1_previous_guess_when_classes_change(c1):
+    """Two steps with the previous-step guess; the second step's spreads move
+    some pairs to another class, whose PE sphere differs: those pairs start
+    from zero, the others from the first step, and every pair still meets
+    the oracle."""
+    wl, phi, sp = c1
+    phit = torch.from_numpy(phi).cuda()
+    ctx = X.Exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, classes=_classes(RADII_C1), omega_scale=5.0,
+                guess="previous")
+    ctx.pairs_spread(wl.orbitals.centers, sp)
+    cls1 = ctx.pair_class()
+    ctx.step(phit)
+    sp2 = sp * np.where(np.arange(len(sp)) % 3 == 0, 1.25, 1.0)
+    ctx.pairs_spread(wl.orbitals.centers, sp2)
+    cls2 = ctx.pair_class()
+    moved = int(np.sum(cls1 != cls2))
+    E2g, D2g = ctx.step(phit)
+    st = ctx.stats()
+    _say(f"[gpu] {moved} pairs changed class; {st['guess_pairs']} started from the previous step")
+    assert moved > 0 and st["guess_pairs"] == len(cls2) - moved
+    E2, D2, _ = O.exx_classed(wl.n_grid, wl.cell, wl.r_pair, _classes(RADII_C1), cls2, wl.orbitals.centers, phi)
+    assert abs(E2g - E2) <= 1e-8 * abs(E2)
+    assert gamma(D2, D2g.cpu().numpy()).max() <= 1e-7
+
+
+def test_c2_classes_full_size():
+    """The 64-water workload on four classes: every pair converged, sampled
+    pairs of each class against the oracle's subdomain of that class; E and
+    the solve time against the two fixed classes (R_PE = 7.56 bohr) printed."""
+    wl = S.c2_water64()
+    sp = S.spreads(wl.orbitals)
+    phi = S.orbitals_torch(wl, device="cuda:0")
+    ref = X.Exx.from_workload(wl)
+    ref.pairs(wl.orbitals.centers)
+    t0 = time.perf_counter()
+    E_ref, _ = ref.step(phi)
+    t_ref = time.perf_counter() - t0
+    ref.close()
+    ctx = X.Exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, classes=_classes(RADII_C2), omega_scale=6.0)
+    n = ctx.pairs_spread(wl.orbitals.centers, sp)
+    t0 = time.perf_counter()
+    E, D = ctx.step(phi)
+    t_cls = time.perf_counter() - t0
+    info = ctx.pair_info()
+    cls = ctx.pair_class()
+    st = ctx.stats()
+    _say(f"[gpu] 64-water, 4 classes (omega_scale 6): pairs per class {st['class_pairs']}, capped "
+         f"{st['class_capped']}; E {E:.12f} vs {E_ref:.12f} on the fixed classes (rel {abs(E - E_ref) / abs(E_ref):.2e}); "
+         f"step {t_cls:.2f} s vs {t_ref:.2f} s")
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    w = np.where(info["i"] == info["j"], 1.0, 2.0)
+    assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
+    pick = [int(np.nonzero(cls == k)[0][len(np.nonzero(cls == k)[0]) // 2]) for k in range(4) if np.any(cls == k)]
+    subs = [O.Subdomain(wl.n_grid, wl.cell, a, b) for a, b in _classes(RADII_C2)]
+    orbs = sorted({int(info["i"][p]) for p in pick} | {int(info["j"][p]) for p in pick})
+    phis = dict(zip(orbs, S.orbitals_np(wl, orbs)))
+
+    def solve(p):
+        i, j = int(info["i"][p]), int(info["j"][p])
+        return subs[int(cls[p])].solve_pair(phis[i], phis[j], info["origin"][p])
+
+    with cf.ThreadPoolExecutor(len(pick)) as ex:
+        refs = list(ex.map(solve, pick))
+    for p, r in zip(pick, refs):
+        sub = subs[int(cls[p])]
+        got = ctx.debug_pair(p, sub.n_pe, sub.n_shell)
+        assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
+        assert np.max(np.abs(got["x"] - r["x"])) <= 1e-7 * np.max(np.abs(r["x"])), p
+    ctx.close()

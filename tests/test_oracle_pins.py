@@ -134,6 +134,76 @@ def test_alg1_distance_order_balances_the_owners():
         assert (ratio <= bound) if by_distance else (ratio > bound), (by_distance, ratio)
 
 
+def test_lens_ball_closed_forms():
+    """Smallest ball around B(C_i, R_i) cap B(C_j, R_j): equal radii give the
+    circle's ball sqrt(R^2 - d^2/4) midway; a ball inside the other is that
+    ball; when the intersection holds a great circle of B_i, B_i itself;
+    disjoint balls give nothing; the minimum image applies."""
+    cell = [40.0, 40.0, 40.0]
+    f, rho = O.lens_enclosing_ball([1.0, 2.0, 3.0], [1.0, 2.0, 5.4], 2.0, 2.0, cell)
+    assert abs(f - 0.5) < 1e-15 and abs(rho - math.sqrt(4.0 - 1.2 ** 2)) < 1e-14
+    assert O.lens_enclosing_ball([0, 0, 0], [1.0, 0, 0], 3.0, 1.0, cell) == (1.0, 1.0)
+    assert O.lens_enclosing_ball([0, 0, 0], [2.5, 0, 0], 1.0, 3.0, cell) == (0.0, 1.0)
+    assert O.lens_enclosing_ball([0, 0, 0], [3.0, 0, 0], 1.0, 2.0, cell) is None
+    f, rho = O.lens_enclosing_ball([0.5, 0, 0], [39.5, 0, 0], 1.0, 1.0, cell)   # 1.0 apart across the boundary
+    assert abs(rho - math.sqrt(0.75)) < 1e-14
+
+
+@pytest.mark.parametrize("seed", [11, 12, 13, 14])
+def test_lens_ball_encloses_and_is_tight(seed):
+    """Brute force: every sampled point of the lens lies in the ball, and the
+    farthest one is within a sampling step of its surface."""
+    rng = np.random.default_rng(seed)
+    Ri, Rj = rng.uniform(0.8, 3.0, 2)
+    d = rng.uniform(abs(Ri - Rj) * 0.5, (Ri + Rj) * 0.95)
+    ci, cj = np.zeros(3), np.array([d, 0.0, 0.0])
+    f, rho = O.lens_enclosing_ball(ci, cj, Ri, Rj, [100.0] * 3)
+    step = 0.02
+    r = np.arange(-max(Ri, Rj), max(Ri, Rj) + d + step, step)
+    X, Y = np.meshgrid(r, np.arange(0.0, max(Ri, Rj) + step, step), indexing="ij")   # axial symmetry: (x, radial)
+    inside = (X ** 2 + Y ** 2 <= Ri ** 2) & ((X - d) ** 2 + Y ** 2 <= Rj ** 2)
+    dist = np.sqrt((X[inside] - f * d) ** 2 + Y[inside] ** 2)
+    assert dist.max() <= rho * (1 + 1e-12)
+    assert dist.max() >= rho - 2 * step
+
+
+def test_pair_domain_radius_from_the_origin():
+    """The radius about the origin g is |g - c| + rho; the self pair's domain
+    is the orbital's ball; an empty domain needs nothing."""
+    cell, n = [24.0, 24.0, 24.0], [48, 48, 48]                       # h = 0.5
+    ci, cj = np.array([5.0, 5.0, 5.0]), np.array([6.0, 5.0, 5.0])
+    g = O.pair_origin(ci, cj, cell, n)                               # 5.5 -> grid point 11 (x), 10, 10
+    r = O.pair_domain_radius(ci, cj, 2.0, 2.0, g, cell, n, False)
+    assert abs(r - math.sqrt(4.0 - 0.25)) < 1e-14                    # g sits on the lens centre
+    rs = O.pair_domain_radius(ci, ci, 1.5, 1.5, O.pair_origin(ci, ci, cell, n), cell, n, True)
+    assert abs(rs - 1.5) < 1e-14                                     # C_i on a grid point
+    assert O.pair_domain_radius(ci, np.array([9.0, 5.0, 5.0]), 1.0, 1.0, g, cell, n, False) == 0.0
+
+
+def test_pair_classes_cover_the_domain():
+    """Each pair's class is the smallest whose radius covers its domain, or
+    the largest (counted) when none does."""
+    wl = S.c1_small()
+    rng = np.random.default_rng(3)
+    spreads = rng.uniform(0.6, 1.4, wl.orbitals.n)
+    radii = [2.0, 3.0, 4.0]
+    cls, capped = O.pair_classes(wl.orbitals.centers, spreads, wl.cell, wl.n_grid, wl.r_pair, 3.0, radii)
+    pi, pj = O.pair_list(wl.orbitals.centers, wl.cell, wl.r_pair)
+    C = wl.orbitals.centers
+    n_cap = 0
+    for p, (i, j) in enumerate(zip(pi, pj)):
+        g = O.pair_origin(C[i], C[j], wl.cell, wl.n_grid)
+        r = O.pair_domain_radius(C[i], C[j], 3.0 * spreads[i], 3.0 * spreads[j], g, wl.cell, wl.n_grid, i == j)
+        k = cls[p]
+        if r > radii[-1]:
+            assert k == 2
+            n_cap += 1
+        else:
+            assert radii[k] >= r and (k == 0 or radii[k - 1] < r)
+    assert n_cap == capped
+    assert len(set(cls.tolist())) == 3                               # all classes in use here
+
+
 def test_pair_origin_wraps_and_rounds():
     L, N = 10.0, 20                                    # h = 0.5
     # midpoint 0.1 -> grid 0
