@@ -182,6 +182,11 @@ def main():
     ap.add_argument("--guess", default="zero", choices=["zero", "previous", "extrap", "learned"])
     ap.add_argument("--precond", default="none", choices=["none", "mg"],
                     help="FP64 CG preconditioner: none (the paper's CG) or a multigrid V-cycle")
+    ap.add_argument("--omega-scale", type=float, default=0.0,
+                    help="per-pair subdomain classes: Omega_i radius = this x the orbital spread (0: the two "
+                         "fixed classes)")
+    ap.add_argument("--class-radii", default="3.5,4.5,6.0,7.56",
+                    help="per-pair classes: PE radii (bohr), ascending; ME radius = PE + 1.9 bohr")
     ap.add_argument("--graph", action="store_true",
                     help="launch each solve as a captured HIP graph (the CG kernel is then timed with the whole solve)")
     ap.add_argument("--coarsen", type=int, default=2, help="learned guess: grid points per coarse cell edge")
@@ -220,15 +225,23 @@ def main():
         return md_run(args, wl)
     dev = torch.device("cuda:0")
     guess = "learned" if args.guess == "learned" else "zero"
+    classed = args.omega_scale > 0.0
+    ckw = {}
+    if classed:
+        radii = [float(v) for v in args.class_radii.split(",")]
+        ckw = dict(classes=[(r, r + 1.9) for r in radii], omega_scale=args.omega_scale)
     ctx = X.Exx.from_workload(wl, block_threads=args.block, cg_cols=args.cols, inner_rtol=args.inner_rtol,
-                              guess=guess, graph=args.graph, precond=args.precond)
+                              guess=guess, graph=args.graph, precond=args.precond, **ckw)
     learned = train_model(args, wl, ctx) if guess == "learned" else None
     # orbitals and D first: the pair waves are sized from the memory left
     shape = (wl.orbitals.n,) + tuple(reversed(wl.box or wl.n_grid))
     fdt = torch.float64 if wl.orbital_dtype == "f64" else torch.float32
     phi = torch.empty(shape, dtype=fdt, device=dev)
     dxx = torch.empty_like(phi)
-    n_pairs = ctx.pairs(wl.orbitals.centers)
+    if classed:
+        n_pairs = ctx.pairs_spread(wl.orbitals.centers, S.spreads(wl.orbitals))
+    else:
+        n_pairs = ctx.pairs(wl.orbitals.centers)
     origins = ctx.box_origins() if wl.box else None
     log(f"[bench] workload {wl.name}: generating {wl.orbitals.n} orbitals on {dev}"
         + (f" on {wl.box} boxes" if wl.box else ""))
@@ -259,7 +272,8 @@ def main():
     ptr = PROFILE_TRAFFIC[args.precond]
     if os.path.exists(ptr):
         tr = json.load(open(ptr))
-        if tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name and guess == "zero":
+        if (tr.get("kernel_hash") == kernel_hash() and tr.get("workload") == wl.name and guess == "zero"
+                and not classed):
             for v in tr.get("variants", []):
                 if v["variant"] == [st["solve_block"], st["cg_cols"]]:
                     # measured HBM bytes of the same launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
@@ -293,12 +307,16 @@ def main():
                             kernel_hash=kernel_hash()))
     if args.precond != "none":
         line["config"]["precond"] = args.precond
+    if classed:
+        line["config"]["pair_classes"] = dict(omega_scale=args.omega_scale,
+                                              r_pe_bohr=[c[0] for c in ckw["classes"]],
+                                              pairs=st["class_pairs"][:st["n_classes"]], capped=st["class_capped"])
     if learned:
         line["config"]["guess"] = "learned"
         learned["guess_ms"] = round(st["guess_ms"], 2)
         line["learned"] = learned
 
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not classed:       # the oracle leg runs the two fixed classes
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
         n_sample = args.cpu_sample or 2 * threads
         n_sample = min(n_sample, n_pairs)
