@@ -989,6 +989,13 @@ exx_status build_pair_list(exx_ctx *c, int n_orb, const double *C)
         a.nc[k] = std::max(1, (int)std::floor(L[k] / (c->prm.r_pair * (1.0 + 1e-9))));
         a.nc[k] = std::min(a.nc[k], 1024);
     }
+    // at most about 8 cells per orbital (wider cells only add candidates)
+    while ((long long)a.nc[0] * a.nc[1] * a.nc[2] > 8LL * n_orb + 64) {
+        int k = 0;
+        for (int d = 1; d < 3; ++d)
+            if (a.nc[d] > a.nc[k]) k = d;
+        a.nc[k] = std::max(1, a.nc[k] / 2);
+    }
     a.r2 = c->prm.r_pair * c->prm.r_pair;
     const int ncell = a.nc[0] * a.nc[1] * a.nc[2];
     std::vector<int> cell_of((size_t)n_orb), start((size_t)ncell + 1, 0), items((size_t)n_orb);

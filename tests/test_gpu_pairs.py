@@ -118,3 +118,17 @@ def test_cells_too_small_for_three_bins(ratio):
     ctx = _tiny_ctx(cell, r_pair, (32, 32, 32))
     _check(ctx, C, cell, r_pair, (32, 32, 32))
     ctx.close()
+
+
+def test_sparse_centres_in_a_large_cell():
+    """Few centres in a cell of many R_pair: the cell list is coarsened to a
+    few cells per centre, the pairs stay exact."""
+    rng = np.random.default_rng(99)
+    cell = (400.0, 380.0, 420.0)
+    C = rng.uniform(0.0, 1.0, size=(40, 3)) * np.array(cell)
+    C[1] = C[0] + np.array([1.5, -0.5, 0.25])                 # a few close pairs
+    C[2] = C[0] + np.array([-2.0, 1.0, 0.0])
+    ctx = _tiny_ctx(cell, 3.0, (64, 64, 64))
+    n, *_ = _check(ctx, C, cell, 3.0, (64, 64, 64))
+    assert n >= 40 + 2                                  # 0-1 and 0-2; 1-2 is 3.8 bohr apart
+    ctx.close()
