@@ -159,3 +159,71 @@ def test_c2_classes_full_size():
         assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
         assert np.max(np.abs(got["x"] - r["x"])) <= 1e-7 * np.max(np.abs(r["x"])), p
     ctx.close()
+
+
+def test_c1_classes_fp32_refinement_and_graph(c1):
+    """Per-pair classes under FP32 CG with FP64 reliable updates, and under
+    HIP-graph replay (bitwise equal to the eager solve)."""
+    wl, phi, sp = c1
+    phit = torch.from_numpy(phi).cuda()
+    ref_cls, _ = O.pair_classes(wl.orbitals.centers, sp, wl.cell, wl.n_grid, wl.r_pair, 5.0, RADII_C1)
+    E, D, _ = O.exx_classed(wl.n_grid, wl.cell, wl.r_pair, _classes(RADII_C1), ref_cls, wl.orbitals.centers, phi)
+    f = X.Exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, classes=_classes(RADII_C1), omega_scale=5.0,
+              precision="fp32_refine")
+    f.pairs_spread(wl.orbitals.centers, sp)
+    Ef, Df = f.step(phit)
+    info = f.pair_info()
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-9
+    assert abs(Ef - E) <= 1e-8 * abs(E)
+    assert gamma(D, Df.cpu().numpy()).max() <= 1e-7
+    eager = X.Exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, classes=_classes(RADII_C1), omega_scale=5.0,
+                  autotune=False)
+    eager.pairs_spread(wl.orbitals.centers, sp)
+    E0, D0 = eager.step(phit)
+    g = X.Exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, classes=_classes(RADII_C1), omega_scale=5.0,
+              autotune=False, graph=True)
+    g.pairs_spread(wl.orbitals.centers, sp)
+    for _ in range(3):
+        Eg, Dg = g.step(phit)
+        torch.cuda.synchronize()
+        assert Eg == E0 and torch.equal(Dg, D0)
+    assert g.stats()["graph_launches"] >= 2
+
+
+def test_c5_classes_boxes_and_waves():
+    """The 512-water workload (FP32 orbitals on 160^3 boxes, pairs in waves,
+    FP32 CG with FP64 reliable updates) on per-pair classes: every ME sphere
+    fits the boxes, every pair converges, and sampled pair energies of each
+    class match the oracle."""
+    wl = S.c5_water512()
+    sp = S.spreads(wl.orbitals)
+    ctx = X.Exx.from_workload(wl, classes=_classes(RADII_C2), omega_scale=5.0, wave_pairs=30000)
+    phi = torch.empty((2048,) + tuple(reversed(wl.box)), dtype=torch.float32, device="cuda:0")
+    D = torch.empty_like(phi)
+    n = ctx.pairs_spread(wl.orbitals.centers, sp)
+    org = ctx.box_origins()
+    S.orbitals_torch(wl, device="cuda:0", origins=org, out=phi)
+    E, D = ctx.step(phi, D)
+    info = ctx.pair_info()
+    cls = ctx.pair_class()
+    st = ctx.stats()
+    _say(f"[gpu] 512-water on classes: {n} pairs in {st['n_waves']} waves, per class {st['class_pairs']}")
+    assert st["n_waves"] > 1
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-9
+    w = np.where(info["i"] == info["j"], 1.0, 2.0)
+    assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
+    pick = [int(np.nonzero(cls == k)[0][-1]) for k in range(4) if np.any(cls == k)]
+    subs = [O.Subdomain(wl.n_grid, wl.cell, a, b) for a, b in _classes(RADII_C2)]
+    orbs = sorted({int(info["i"][p]) for p in pick} | {int(info["j"][p]) for p in pick})
+    vals = S.orbitals_np(wl, orbs, origins=org).astype(np.float32).astype(np.float64)
+    phis = dict(zip(orbs, S.embed_boxes(vals, [org[k] for k in orbs], wl.n_grid)))
+
+    def solve(p):
+        i, j = int(info["i"][p]), int(info["j"][p])
+        return subs[int(cls[p])].solve_pair(phis[i], phis[j], info["origin"][p])
+
+    with cf.ThreadPoolExecutor(len(pick)) as ex:
+        refs = list(ex.map(solve, pick))
+    for p, r in zip(pick, refs):
+        assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
+    ctx.close()
