@@ -424,3 +424,18 @@ def test_energy_potential_consistency(c1_result):
     _, D13, _ = O.exx(wl.n_grid, wl.cell, wl.r_pair, wl.r_pe, wl.r_me, wl.orbitals.centers, phi, tol=1e-13)
     an = -4 * h3 * float(np.sum(eta * D13[k]))
     assert abs(fd - an) < 1e-5 * abs(an), (fd, an)
+
+
+def test_per_class_pipeline_reduces_to_the_two_fixed_classes(c1_result):
+    """The per-pair-class accumulation (Python, one Subdomain per class)
+    given the fixed classes (self pairs on class 0, the others on class 1)
+    reproduces the C pipeline's E and D exactly: same pair solves, same
+    pair order of the D sums."""
+    wl, phi, E, D, out = c1_result
+    pi, pj = O.pair_list(wl.orbitals.centers, wl.cell, wl.r_pair)
+    cls = (pi != pj).astype(np.int32)
+    classes = [(wl.r_pe[0], wl.r_me[0]), (wl.r_pe[1], wl.r_me[1])]
+    E2, D2, o2 = O.exx_classed(wl.n_grid, wl.cell, wl.r_pair, classes, cls, wl.orbitals.centers, phi)
+    assert E2 == E
+    assert np.array_equal(D2, D)
+    assert np.array_equal(o2["e"], out["e"])
