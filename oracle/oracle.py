@@ -151,22 +151,33 @@ def unique_pair_owners(centers, cell, r_pair, by_distance=True):
         rows[i].append((d2, j))
         if j != i:
             rows[j].append((d2, i))
-    L = [[j for _, j in (sorted(r) if by_distance else sorted(r, key=lambda t: t[1]))] for r in rows]
+    L0 = [[j for _, j in (sorted(r) if by_distance else sorted(r, key=lambda t: t[1]))] for r in rows]
+    Lu, sweeps = refine_pair_rows(L0)
+    member = [set(r) for r in Lu]
+    owner = np.array([i if j in member[i] else j for i, j in zip(pi.tolist(), pj.tolist())], np.int32)
+    return owner, sweeps
+
+
+def refine_pair_rows(L0):
+    """Alg. 1 on explicit rows: L0[i] lists orbital i's overlapping orbitals
+    (i among them) in the order the sweeps scan them.  Returns (Lu, sweeps):
+    the refined rows, in their original order with the removed entries
+    dropped, and the number of sweeps including the last, empty one."""
+    L = [list(r) for r in L0]
     member = [set(r) for r in L]
     sweeps = 0
     removed = True
     while removed:
         removed = False
         sweeps += 1
-        for i in range(n):
+        for i in range(len(L)):
             for j in L[i]:
                 if j != i and i in member[j]:
                     L[j].remove(i)
                     member[j].discard(i)
                     removed = True
                     break
-    owner = np.array([i if j in member[i] else j for i, j in zip(pi.tolist(), pj.tolist())], np.int32)
-    return owner, sweeps
+    return L, sweeps
 
 
 def pair_origin(ci, cj, cell, n):

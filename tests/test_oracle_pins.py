@@ -97,6 +97,26 @@ def test_alg1_hand_worked_examples():
         assert sweeps == case["sweeps"], case["name"]
 
 
+def test_alg1_paper_worked_example():
+    """The worked example of the paper's pair-list figure (four orbitals of one
+    water molecule, tests/golden/alg1_paper_example.json): Alg. 1 on the
+    printed rows gives the printed unique rows and loads, for every order of
+    the entries the caption leaves open."""
+    import itertools, json, os
+    g = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "alg1_paper_example.json")))
+    rows = g["L0"]
+    n = len(rows)
+    for fills in itertools.product(*[itertools.permutations(sorted(set(range(1, n + 1)) - {v for v in r if v}))
+                                     for r in rows]):
+        L0 = []
+        for r, f in zip(rows, fills):
+            known = [v for v in r if v is not None]
+            L0.append([v - 1 for v in known + list(f)])
+        Lu, sweeps = O.refine_pair_rows(L0)
+        assert [[v + 1 for v in r] for r in Lu] == g["Lu"], fills
+        assert [len(r) for r in Lu] == g["loads"]
+
+
 @pytest.mark.parametrize("seed", [1, 2, 3])
 def test_alg1_assigns_every_pair_once(seed):
     """Whatever the order of removals, Lu holds each unique pair exactly once
