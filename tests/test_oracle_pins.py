@@ -459,3 +459,39 @@ def test_per_class_pipeline_reduces_to_the_two_fixed_classes(c1_result):
     assert E2 == E
     assert np.array_equal(D2, D)
     assert np.array_equal(o2["e"], out["e"])
+
+
+def test_orthogonal_mixing_of_the_orbitals():
+    """E_xx = -sum over ordered pairs of (rho_ij | rho_ij) is invariant under
+    an orthogonal mixing phi -> U phi, and D transforms as D -> U D, when
+    every pair is solved by the same linear operator: all centres at one
+    point (one pair origin) and equal self / non-self radii.  Exact up to the
+    CG tolerance."""
+    n, cell = (32, 32, 32), (12.0, 12.0, 12.0)
+    rng = np.random.default_rng(5)
+    C = np.tile([6.0, 6.0, 6.0], (4, 1))
+    u = rng.normal(size=(4, 3))
+    u /= np.linalg.norm(u, axis=1, keepdims=True)
+    wl = S.custom(n, cell, C, kind=[0, 1, 0, 1], alpha=rng.uniform(1.2, 2.0, 4), u=u,
+                  a=rng.uniform(-0.2, 0.2, (4, 3)), r_pair=1.0, r_pe=4.0, r_me=5.5)
+    phi = S.orbitals_np(wl)
+    E, D, _ = O.exx(n, cell, wl.r_pair, wl.r_pe, wl.r_me, C, phi)
+    U, _ = np.linalg.qr(rng.normal(size=(4, 4)))
+    E2, D2, _ = O.exx(n, cell, wl.r_pair, wl.r_pe, wl.r_me, C, np.einsum("ik,k...->i...", U, phi))
+    assert abs(E2 - E) <= 1e-10 * abs(E)
+    assert np.abs(D2 - np.einsum("ik,k...->i...", U, D)).max() <= 1e-9 * np.abs(D).max()
+
+
+def test_energy_converges_with_the_subdomain_radius():
+    """The paper's convergence test (Sec. IV A): the self-pair energy of one
+    diffuse s orbital approaches its large-domain value monotonically as
+    R_PE grows (R_ME = R_PE + 1.5 bohr) until the solver's tolerance."""
+    n, cell = (32, 32, 32), (12.0, 12.0, 12.0)
+    C = np.array([[6.0, 6.0, 6.0]])
+    wl = S.custom(n, cell, C, alpha=[0.9], r_pair=1.0)
+    phi = S.orbitals_np(wl)
+    radii = [2.0, 2.5, 3.0, 3.5, 4.5]
+    E = [O.exx(n, cell, 1.0, r, r + 1.5, C, phi, want_D=False)[0] for r in radii]
+    err = [abs(e - E[-1]) for e in E[:-1]]
+    assert all(a > b for a, b in zip(err, err[1:])), err
+    assert err[0] > 1e-3 * abs(E[-1]) and err[-1] < 1e-7 * abs(E[-1])
