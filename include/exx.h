@@ -189,18 +189,19 @@ exx_status exx_pairs(exx_ctx *ctx, int32_t n_orb, const double *centers, int64_t
  * R_i = omega_scale * spread_i about C_i; pair (i, j) the domain
  * Omega_ij = Omega_i cap Omega_j (Omega_i for the self pair).  The pair's PE
  * sphere about its origin g must hold Omega_ij; it is taken to need the
- * radius |g - c| + rho, (c, rho) the smallest ball that encloses Omega_ij:
- * with d = |C_j - C_i| (minimum image) and x = (d^2 + R_i^2 - R_j^2) / (2d),
- *   d >= R_i + R_j:            empty, radius 0 (the smallest class)
- *   x <= 0 (or d = 0, R_i <= R_j): Omega_i lies in Omega_j up to its cap,
- *                              c = C_i, rho = R_i
- *   x >= d:                    c = C_j, rho = R_j
- *   else:                      c = C_i + x (C_j - C_i) / d,
- *                              rho = sqrt(R_i^2 - x^2)
+ * radius |g - c| + rho, (c, rho) the smallest ball that encloses Omega_ij.
+ * With d = |C_j - C_i| (minimum image) and x = (d^2 + R_i^2 - R_j^2) / (2d)
+ * the signed distance from C_i to the plane of the spheres' intersection:
+ *   d >= R_i + R_j:  empty; radius 0 (the smallest class)
+ *   d = 0:           c = C_i, rho = min(R_i, R_j)
+ *   x <= 0:          Omega_ij holds a great circle of Omega_i: c = C_i, rho = R_i
+ *   x >= d:          the same for Omega_j: c = C_j, rho = R_j
+ *   otherwise:       c = C_i + (x / d) (C_j - C_i), rho = sqrt(R_i^2 - x^2)
  * The pair goes to the smallest class whose r_pe is at least that radius,
- * or to the largest class (counted in exx_stats class_capped).  Everything
- * else is as exx_pairs.  EXX_EINVAL if n_classes < 2, a spread is negative
- * or not finite, or omega_scale <= 0. */
+ * or to the largest class (counted in exx_stats class_capped).  spreads is
+ * read during the call.  Everything else is as exx_pairs (same errors).
+ * EXX_EINVAL also if n_classes < 2 or a spread is negative or not finite
+ * (omega_scale was checked by exx_setup). */
 exx_status exx_pairs_spread(exx_ctx *ctx, int32_t n_orb, const double *centers, const double *spreads,
                             int64_t *n_pairs);
 
