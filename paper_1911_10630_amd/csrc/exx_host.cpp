@@ -36,10 +36,12 @@ struct HostClass {
     std::vector<int> pe_xyz, sh_xyz, cols;
     std::vector<int> colz, pe_off;
     std::vector<int> bands, bands32;   // [n][12] for the selected CG variant
+    std::vector<int> bnd_q, bnd_ptr, bnd_ent;   // PE-to-shell stencil coupling (CSR)
     int plane_rows = 0, plane_rows32 = 0;
     int4 *d_pe_rows = nullptr, *d_me_rows = nullptr;
     int *d_pe_xyz = nullptr, *d_sh_xyz = nullptr, *d_cols = nullptr, *d_bands = nullptr;
     int *d_colz = nullptr, *d_pe_off = nullptr, *d_bands32 = nullptr;
+    int *d_bnd_q = nullptr, *d_bnd_ptr = nullptr, *d_bnd_ent = nullptr;
     // multigrid coarse levels: dims and masks (host), device masks, offsets
     int mg_levels = 0;
     int mg_n[MG_MAX][3] = {};
@@ -354,6 +356,49 @@ exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
     k.pe_off.assign((size_t)pny * pnz, 0);
     for (size_t t = 0; t < k.pe_rows.size(); ++t)
         if (k.pe_rows[t].y <= k.pe_rows[t].z) k.pe_off[t] = k.pe_rows[t].x - k.pe_rows[t].y;
+    // Stencil coupling of PE points to the shell, the boundary-charge term of
+    // Eq. pe_mat_red: for each PE point with a stencil neighbour outside PE,
+    // its neighbours on the shell as (shell index << 4) | (axis * 3 + s - 1),
+    // in the order the right-hand side adds them (s = 1..3, then -s before
+    // +s, then x, y, z).  Interior points have none: only the layer within
+    // three points of the surface is listed (a sixth of PE at R_PE = 41 h).
+    {
+        auto pe_at = [&](int x, int y, int z) -> int {
+            const int zz = z - k.pzlo, yy = y - k.pylo;
+            if (zz < 0 || zz >= pnz || yy < 0 || yy >= pny) return -1;
+            const int4 r = k.pe_rows[(size_t)zz * pny + yy];
+            return (x < r.y || x > r.z) ? -1 : r.x + x - r.y;
+        };
+        auto sh_at = [&](int x, int y, int z) -> int {
+            const size_t row = (size_t)(z - k.mzlo) * mny + (y - k.mylo);
+            const int4 a = k.me_rows[2 * row], b = k.me_rows[2 * row + 1];
+            return a.w + (x < a.y ? x - b.x : (a.y - b.x) + (x - a.z - 1));
+        };
+        k.bnd_q.clear();
+        k.bnd_ent.clear();
+        k.bnd_ptr.assign(1, 0);
+        for (int q = 0; q < k.n_pe; ++q) {
+            int x, y, z;
+            unpack_xyz(k.pe_xyz[q], x, y, z);
+            const size_t before = k.bnd_ent.size();
+            for (int s = 1; s <= FD_N; ++s)
+                for (int sg = -1; sg <= 1; sg += 2) {
+                    const int d = sg * s;
+                    const int nb[3][3] = {{x + d, y, z}, {x, y + d, z}, {x, y, z + d}};
+                    for (int ax = 0; ax < 3; ++ax)
+                        if (pe_at(nb[ax][0], nb[ax][1], nb[ax][2]) < 0) {
+                            const int sh = sh_at(nb[ax][0], nb[ax][1], nb[ax][2]);
+                            if (sh < 0 || sh >= k.n_sh || sh >= (1 << 27))
+                                return fail(c, EXX_EINVAL, "shell index %d of PE point %d out of range", sh, q);
+                            k.bnd_ent.push_back((sh << 4) | (ax * 3 + s - 1));
+                        }
+                }
+            if (k.bnd_ent.size() != before) {
+                k.bnd_q.push_back(q);
+                k.bnd_ptr.push_back((int)k.bnd_ent.size());
+            }
+        }
+    }
     // upload
     auto up = [&](auto **dst, const auto &v) -> exx_status {
         using T = std::remove_reference_t<decltype(v[0])>;
@@ -370,6 +415,9 @@ exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
     if ((st = up(&k.d_cols, k.cols)) != EXX_OK) return st;
     if ((st = up(&k.d_colz, k.colz)) != EXX_OK) return st;
     if ((st = up(&k.d_pe_off, k.pe_off)) != EXX_OK) return st;
+    if ((st = up(&k.d_bnd_q, k.bnd_q)) != EXX_OK) return st;
+    if ((st = up(&k.d_bnd_ptr, k.bnd_ptr)) != EXX_OK) return st;
+    if ((st = up(&k.d_bnd_ent, k.bnd_ent)) != EXX_OK) return st;
     return EXX_OK;
 }
 
@@ -474,6 +522,10 @@ ClassDev class_dev(const HostClass &k)
     d.n_sh = k.n_sh;
     d.colz = k.d_colz;
     d.pe_off = k.d_pe_off;
+    d.bnd_q = k.d_bnd_q;
+    d.bnd_ptr = k.d_bnd_ptr;
+    d.bnd_ent = k.d_bnd_ent;
+    d.n_bnd = (int)k.bnd_q.size();
     d.bands = k.d_bands;
     d.n_bands = (int)k.bands.size() / 12;
     d.tbl_ints = (d.pny * d.pnz + 3) / 4 * 4;
@@ -593,10 +645,12 @@ bool make_bands(const HostClass &k, int cols_per_thread, int halo_per_thread, in
 void free_class(HostClass &k)
 {
     for (void *p : {(void *)k.d_pe_rows, (void *)k.d_me_rows, (void *)k.d_pe_xyz, (void *)k.d_sh_xyz,
-                    (void *)k.d_cols, (void *)k.d_bands, (void *)k.d_colz, (void *)k.d_pe_off, (void *)k.d_bands32})
+                    (void *)k.d_cols, (void *)k.d_bands, (void *)k.d_colz, (void *)k.d_pe_off, (void *)k.d_bands32,
+                    (void *)k.d_bnd_q, (void *)k.d_bnd_ptr, (void *)k.d_bnd_ent})
         if (p) (void)hipFree(p);
     k.d_pe_rows = k.d_me_rows = nullptr;
     k.d_pe_xyz = k.d_sh_xyz = k.d_cols = k.d_bands = k.d_colz = k.d_pe_off = k.d_bands32 = nullptr;
+    k.d_bnd_q = k.d_bnd_ptr = k.d_bnd_ent = nullptr;
     for (auto &m : k.d_mg_mask)
         if (m) { (void)hipFree(m); m = nullptr; }
 }

@@ -42,6 +42,10 @@ struct ClassDev {
     int n_cols;
     const int *colz;       // [n_cols] z range of each column: (zlo + 512) | (zhi + 512) << 16
     const int *pe_off;     // [pnz][pny] base(z, y) - xlo(z, y): packed index of (x, y, z) = pe_off + x
+    const int *bnd_q;      // [n_bnd] PE points with a stencil neighbour on the shell, ascending
+    const int *bnd_ptr;    // [n_bnd + 1] their runs in bnd_ent
+    const int *bnd_ent;    // shell neighbours: (shell index << 4) | (axis * 3 + s - 1)
+    int n_bnd;
     const int *bands;      // [n_bands][12] z-march bands: own cols [c0,c1), halo cols
                            // [h0,h1) u [h2,h3), planes [zlo, zhi], first own row ya
     int n_bands;

@@ -37,30 +37,31 @@ __device__ __forceinline__ int wrap_n(int v, int n)
 // Condon-Shortley phase.  R_lm = norm_lm U_lm are orthonormal solid
 // harmonics, r^l S_lm(rhat); sum_m Q_lm R_lm equals the complex-form
 // sum of Eqs. me / mepole by the addition theorem.
-__device__ __forceinline__ void solid_u(double x, double y, double z, double *U)
+// Each value is handed to use(l, index, U) as soon as it is formed (m-major
+// order), so a caller that folds it into a sum never holds all 49.
+template <class Use>
+__device__ __forceinline__ void solid_u(double x, double y, double z, Use &&use)
 {
     const double r2 = x * x + y * y + z * z;
-    double A[LMAX + 1], B[LMAX + 1];
-    A[0] = 1.0;
-    B[0] = 0.0;
-#pragma unroll
-    for (int m = 1; m <= LMAX; ++m) {
-        A[m] = x * A[m - 1] - y * B[m - 1];
-        B[m] = x * B[m - 1] + y * A[m - 1];
-    }
+    double A = 1.0, B = 0.0;
     constexpr double dfact[LMAX + 1] = {1.0, 1.0, 3.0, 15.0, 105.0, 945.0, 10395.0};
 #pragma unroll
     for (int m = 0; m <= LMAX; ++m) {
+        if (m > 0) {
+            const double An = x * A - y * B;
+            B = x * B + y * A;
+            A = An;
+        }
         double p2 = 0.0, p1 = dfact[m];
-        U[m * m + 2 * m] = p1 * A[m];
-        if (m > 0) U[m * m] = p1 * B[m];
+        use(m, m * m + 2 * m, p1 * A);
+        if (m > 0) use(m, m * m, p1 * B);
 #pragma unroll
         for (int l = m + 1; l <= LMAX; ++l) {
             const double pl = ((2 * l - 1) * z * p1 - (l + m - 1) * r2 * p2) * (1.0 / (l - m));
             p2 = p1;
             p1 = pl;
-            U[l * l + l + m] = pl * A[m];
-            if (m > 0) U[l * l + l - m] = pl * B[m];
+            use(l, l * l + l + m, pl * A);
+            if (m > 0) use(l, l * l + l - m, pl * B);
         }
     }
 }
@@ -133,11 +134,13 @@ constexpr int PREP_BLOCK = 256;
 // Gather of phi_i, phi_j on PE and the pair density rho_ij (Step III, Eq. l2g),
 // moments Q_lm (Eq. mepole), far-field potential on the shell (Eq. me) and the
 // boundary-charge right-hand side b = 4 pi rho + sum_shell w v / h^2
-// (Eq. pe_mat_red).  b is first used to hold rho (same thread, same index).
+// (Eq. pe_mat_red).  b first holds 4 pi rho; the shell term is then added
+// to the PE points of the class's coupling list only, in stencil order.
 __global__ __launch_bounds__(PREP_BLOCK) void k_prep(SolveArgs a)
 {
     __shared__ double red[PREP_BLOCK / 64][NLM];
     __shared__ double qs[NLM];
+    __shared__ double wsh[3 * FD_N];   // stencil weight of axis a, distance s at a * 3 + s - 1
     const int tid = threadIdx.x;
     const int pair = a.wave_begin + blockIdx.x;
     const int4 pg = a.pair_gc[pair];
@@ -149,8 +152,7 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep(SolveArgs a)
     const double hx = a.h[0], hy = a.h[1], hz = a.h[2];
     const long long oi = (long long)ij.x * a.box.vol, oj = (long long)ij.y * a.box.vol;
     const int4 org_i = a.box.org[ij.x], org_j = a.box.org[ij.y];
-    double w[3][4];
-    fd_weights(a, w);
+    if (tid < 3 * FD_N) wsh[tid] = a.wfd[tid % FD_N + 1] / (a.h[tid / FD_N] * a.h[tid / FD_N]);
 
     double acc[NLM];
 #pragma unroll
@@ -159,12 +161,9 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep(SolveArgs a)
         int x, y, z;
         unpack_xyz(g.pe_xyz[q], x, y, z);
         const double rv = pair_rho(a, pg, oi, oj, org_i, org_j, x, y, z);
-        bv[q] = rv;
+        bv[q] = 4.0 * M_PI * rv;
         if (keep) keep[q] = rv;
-        double U[NLM];
-        solid_u(x * hx, y * hy, z * hz, U);
-#pragma unroll
-        for (int k = 0; k < NLM; ++k) acc[k] += rv * U[k];
+        solid_u(x * hx, y * hy, z * hz, [&](int, int k, double u) { acc[k] += rv * u; });
     }
     {
         const int lane = tid & 63, wv = tid >> 6;
@@ -193,35 +192,28 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep(SolveArgs a)
         unpack_xyz(g.sh_xyz[s], x, y, z);
         const double X = x * hx, Y = y * hy, Z = z * hz;
         const double r2 = X * X + Y * Y + Z * Z;
-        double U[NLM];
-        solid_u(X, Y, Z, U);
+        double t[LMAX + 1];
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) t[l] = 0.0;
+        solid_u(X, Y, Z, [&](int l, int k, double u) { t[l] += qs[k] * u; });
         const double inv_r2 = 1.0 / r2;
         double f = 1.0 / sqrt(r2);
         double v = 0.0;
 #pragma unroll
         for (int l = 0; l <= LMAX; ++l) {
-            double t = 0.0;
-#pragma unroll
-            for (int m = -l; m <= l; ++m) t += qs[l * l + l + m] * U[l * l + l + m];
-            v += f * t;
+            v += f * t[l];
             f *= inv_r2;
         }
         v_sh[s] = v;
     }
     __syncthreads();
-    for (int q = tid; q < g.n_pe; q += PREP_BLOCK) {
-        int x, y, z;
-        unpack_xyz(g.pe_xyz[q], x, y, z);
-        double bq = 4.0 * M_PI * bv[q];
-#pragma unroll
-        for (int s = 1; s <= FD_N; ++s) {
-#pragma unroll
-            for (int sg = -1; sg <= 1; sg += 2) {
-                const int d = sg * s;
-                if (pe_index(g, x + d, y, z) < 0) bq += w[0][s] * v_sh[sh_index(g, x + d, y, z)];
-                if (pe_index(g, x, y + d, z) < 0) bq += w[1][s] * v_sh[sh_index(g, x, y + d, z)];
-                if (pe_index(g, x, y, z + d) < 0) bq += w[2][s] * v_sh[sh_index(g, x, y, z + d)];
-            }
+    // boundary charge: only the PE points next to the shell receive any
+    for (int t = tid; t < g.n_bnd; t += PREP_BLOCK) {
+        const int q = g.bnd_q[t];
+        double bq = bv[q];
+        for (int e = g.bnd_ptr[t]; e < g.bnd_ptr[t + 1]; ++e) {
+            const int ent = g.bnd_ent[e];
+            bq += wsh[ent & 15] * v_sh[ent >> 4];
         }
         bv[q] = bq;
     }
