@@ -174,7 +174,7 @@ def main():
     ap.add_argument("--block", type=int, default=0)
     ap.add_argument("--cols", type=int, default=0, help="CG columns per thread (-1: flat kernel)")
     ap.add_argument("--inner-rtol", type=float, default=1e-5, help="FP32 inner CG tolerance (refinement)")
-    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 2 per thread)")
+    ap.add_argument("--cpu-sample", type=int, default=0, help="oracle sample size (0: 6 per thread, about 15 s of CPU work)")
     ap.add_argument("--cpu-threads", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--md-steps", type=int, default=0,
@@ -318,7 +318,7 @@ def main():
 
     if not args.no_cpu_baseline and not classed:       # the oracle leg runs the two fixed classes
         threads = args.cpu_threads or min(16, os.cpu_count() or 1)
-        n_sample = args.cpu_sample or 2 * threads
+        n_sample = args.cpu_sample or 6 * threads
         n_sample = min(n_sample, n_pairs)
         log(f"[bench] CPU oracle baseline: {n_sample} pairs on {threads} threads")
         cb, pick, res = cpu_baseline(wl, info["i"], info["j"], n_sample, threads, origins=origins)
