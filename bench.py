@@ -200,8 +200,9 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is "
-              "not part of this build", file=sys.stderr)
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU path "
+              "(each GPU a share of the pair list, D summed over GPUs) is designed but not implemented",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch
