@@ -85,6 +85,8 @@ struct exx_ctx {
     DevBuf<int2> d_ij;
     DevBuf<int4> d_gc;
     DevBuf<long long> d_off;
+    std::vector<int> queue;     // CG queue order per wave (empty: pair order)
+    DevBuf<int> d_queue;
     DevBuf<int> d_orb_ptr, d_orb_pairs;
     // pair-list construction
     DevBuf<double> d_pC;
@@ -1384,6 +1386,23 @@ exx_status pairs_common(exx_ctx *c, int32_t n_orb, const double *C, const double
         }
         c->vout_n = vmax;
         if ((st = upload(c, c->d_off, c->out_off)) != EXX_OK) return st;
+        // CG queue: within each wave the pairs of the larger classes first, so
+        // that the longest solves do not start last and leave a tail where
+        // most of the GPU idles.  Each pair's result does not depend on when
+        // or where it is solved, so the order changes no value.
+        c->queue.clear();
+        bool mixed_sizes = false;
+        for (int k = 1; k < c->n_cls; ++k) mixed_sizes |= c->cls[k].n_pe != c->cls[0].n_pe;
+        if (mixed_sizes) {
+            c->queue.resize((size_t)c->n_pairs);
+            for (int64_t p = 0; p < c->n_pairs; ++p) c->queue[p] = (int)p;
+            for (int64_t w0 = 0; w0 < c->n_pairs; w0 += w)
+                std::stable_sort(c->queue.begin() + w0, c->queue.begin() + std::min<int64_t>(w0 + w, c->n_pairs),
+                                 [&](int u, int v) { return c->cls[c->gc[u].w].n_pe > c->cls[c->gc[v].w].n_pe; });
+            if ((st = upload(c, c->d_queue, c->queue)) != EXX_OK) return st;
+        } else {
+            dev_free(c->d_queue);
+        }
         if ((st = dev_reserve(c, c->d_vout, (size_t)vmax)) != EXX_OK) return st;
         if ((st = dev_reserve(c, c->d_rhs, (size_t)w * c->slot_n)) != EXX_OK) return st;
         if (w < c->n_pairs) {
@@ -1431,6 +1450,7 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
     a.pair_gc = c->d_gc.p;
     a.pair_ij = c->d_ij.p;
     a.out_off = c->d_off.p;
+    a.queue = c->queue.empty() ? nullptr : c->d_queue.p;
     a.phi = phi;
     a.box = orb_box(c);
     a.phi_f32 = c->prm.orbital_dtype == EXX_F32;
@@ -1952,7 +1972,7 @@ void exx_destroy(exx_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (auto &k : c->cls) free_class(k);
-    dev_free(c->d_ij); dev_free(c->d_gc); dev_free(c->d_off); dev_free(c->d_orb_ptr); dev_free(c->d_orb_pairs);
+    dev_free(c->d_ij); dev_free(c->d_gc); dev_free(c->d_off); dev_free(c->d_queue); dev_free(c->d_orb_ptr); dev_free(c->d_orb_pairs);
     dev_free(c->d_vout); dev_free(c->d_q); dev_free(c->d_e); dev_free(c->d_relres); dev_free(c->d_scratch);
     dev_free(c->d_rhs); dev_free(c->d_rho_keep);
     dev_free(c->d_guess); dev_free(c->d_hist_off);

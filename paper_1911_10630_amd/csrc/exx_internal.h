@@ -127,6 +127,8 @@ struct SolveArgs {
     const int4 *pair_gc;        // [n_pairs] {gx, gy, gz, class}
     const int2 *pair_ij;        // [n_pairs] {i, j}
     const long long *out_off;   // [n_pairs] offset of the pair's v in vout (relative to its wave)
+    const int *queue;           // [n_pairs] pair taken at each CG queue position (a permutation
+                                // within each wave, largest class first), or null: pair order
     const void *phi;            // [n_orb][bz][by][bx] on the orbital boxes
     OrbBox box;
     int phi_f32;

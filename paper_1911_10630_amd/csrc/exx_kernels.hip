@@ -314,7 +314,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve(SolveArgs a)
             __syncthreads();
         }
         if (k >= a.wave_n) break;
-        cg_one_pair<BLOCK>(a, a.wave_begin + k, blockIdx.x, red);
+        cg_one_pair<BLOCK>(a, a.queue ? a.queue[a.wave_begin + k] : a.wave_begin + k, blockIdx.x, red);
     }
 }
 
@@ -1426,7 +1426,8 @@ __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
         const int k = s_pair;
         __syncthreads();
         if (k >= a.wave_n) break;
-        const int cls = a.pair_gc[a.wave_begin + k].w;
+        const int pair = a.queue ? a.queue[a.wave_begin + k] : a.wave_begin + k;
+        const int cls = a.pair_gc[pair].w;
         if (cls != last_cls) {
             // the row-offset table of the class lives at the start of LDS
             const ClassDev g = a.cls[cls];
@@ -1435,7 +1436,7 @@ __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
             __syncthreads();
             last_cls = cls;
         }
-        cg_zmarch_pair<T, K, KH, K32, KH32, MODE>(a, a.wave_begin + k, blockIdx.x, lds_dyn, red, par);
+        cg_zmarch_pair<T, K, KH, K32, KH32, MODE>(a, pair, blockIdx.x, lds_dyn, red, par);
     }
 }
 
