@@ -309,9 +309,13 @@ def main():
     if args.precond != "none":
         line["config"]["precond"] = args.precond
     if classed:
+        nc = st["n_classes"]
+        # the subdomains are the classes', not the workload's fixed pair
+        line["config"].update(r_pe_bohr=[round(c[0], 4) for c in ckw["classes"]],
+                              r_me_bohr=[round(c[1], 4) for c in ckw["classes"]],
+                              n_pe=st["class_n_pe"][:nc], n_me=st["class_n_me"][:nc])
         line["config"]["pair_classes"] = dict(omega_scale=args.omega_scale,
-                                              r_pe_bohr=[c[0] for c in ckw["classes"]],
-                                              pairs=st["class_pairs"][:st["n_classes"]], capped=st["class_capped"])
+                                              pairs=st["class_pairs"][:nc], capped=st["class_capped"])
     if learned:
         line["config"]["guess"] = "learned"
         learned["guess_ms"] = round(st["guess_ms"], 2)
