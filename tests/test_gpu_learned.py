@@ -27,6 +27,11 @@ from oracle import oracle as O  # noqa: E402
 from paper_1911_10630_amd import exx as X  # noqa: E402
 from paper_1911_10630_amd import synth as S  # noqa: E402
 
+# The CG stops when its recursive residual reaches 1e-10 ||b|| (as the
+# oracle's CG does); the true residual recomputed after the last step can sit
+# above that by the drift between the two (2.8e-7 relative seen on water64).
+RELRES_BAR = 1e-10 * (1 + 1e-4)
+
 LAYERS = [(16, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (64, 64), (64, 64), (128, 64), (96, 32),
           (48, 16), (16, 16)]
 
@@ -213,7 +218,7 @@ def test_learned_guess_same_result(c1_ref, trained, precision):
     i0, il = c0.pair_info(), cl.pair_info()
     st = cl.stats()
     assert st["guess_pairs"] == len(il["e"]) and st["guess_ms"] >= 0.0
-    assert np.all(il["converged"] == 1) and il["relres"].max() <= 1e-10
+    assert np.all(il["converged"] == 1) and il["relres"].max() <= RELRES_BAR
     assert abs(El - E) <= 1e-8 * abs(E), (El, E)
     assert _gamma(D, Dl).max() <= 1e-7
     _say(f"  iterations zero {i0['iters'].mean():.1f} learned {il['iters'].mean():.1f}")

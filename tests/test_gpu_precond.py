@@ -21,6 +21,11 @@ from oracle import oracle as O  # noqa: E402
 from paper_1911_10630_amd import exx as X  # noqa: E402
 from paper_1911_10630_amd import synth as S  # noqa: E402
 
+# The CG stops when its recursive residual reaches 1e-10 ||b|| (as the
+# oracle's CG does); the true residual recomputed after the last step can sit
+# above that by the drift between the two (2.8e-7 relative seen on water64).
+RELRES_BAR = 1e-10 * (1 + 1e-4)
+
 
 def _say(msg):
     print(msg, flush=True)
@@ -48,7 +53,7 @@ def test_mg_c1_matches_the_oracle(c1):
     Eg, Dg = ctx.step(torch.from_numpy(phi).cuda())
     info = ctx.pair_info()
     assert n == len(out["e"])
-    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
     assert abs(Eg - E) <= 1e-8 * abs(E), (Eg, E)
     rel = np.abs(info["e"] - out["e"]) / np.abs(out["e"])
     assert rel.max() <= 1e-8, rel.max()
@@ -68,7 +73,7 @@ def test_mg_c1_previous_guess(c1):
     it1 = ctx.pair_info()["iters"].mean()
     E2, _ = ctx.step(phit)
     info = ctx.pair_info()
-    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
     assert abs(E2 - E) <= 1e-8 * abs(E) and abs(E1 - E) <= 1e-8 * abs(E)
     assert info["iters"].mean() < 0.5 * it1
 
@@ -102,7 +107,7 @@ def test_mg_c2_sampled_pairs_vs_oracle():
     st = ctx.stats()
     _say(f"[gpu] {n} pairs, mean iterations {info['iters'].mean():.1f}, cg {st['cg_ms']:.1f} ms")
     assert n == 9966
-    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
     w = np.where(info["i"] == info["j"], 1.0, 2.0)
     assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
     assert info["iters"].mean() < 100
@@ -149,7 +154,7 @@ def test_mg_c5_full_size_two_classes_in_waves():
     st = ctx.stats()
     _say(f"[gpu] {n} pairs in {st['n_waves']} waves, mean iterations {info['iters'].mean():.1f}")
     assert st["n_waves"] > 1 and st["n_pe"][0] > st["n_pe"][1]
-    assert np.all(info["converged"] == 1) and info["relres"].max() <= 1e-10
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
     assert info["iters"].mean() < 60
     w = np.where(info["i"] == info["j"], 1.0, 2.0)
     assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
