@@ -136,6 +136,7 @@ struct exx_ctx {
     bool g_learned = false, last_graph = false;
     int graph_builds = 0, graph_launches = 0;
     double tune_ms = 0.0;    // time of the timed tuning launches
+    bool tune_on_pairs = false;   // variant to be timed on the first per-pair class mix
     CgVariant var{0, 256, 0, 0, 0, 0, 0};
     size_t lds_bytes = 0;
     long long slot_n = 0;
@@ -717,13 +718,6 @@ struct Candidate {
     int bands;               // y bands over all classes (each re-reads 3-row halos)
 };
 
-// Measured choice among the candidates: each runs kTuneIters CG iterations
-// (60; 15 with the multigrid preconditioner) on every pair of a synthetic
-// batch (the largest class, constant right-hand side, residual target 0 so no
-// pair stops early; two pairs per resident work-group of the widest grid),
-// after one untimed launch; the fastest wins, a tie within 1 % going to the
-// fewest bands.  Returns the index of the winner, or -1 (heuristic) when the
-// device cannot hold the batch.
 // Multigrid arguments of the CG kernel: the levels of every class and the
 // per-slot coarse scratch.
 void mg_args(const exx_ctx *c, SolveArgs &a, double *scratch)
@@ -747,7 +741,16 @@ void mg_args(const exx_ctx *c, SolveArgs &a, double *scratch)
     a.mg_coarse_sweeps = 8;
 }
 
-int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
+// Measured choice among the candidates: each runs kTuneIters CG iterations
+// (60; 15 with the multigrid preconditioner) on every pair of a synthetic
+// batch (constant right-hand side, residual target 0 so no pair stops early;
+// two pairs per resident work-group of the widest grid), after one untimed
+// launch; the fastest wins, a tie within 1 % going to the fewest bands.  The
+// batch is the largest class, or, given mix (pairs per class of the real
+// list), the classes in those proportions, larger classes first as in the
+// CG queue.  Returns the index of the winner, or -1 (heuristic) when the
+// device cannot hold the batch.
+int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms, const int64_t *mix)
 {
     // a preconditioned iteration costs about four plain ones
     const int kTuneIters = c->prm.precond == EXX_PRECOND_MG ? 15 : 60;
@@ -796,6 +799,30 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
         return -1;
     }
     std::vector<int4> hgc((size_t)n, int4{0, 0, 0, kb});
+    if (mix) {
+        // pairs per class in proportion to the real list (each class in use
+        // at least once), the larger classes first
+        int64_t tot = 0;
+        for (int k = 0; k < c->n_cls; ++k) tot += mix[k];
+        std::vector<int> cnt(c->n_cls, 0);
+        int used = 0;
+        for (int k = 0; k < c->n_cls && tot > 0; ++k) {
+            cnt[k] = mix[k] > 0 ? std::max(1, (int)((double)n * mix[k] / tot + 0.5)) : 0;
+            used += cnt[k];
+        }
+        if (tot > 0) {
+            int most = 0;
+            for (int k = 1; k < c->n_cls; ++k) if (cnt[k] > cnt[most]) most = k;
+            cnt[most] = std::max(1, cnt[most] + (n - used));
+            std::vector<int> order(c->n_cls);
+            for (int k = 0; k < c->n_cls; ++k) order[k] = k;
+            std::stable_sort(order.begin(), order.end(), [&](int u, int v) { return c->cls[u].n_pe > c->cls[v].n_pe; });
+            size_t p = 0;
+            for (int k : order)
+                for (int t = 0; t < cnt[k] && p < hgc.size(); ++t) hgc[p++].w = k;
+            for (; p < hgc.size(); ++p) hgc[p].w = order.back();
+        }
+    }
     std::vector<int2> hij((size_t)n, int2{0, 0});
     std::vector<long long> hoff((size_t)n);
     for (int p = 0; p < n; ++p) hoff[p] = (long long)p * per_pair;
@@ -872,7 +899,7 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms)
 // more than one fits, else the one with the most resident waves per CU, then
 // the most work-groups per CU, then the fewest bands.  The flat kernel when
 // none fits.
-exx_status select_variant(exx_ctx *c)
+exx_status select_variant(exx_ctx *c, const int64_t *mix = nullptr)
 {
     CgVariant vs[32];
     const int nv = cg_variants(vs, 32);
@@ -912,9 +939,16 @@ exx_status select_variant(exx_ctx *c)
         return fail(c, EXX_EINVAL, "no CG kernel available");
     }
     int best = -1;
+    c->tune_on_pairs = false;
     if (c->prm.autotune && cands.size() > 1) {
-        best = autotune(c, cands, &c->tune_ms);
-        if (best >= 0) c->tuned = (int)cands.size();
+        if (c->prm.n_classes >= 2 && !mix) {
+            // per-pair classes: the mix of classes is known at the first
+            // exx_pairs_spread, which times the variants on it
+            c->tune_on_pairs = true;
+        } else {
+            best = autotune(c, cands, &c->tune_ms, mix);
+            if (best >= 0) c->tuned = (int)cands.size();
+        }
     }
     if (best < 0) {
         best = 0;
@@ -1259,6 +1293,12 @@ exx_status pairs_common(exx_ctx *c, int32_t n_orb, const double *C, const double
                 ++c->class_capped;
             }
             c->gc[p].w = k;
+        }
+        if (c->tune_on_pairs) {
+            std::vector<int64_t> mix(KMAX, 0);
+            for (const int4 &q : c->gc) ++mix[q.w];
+            exx_status st = select_variant(c, mix.data());
+            if (st != EXX_OK) return st;
         }
     }
     c->n_orb = n_orb;
