@@ -94,7 +94,9 @@ typedef struct {
     int32_t keep_intermediates; /* 1: keep rho, b per pair for exx_debug_pair   */
     int32_t autotune;       /* 1 (default): exx_setup times every CG kernel
                                variant that fits (a few CG iterations on a
-                               synthetic batch) and keeps the fastest;
+                               synthetic batch) and keeps the fastest; with
+                               n_classes >= 2 the first exx_pairs_spread does
+                               it instead, on a batch in its class mix;
                                0: choose by occupancy alone                  */
     int32_t graph;          /* 1: exx_solve captures its launches into a HIP
                                graph on a stream of its own and replays it
@@ -148,7 +150,7 @@ typedef struct {
     int32_t wave_n;          /* pairs per wave (the last wave may hold fewer)   */
     int32_t guess_pairs;     /* pairs whose CG started from a non-zero guess    */
     double  guess_ms;        /* last solve: guess kernels / model inference     */
-    int32_t tuned;           /* CG variants the set-up autotuner timed (0: none) */
+    int32_t tuned;           /* CG variants the autotuner timed (0: none)      */
     double  tune_ms;         /* time of those tuning launches                   */
     int32_t graph_builds;    /* graph mode: captures so far                     */
     int32_t graph_launches;  /* graph mode: solves launched as a graph          */
