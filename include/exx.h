@@ -232,8 +232,10 @@ exx_status exx_pair_owners(exx_ctx *ctx, int32_t *owner, int32_t *sweeps);
 exx_status exx_box_origins(exx_ctx *ctx, int32_t *origins);
 
 /* Enqueues every pair solve on `stream` (a hipStream_t; NULL = default):
- * gather and pair density, multipole moments, shell potential and
- * right-hand side, conjugate gradient, pair energy.  phi: device,
+ * gather and pair density (Step III, Eq. l2g), multipole moments
+ * (Eq. mepole), shell potential (Eq. me) and right-hand side
+ * (Eq. pe_mat_red), conjugate gradient on the stencil of Eq. d2_1 (Step IV),
+ * pair energy (Step V, Eq. exx_omega).  phi: device,
  * [n_orb][Nz][Ny][Nx] of orbital_dtype, read-only, must stay valid until
  * the stream work completes.  Asynchronous.  When the pairs' potentials
  * do not fit at once, the pairs run in waves and D is summed wave by wave
@@ -241,8 +243,9 @@ exx_status exx_box_origins(exx_ctx *ctx, int32_t *origins);
  * split). */
 exx_status exx_solve(exx_ctx *ctx, const void *phi, void *stream);
 
-/* Enqueues D accumulation and the E reduction on `stream`, then
- * synchronizes it.  dxx: device, same shape and dtype as phi, fully
+/* Enqueues D accumulation (Step V, Eq. Dxx_mlwf_omega: D^i += v_ij phi_j
+ * and D^j += v_ij phi_i over the ME sphere of each pair) and the E reduction
+ * (Eq. exx_omega) on `stream`, then synchronizes it.  dxx: device, same shape and dtype as phi, fully
  * overwritten (every point of every orbital).  *e_xx receives E_xx (host).
  * Returns EXX_ENOCONV (with results written) if any pair failed to
  * converge. */
@@ -275,7 +278,7 @@ exx_status exx_debug_pair(exx_ctx *ctx, int64_t pair, double *v_pe, double *v_sh
  * coarse cells of `coarsen`^3 grid points around the pair origin, to the
  * coarse potential; the potential is interpolated back onto the PE sphere as
  * the CG starting point (EXX_GUESS_LEARNED).  The paper names better initial
- * guesses as the route to fewer CG iterations (Sec. III.C Step IV, Sec. VI).
+ * guesses as the route to fewer CG iterations (Sec. III.C Step IV, Sec. IV.B).
  * The model lives in the context and survives exx_pairs. */
 
 /* Creates a model with random (He-normal, seeded) weights.  coarsen: 2 or 4
@@ -322,6 +325,28 @@ exx_status exx_model_conv(exx_ctx *ctx, int32_t layer, int32_t transposed, const
  * dw: device FP32 [27][Cout][Cin], overwritten.  Asynchronous. */
 exx_status exx_model_wgrad(exx_ctx *ctx, int32_t layer, const void *x, const void *dy, float *dw, int32_t n,
                            int32_t edge, void *stream);
+
+/* ---- measurement -----------------------------------------------------------
+ *
+ * Streaming rates of plain kernels on `device`, the measured ceiling that the
+ * pair CG's HBM bandwidth is set against beside the nominal peak.  Not part
+ * of the method.  Five arrays of bytes_per_array bytes (rounded down to a
+ * whole number of 16 KiB) are allocated, zeroed and freed inside the call.
+ * gbs: host [4] receives GB/s (1e9 bytes per second, every byte read or
+ * written counted once) of the best launch of each kind:
+ *   gbs[0] read   two arrays read, nothing written
+ *   gbs[1] copy   one read, one written
+ *   gbs[2] triad  two read, one written (the CG passes' mix, about 2:1)
+ *   gbs[3] cg     three read, two written
+ * the best over 4, 8 and 16 work-groups of 256 threads per CU, 1, 2 or 4
+ * 16-byte accesses per array in flight per thread, plain or non-temporal,
+ * `reps` timed launches each after one untimed (HIP events, default stream).
+ * detail (may be NULL): host buffer of detail_len bytes receiving a one-line
+ * description of the winning launch shapes.  Synchronizes the device.
+ * EXX_EINVAL if gbs is NULL, bytes_per_array < 1 MiB or reps < 1;
+ * EXX_ENOMEM if the arrays do not fit; EXX_EDEVICE on any HIP error. */
+exx_status exx_stream_rates(int device, int64_t bytes_per_array, int32_t reps, double *gbs, char *detail,
+                            int32_t detail_len);
 
 /* Message of the last failing call on ctx (or of the last failing
  * exx_setup when ctx is NULL).  Never NULL. */

@@ -124,20 +124,17 @@ def min_image_d2(ci, cj, cell) -> float:
 
 
 def unique_pair_owners(centers, cell, r_pair, by_distance=True):
-    """Alg. 1 (Sec. III C): refinement of the non-unique pair list L0 to the
-    unique list Lu.
+    """Alg. 1 (Sec. III C): the unique pair list Lu refined from the
+    non-unique list L0, given as the owner of every pair.
 
     L0 row i lists every orbital that overlaps i (the pair criterion of
-    Step II), i itself included, in ascending distance from i; distances are
+    Step II), i itself included, ordered by distance from i; distances are
     compared as the squared minimum-image length, ties by index (the paper
-    sorts by |C_i - C_j| and does not say how ties fall).  A sweep visits
-    i = 0, 1, ..., n-1; orbital i walks its current row and, at the first
-    j != i whose row still contains i, deletes i from row j and ends its turn.
-    Sweeps repeat until one deletes nothing.  The pair (i, j) then belongs to
-    the orbital whose row still holds the other.
+    orders by |C_i - C_j| and leaves ties open).  See refine_pair_rows for
+    the refinement itself.
 
-    by_distance=False keeps each row in index order instead, the ordering
-    the paper warns against (it unbalances the owners).
+    by_distance=False orders each row by index instead, the ordering the
+    paper warns against (it unbalances the owners).
 
     Returns (owner, sweeps): owner[p] for the pairs of pair_list() in its
     order, and the number of sweeps including the last, empty one.
@@ -162,22 +159,41 @@ def refine_pair_rows(L0):
     """Alg. 1 on explicit rows: L0[i] lists orbital i's overlapping orbitals
     (i among them) in the order the sweeps scan them.  Returns (Lu, sweeps):
     the refined rows, in their original order with the removed entries
-    dropped, and the number of sweeps including the last, empty one."""
-    L = [list(r) for r in L0]
-    member = [set(r) for r in L]
+    dropped, and the number of sweeps including the last, empty one.
+
+    The rule, as the paper's prose states it: an unordered pair {i, j} is
+    redundant while it is listed both in row i and in row j.  A sweep takes
+    the orbitals in index order, and each orbital i settles the first
+    redundant pair of its row, in the row's order: i keeps it and j's row
+    drops i.  Sweeps repeat until one settles nothing.  Here every pair
+    carries a holder: "both" while redundant, else the one row that still
+    lists it; a self pair is held by its orbital from the start.
+    """
+    n = len(L0)
+    listed = [set(r) for r in L0]
+    holder = {}
+    for i in range(n):
+        for j in L0[i]:
+            key = (min(i, j), max(i, j))
+            if i == j:
+                holder[key] = i
+            elif key not in holder:
+                holder[key] = "both" if i in listed[j] else i
     sweeps = 0
-    removed = True
-    while removed:
-        removed = False
+    while True:
         sweeps += 1
-        for i in range(len(L)):
-            for j in L[i]:
-                if j != i and i in member[j]:
-                    L[j].remove(i)
-                    member[j].discard(i)
-                    removed = True
+        settled = 0
+        for i in range(n):
+            for j in L0[i]:
+                key = (min(i, j), max(i, j))
+                if holder[key] == "both":
+                    holder[key] = i
+                    settled += 1
                     break
-    return L, sweeps
+        if settled == 0:
+            break
+    Lu = [[j for j in L0[i] if holder[(min(i, j), max(i, j))] == i] for i in range(n)]
+    return Lu, sweeps
 
 
 def pair_origin(ci, cj, cell, n):

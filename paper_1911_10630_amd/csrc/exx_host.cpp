@@ -21,7 +21,8 @@ namespace {
 // Central-difference weights of the second derivative for n = 3 (Eq. d2_1).
 constexpr double kFD[4] = {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0};
 
-std::string g_setup_error = "no error";
+// messages live in fixed buffers so that reporting a failure never allocates
+char g_setup_error[512] = "no error";
 
 // Fortran NINT: nearest integer, halves away from zero.
 long nint_away(double v) { return (long)(v >= 0.0 ? std::floor(v + 0.5) : -std::floor(-v + 0.5)); }
@@ -70,7 +71,7 @@ struct exx_ctx {
     HostClass cls[KMAX];
     int n_cls = 2;            // classes in use (self / non-self unless params.n_classes >= 2)
     int64_t class_capped = 0; // pairs of the list whose domain the largest class does not cover
-    std::string err = "no error";
+    char err[512] = "no error";
     int state = 0;  // 1 set up, 2 pairs built, 3 solved
 
     // pairs
@@ -151,17 +152,21 @@ namespace {
 
 exx_status fail(exx_ctx *c, exx_status st, const char *fmt, ...)
 {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(c ? c->err : g_setup_error, sizeof g_setup_error, fmt, ap);
     va_end(ap);
-    if (c)
-        c->err = buf;
-    else
-        g_setup_error = buf;
     return st;
 }
+
+#define EXX_GUARDED(ctx, call)                                                   \
+    try {                                                                        \
+        return call;                                                             \
+    } catch (const std::bad_alloc &) {                                           \
+        return fail(ctx, EXX_ENOMEM, "host allocation failed");                  \
+    } catch (...) {                                                              \
+        return fail(ctx, EXX_EDEVICE, "unexpected C++ exception");               \
+    }
 
 #define HIPCHK(ctx, call)                                                                            \
     do {                                                                                             \
@@ -402,7 +407,12 @@ exx_status build_class(exx_ctx *c, HostClass &k, double r_pe, double r_me)
             }
         }
     }
-    // upload
+    return EXX_OK;
+}
+
+// Copies the tables of one class to the current device.
+exx_status upload_class(exx_ctx *c, HostClass &k)
+{
     auto up = [&](auto **dst, const auto &v) -> exx_status {
         using T = std::remove_reference_t<decltype(v[0])>;
         size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
@@ -1032,42 +1042,55 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         if (classed && c > 0 && !(rpe[c] > rpe[c - 1]))
             return fail(nullptr, EXX_EINVAL, "class_r_pe must be strictly ascending");
     }
-    int ndev = 0;
-    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
-        return fail(nullptr, EXX_EDEVICE, "no HIP device available");
-    if (device < 0 || device >= ndev) return fail(nullptr, EXX_EINVAL, "device %d out of range [0, %d)", device, ndev);
+    if (device < 0) return fail(nullptr, EXX_EINVAL, "device %d is negative", device);
     exx_ctx *c = new (std::nothrow) exx_ctx();
     if (!c) return fail(nullptr, EXX_ENOMEM, "host allocation failed");
     c->prm = *p;
     c->device = device;
     auto bail = [&](exx_status st) {
-        g_setup_error = c->err;
+        std::snprintf(g_setup_error, sizeof g_setup_error, "%s", c->err);
         exx_destroy(c);
         return st;
     };
-    if (hipSetDevice(device) != hipSuccess) return bail(fail(c, EXX_EDEVICE, "hipSetDevice(%d) failed", device));
-    hipDeviceProp_t prop;
-    if (hipGetDeviceProperties(&prop, device) != hipSuccess) return bail(fail(c, EXX_EDEVICE, "hipGetDeviceProperties failed"));
-    c->n_cu = prop.multiProcessorCount;
-    for (int a = 0; a < 3; ++a) {
-        c->h[a] = p->cell[a] / p->n_grid[a];
-        c->c0[a] = (int)nint_away(0.5 * p->n_grid[a]);
-        c->box[a] = p->box_dims[a] > 0 ? p->box_dims[a] : p->n_grid[a];
+    try {
+        // the proto-subdomain tables first: they need no device
+        for (int a = 0; a < 3; ++a) {
+            c->h[a] = p->cell[a] / p->n_grid[a];
+            c->c0[a] = (int)nint_away(0.5 * p->n_grid[a]);
+            c->box[a] = p->box_dims[a] > 0 ? p->box_dims[a] : p->n_grid[a];
+        }
+        c->box_vol = (long long)c->box[0] * c->box[1] * c->box[2];
+        c->n_cls = ncls;
+        for (int k = 0; k < ncls; ++k) {
+            exx_status st = build_class(c, c->cls[k], rpe[k], rme[k]);
+            if (st != EXX_OK) return bail(st);
+        }
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+            return bail(fail(c, EXX_EDEVICE, "no HIP device available"));
+        if (device >= ndev) return bail(fail(c, EXX_EINVAL, "device %d out of range [0, %d)", device, ndev));
+        if (hipSetDevice(device) != hipSuccess) return bail(fail(c, EXX_EDEVICE, "hipSetDevice(%d) failed", device));
+        hipDeviceProp_t prop;
+        if (hipGetDeviceProperties(&prop, device) != hipSuccess)
+            return bail(fail(c, EXX_EDEVICE, "hipGetDeviceProperties failed"));
+        c->n_cu = prop.multiProcessorCount;
+        for (int k = 0; k < ncls; ++k) {
+            exx_status st = upload_class(c, c->cls[k]);
+            if (st != EXX_OK) return bail(st);
+            if (p->precond == EXX_PRECOND_MG && (st = build_mg_levels(c, c->cls[k])) != EXX_OK) return bail(st);
+        }
+        {
+            exx_status st = select_variant(c);
+            if (st != EXX_OK) return bail(st);
+        }
+        for (auto &e : c->ev)
+            if (hipEventCreate(&e) != hipSuccess) return bail(fail(c, EXX_EDEVICE, "hipEventCreate failed"));
+        c->have_events = true;
+    } catch (const std::bad_alloc &) {
+        return bail(fail(c, EXX_ENOMEM, "exx_setup: host allocation failed"));
+    } catch (...) {
+        return bail(fail(c, EXX_EDEVICE, "exx_setup: unexpected C++ exception"));
     }
-    c->box_vol = (long long)c->box[0] * c->box[1] * c->box[2];
-    c->n_cls = ncls;
-    for (int k = 0; k < ncls; ++k) {
-        exx_status st = build_class(c, c->cls[k], rpe[k], rme[k]);
-        if (st != EXX_OK) return bail(st);
-        if (p->precond == EXX_PRECOND_MG && (st = build_mg_levels(c, c->cls[k])) != EXX_OK) return bail(st);
-    }
-    {
-        exx_status st = select_variant(c);
-        if (st != EXX_OK) return bail(st);
-    }
-    for (auto &e : c->ev)
-        if (hipEventCreate(&e) != hipSuccess) return bail(fail(c, EXX_EDEVICE, "hipEventCreate failed"));
-    c->have_events = true;
     c->state = 1;
     *out = c;
     return EXX_OK;
@@ -1153,66 +1176,64 @@ exx_status build_pair_list(exx_ctx *c, int n_orb, const double *C)
     return EXX_OK;
 }
 
-// Alg. 1: refinement of the non-unique pair list L0 (row i: every orbital
-// overlapping i, itself included, in ascending distance from i) to the
-// unique list Lu.  Sweeps over i = 0..n-1: i takes the first j != i of its
-// current row whose row still holds i, and removes i from row j; repeated
-// until a sweep removes nothing.  The pair (i, j) is then owned by the
-// orbital whose row kept the other.  Distances are compared as the squared
-// minimum-image length, ties by index.
+// Alg. 1: the unique pair list Lu refined from the non-unique list L0, as
+// the owner of every pair.  A pair (i, j), i != j, is redundant while both
+// row i and row j of L0 list it; a sweep takes the orbitals in index order
+// and each orbital claims the nearest pair of its own that is still
+// redundant (the partner's row drops it); sweeps repeat until one claims
+// nothing.  Here each pair has an owner slot, -1 while it is redundant;
+// each orbital's pairs are kept in ascending squared minimum-image distance
+// of the partner, ties by partner index (the row order of L0).
 void unique_pair_owners(exx_ctx *c)
 {
     const int n = c->n_orb;
     const size_t np = c->ij.size();
     const double *L = c->prm.cell;
-    // rows: (d^2, partner, pair) per orbital, self first
+    // each orbital's non-self pairs, as (d^2, partner, pair)
     std::vector<int> rs((size_t)n + 1, 0);
-    for (const int2 &q : c->ij) {
-        rs[q.x + 1]++;
-        if (q.y != q.x) rs[q.y + 1]++;
-    }
+    for (const int2 &q : c->ij)
+        if (q.y != q.x) {
+            rs[q.x + 1]++;
+            rs[q.y + 1]++;
+        }
     for (int i = 0; i < n; ++i) rs[i + 1] += rs[i];
     struct Ent { double d2; int j; int p; };
-    std::vector<Ent> row((size_t)rs[n]);
+    std::vector<Ent> mine((size_t)rs[n]);
+    c->owner.assign(np, -1);
     {
         std::vector<int> fill(rs.begin(), rs.end() - 1);
         for (size_t p = 0; p < np; ++p) {
             const int i = c->ij[p].x, j = c->ij[p].y;
+            if (i == j) {
+                c->owner[p] = i;          // a self pair is never redundant
+                continue;
+            }
             double dd = 0.0;
             for (int a = 0; a < 3; ++a) {
                 double v = c->centers[3 * j + a] - c->centers[3 * i + a];
                 v -= L[a] * (double)nint_away(v / L[a]);
                 dd += v * v;
             }
-            row[fill[i]++] = Ent{dd, j, (int)p};
-            if (j != i) row[fill[j]++] = Ent{dd, i, (int)p};
+            mine[fill[i]++] = Ent{dd, j, (int)p};
+            mine[fill[j]++] = Ent{dd, i, (int)p};
         }
     }
     for (int i = 0; i < n; ++i)
-        std::sort(row.begin() + rs[i], row.begin() + rs[i + 1], [](const Ent &u, const Ent &v) {
+        std::sort(mine.begin() + rs[i], mine.begin() + rs[i + 1], [](const Ent &u, const Ent &v) {
             return u.d2 < v.d2 || (u.d2 == v.d2 && u.j < v.j);
         });
-    // in_row[2p + s]: pair p still listed in the row of its i (s = 0) / j (s = 1)
-    std::vector<unsigned char> in_row(2 * np, 1);
-    auto listed = [&](int orb, int p) { return in_row[2 * p + (c->ij[p].x == orb ? 0 : 1)] != 0; };
-    bool any = true;
     int sweeps = 0;
-    while (any) {
-        any = false;
+    for (bool claimed = true; claimed;) {
+        claimed = false;
         ++sweeps;
         for (int i = 0; i < n; ++i)
-            for (int t = rs[i]; t < rs[i + 1]; ++t) {
-                const Ent &e = row[t];
-                if (e.j == i || !listed(i, e.p)) continue;
-                if (listed(e.j, e.p)) {
-                    in_row[2 * e.p + (c->ij[e.p].x == e.j ? 0 : 1)] = 0;   // i leaves row j
-                    any = true;
+            for (int t = rs[i]; t < rs[i + 1]; ++t)
+                if (c->owner[mine[t].p] < 0) {
+                    c->owner[mine[t].p] = i;
+                    claimed = true;
                     break;
                 }
-            }
     }
-    c->owner.assign(np, 0);
-    for (size_t p = 0; p < np; ++p) c->owner[p] = in_row[2 * p] ? c->ij[p].x : c->ij[p].y;
     c->owner_sweeps = sweeps;
 }
 
@@ -1460,14 +1481,14 @@ exx_status pairs_common(exx_ctx *c, int32_t n_orb, const double *C, const double
     return EXX_OK;
 }
 
-exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pairs)
+static exx_status exx_pairs_body(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pairs)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_pairs: ctx is NULL");
     if (c->prm.n_classes >= 2) return fail(c, EXX_EINVAL, "n_classes >= 2: the pair classes need exx_pairs_spread");
     return pairs_common(c, n_orb, C, nullptr, n_pairs);
 }
 
-exx_status exx_pairs_spread(exx_ctx *c, int32_t n_orb, const double *C, const double *spreads, int64_t *n_pairs)
+static exx_status exx_pairs_spread_body(exx_ctx *c, int32_t n_orb, const double *C, const double *spreads, int64_t *n_pairs)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_pairs_spread: ctx is NULL");
     if (c->prm.n_classes < 2) return fail(c, EXX_EINVAL, "exx_pairs_spread needs n_classes >= 2");
@@ -1478,7 +1499,7 @@ exx_status exx_pairs_spread(exx_ctx *c, int32_t n_orb, const double *C, const do
     return pairs_common(c, n_orb, C, spreads, n_pairs);
 }
 
-exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
+static exx_status exx_solve_body(exx_ctx *c, const void *phi, void *stream)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_solve: ctx is NULL");
     if (c->state < 2) return fail(c, EXX_ESTATE, "exx_solve before exx_pairs");
@@ -1696,7 +1717,7 @@ exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
     return EXX_OK;
 }
 
-exx_status exx_energy_potential(exx_ctx *c, double *e_xx, void *dxx, void *stream)
+static exx_status exx_energy_potential_body(exx_ctx *c, double *e_xx, void *dxx, void *stream)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_energy_potential: ctx is NULL");
     if (c->state < 3) return fail(c, EXX_ESTATE, "exx_energy_potential before exx_solve");
@@ -1722,7 +1743,7 @@ exx_status exx_energy_potential(exx_ctx *c, double *e_xx, void *dxx, void *strea
     return EXX_OK;
 }
 
-exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
+static exx_status exx_stats_body(exx_ctx *c, exx_stats_t *st)
 {
     if (!c || !st) return fail(c, EXX_EINVAL, "exx_stats: null argument");
     std::memset(st, 0, sizeof *st);
@@ -1817,7 +1838,7 @@ exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
     return EXX_OK;
 }
 
-exx_status exx_pair_class(exx_ctx *c, int32_t *cls)
+static exx_status exx_pair_class_body(exx_ctx *c, int32_t *cls)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_pair_class: ctx is NULL");
     if (c->state < 2) return fail(c, EXX_ESTATE, "exx_pair_class before exx_pairs");
@@ -1826,7 +1847,7 @@ exx_status exx_pair_class(exx_ctx *c, int32_t *cls)
     return EXX_OK;
 }
 
-exx_status exx_pair_owners(exx_ctx *c, int32_t *owner, int32_t *sweeps)
+static exx_status exx_pair_owners_body(exx_ctx *c, int32_t *owner, int32_t *sweeps)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_pair_owners: ctx is NULL");
     if (c->state < 2) return fail(c, EXX_ESTATE, "exx_pair_owners before exx_pairs");
@@ -1837,7 +1858,7 @@ exx_status exx_pair_owners(exx_ctx *c, int32_t *owner, int32_t *sweeps)
     return EXX_OK;
 }
 
-exx_status exx_pair_info(exx_ctx *c, int32_t *pi, int32_t *pj, int32_t *origin, double *e, int32_t *iters,
+static exx_status exx_pair_info_body(exx_ctx *c, int32_t *pi, int32_t *pj, int32_t *origin, double *e, int32_t *iters,
                          int32_t *converged, double *relres)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_pair_info: ctx is NULL");
@@ -1860,7 +1881,7 @@ exx_status exx_pair_info(exx_ctx *c, int32_t *pi, int32_t *pj, int32_t *origin, 
     return EXX_OK;
 }
 
-exx_status exx_debug_pair(exx_ctx *c, int64_t pair, double *v_pe, double *v_shell, double *q_lm, double *rho,
+static exx_status exx_debug_pair_body(exx_ctx *c, int64_t pair, double *v_pe, double *v_shell, double *q_lm, double *rho,
                           double *rhs)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_debug_pair: ctx is NULL");
@@ -1883,7 +1904,7 @@ exx_status exx_debug_pair(exx_ctx *c, int64_t pair, double *v_pe, double *v_shel
     return EXX_OK;
 }
 
-exx_status exx_model_init(exx_ctx *c, int32_t coarsen, uint64_t seed)
+static exx_status exx_model_init_body(exx_ctx *c, int32_t coarsen, uint64_t seed)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_init: ctx is NULL");
     if (coarsen != 2 && coarsen != 4) return fail(c, EXX_EINVAL, "coarsen must be 2 or 4 (got %d)", coarsen);
@@ -1909,7 +1930,7 @@ exx_status exx_model_init(exx_ctx *c, int32_t coarsen, uint64_t seed)
     return EXX_OK;
 }
 
-exx_status exx_load_model(exx_ctx *c, const void *weights, size_t bytes)
+static exx_status exx_load_model_body(exx_ctx *c, const void *weights, size_t bytes)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_load_model: ctx is NULL");
     if (c->prm.n_classes >= 2) return fail(c, EXX_EINVAL, "the learned guess needs n_classes = 0 (two classes)");
@@ -1924,7 +1945,7 @@ exx_status exx_load_model(exx_ctx *c, const void *weights, size_t bytes)
     return EXX_OK;
 }
 
-exx_status exx_model_save(exx_ctx *c, void *buf, size_t *bytes)
+static exx_status exx_model_save_body(exx_ctx *c, void *buf, size_t *bytes)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_save: ctx is NULL");
     if (!bytes) return fail(c, EXX_EINVAL, "exx_model_save: bytes is NULL");
@@ -1942,7 +1963,7 @@ exx_status exx_model_save(exx_ctx *c, void *buf, size_t *bytes)
     return EXX_OK;
 }
 
-exx_status exx_model_train(exx_ctx *c, int32_t epochs, int32_t batch, double lr, uint64_t seed, double *loss,
+static exx_status exx_model_train_body(exx_ctx *c, int32_t epochs, int32_t batch, double lr, uint64_t seed, double *loss,
                            void *stream)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_train: ctx is NULL");
@@ -1961,7 +1982,7 @@ exx_status exx_model_train(exx_ctx *c, int32_t epochs, int32_t batch, double lr,
     return EXX_OK;
 }
 
-exx_status exx_model_conv(exx_ctx *c, int32_t layer, int32_t transposed, const void *x, float *y, int32_t n,
+static exx_status exx_model_conv_body(exx_ctx *c, int32_t layer, int32_t transposed, const void *x, float *y, int32_t n,
                           int32_t edge, void *stream)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_conv: ctx is NULL");
@@ -1975,7 +1996,7 @@ exx_status exx_model_conv(exx_ctx *c, int32_t layer, int32_t transposed, const v
     return EXX_OK;
 }
 
-exx_status exx_model_wgrad(exx_ctx *c, int32_t layer, const void *x, const void *dy, float *dw, int32_t n,
+static exx_status exx_model_wgrad_body(exx_ctx *c, int32_t layer, const void *x, const void *dy, float *dw, int32_t n,
                            int32_t edge, void *stream)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_wgrad: ctx is NULL");
@@ -1989,7 +2010,7 @@ exx_status exx_model_wgrad(exx_ctx *c, int32_t layer, const void *x, const void 
     return EXX_OK;
 }
 
-exx_status exx_box_origins(exx_ctx *c, int32_t *origins)
+static exx_status exx_box_origins_body(exx_ctx *c, int32_t *origins)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_box_origins: ctx is NULL");
     if (!origins) return fail(c, EXX_EINVAL, "exx_box_origins: origins is NULL");
@@ -2002,9 +2023,96 @@ exx_status exx_box_origins(exx_ctx *c, int32_t *origins)
     return EXX_OK;
 }
 
+// Every entry point that takes a context: nothing thrown inside (a host
+// allocation that fails, say) crosses the C ABI; it becomes a status.
+exx_status exx_pairs(exx_ctx *c, int32_t n_orb, const double *C, int64_t *n_pairs)
+{
+    EXX_GUARDED(c, exx_pairs_body(c, n_orb, C, n_pairs));
+}
+
+exx_status exx_pairs_spread(exx_ctx *c, int32_t n_orb, const double *C, const double *spreads, int64_t *n_pairs)
+{
+    EXX_GUARDED(c, exx_pairs_spread_body(c, n_orb, C, spreads, n_pairs));
+}
+
+exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
+{
+    EXX_GUARDED(c, exx_solve_body(c, phi, stream));
+}
+
+exx_status exx_energy_potential(exx_ctx *c, double *e_xx, void *dxx, void *stream)
+{
+    EXX_GUARDED(c, exx_energy_potential_body(c, e_xx, dxx, stream));
+}
+
+exx_status exx_stats(exx_ctx *c, exx_stats_t *st)
+{
+    EXX_GUARDED(c, exx_stats_body(c, st));
+}
+
+exx_status exx_pair_class(exx_ctx *c, int32_t *cls)
+{
+    EXX_GUARDED(c, exx_pair_class_body(c, cls));
+}
+
+exx_status exx_pair_owners(exx_ctx *c, int32_t *owner, int32_t *sweeps)
+{
+    EXX_GUARDED(c, exx_pair_owners_body(c, owner, sweeps));
+}
+
+exx_status exx_pair_info(exx_ctx *c, int32_t *pi, int32_t *pj, int32_t *origin, double *e, int32_t *iters,
+                         int32_t *converged, double *relres)
+{
+    EXX_GUARDED(c, exx_pair_info_body(c, pi, pj, origin, e, iters, converged, relres));
+}
+
+exx_status exx_debug_pair(exx_ctx *c, int64_t pair, double *v_pe, double *v_shell, double *q_lm, double *rho,
+                          double *rhs)
+{
+    EXX_GUARDED(c, exx_debug_pair_body(c, pair, v_pe, v_shell, q_lm, rho, rhs));
+}
+
+exx_status exx_model_init(exx_ctx *c, int32_t coarsen, uint64_t seed)
+{
+    EXX_GUARDED(c, exx_model_init_body(c, coarsen, seed));
+}
+
+exx_status exx_load_model(exx_ctx *c, const void *weights, size_t bytes)
+{
+    EXX_GUARDED(c, exx_load_model_body(c, weights, bytes));
+}
+
+exx_status exx_model_save(exx_ctx *c, void *buf, size_t *bytes)
+{
+    EXX_GUARDED(c, exx_model_save_body(c, buf, bytes));
+}
+
+exx_status exx_model_train(exx_ctx *c, int32_t epochs, int32_t batch, double lr, uint64_t seed, double *loss,
+                           void *stream)
+{
+    EXX_GUARDED(c, exx_model_train_body(c, epochs, batch, lr, seed, loss, stream));
+}
+
+exx_status exx_model_conv(exx_ctx *c, int32_t layer, int32_t transposed, const void *x, float *y, int32_t n,
+                          int32_t edge, void *stream)
+{
+    EXX_GUARDED(c, exx_model_conv_body(c, layer, transposed, x, y, n, edge, stream));
+}
+
+exx_status exx_model_wgrad(exx_ctx *c, int32_t layer, const void *x, const void *dy, float *dw, int32_t n,
+                           int32_t edge, void *stream)
+{
+    EXX_GUARDED(c, exx_model_wgrad_body(c, layer, x, dy, dw, n, edge, stream));
+}
+
+exx_status exx_box_origins(exx_ctx *c, int32_t *origins)
+{
+    EXX_GUARDED(c, exx_box_origins_body(c, origins));
+}
+
 int32_t exx_model_edge(const exx_ctx *c) { return c && c->net ? c->net_D : 0; }
 
-const char *exx_last_error(const exx_ctx *c) { return c ? c->err.c_str() : g_setup_error.c_str(); }
+const char *exx_last_error(const exx_ctx *c) { return c ? c->err : g_setup_error; }
 
 void exx_destroy(exx_ctx *c)
 {

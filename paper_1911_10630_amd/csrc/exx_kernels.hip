@@ -1,17 +1,23 @@
 // exx_kernels.hip -- HIP kernels (gfx950) of the pair-Poisson exact-exchange
 // path of Ko et al., arXiv:1911.10630, Sec. III.C Steps III-V.
 //
-//   k_solve   persistent: one work-group owns one pair at a time, pulled from a
-//             queue; gather + pair density + multipoles (Eq. mepole), shell
-//             potential (Eq. me), boundary-charge right-hand side
-//             (Eq. pe_mat_red), conjugate gradient on the 19-point stencil
-//             (Eq. d2_1), pair energy (Eq. exx_omega).  Every reduction is a
-//             fixed-order work-group tree, so results are bitwise
-//             reproducible whatever the scheduling.
-//   k_dxx     owner-computes accumulation of D^k = sum_j v_kj phi_j over the
-//             pairs of each orbital, in pair order (Eq. Dxx_mlwf_omega);
-//             no atomics.
-//   k_energy  E_xx = -sum w_ij e_ij in pair order, one work-group.
+//   k_prep        one work-group per pair: gather and pair density (Eq. l2g),
+//                 multipoles (Eq. mepole), shell potential (Eq. me) and the
+//                 boundary-charge right-hand side (Eq. pe_mat_red).
+//   k_cg_zmarch   persistent: one work-group owns one pair at a time, pulled
+//                 from a queue; conjugate gradient on the 19-point stencil
+//                 (Eq. d2_1) marching z planes with a register queue (FP64,
+//                 FP32 with FP64 reliable updates, or multigrid-preconditioned),
+//                 then the true residual.  k_solve is the flat form for
+//                 spheres whose planes do not fit the LDS.
+//   k_pair_energy e_ij = h^3 sum_PE rho_ij v_ij (Eq. exx_omega), one
+//                 work-group per pair.
+//   k_dxx         owner-computes accumulation of D^k = sum_j v_kj phi_j over
+//                 the pairs of each orbital, in pair order (Eq. Dxx_mlwf_omega);
+//                 no atomics.
+//   k_energy      E_xx = -sum w_ij e_ij in pair order, one work-group.
+// Every reduction is a fixed-order work-group tree, so results are bitwise
+// reproducible whatever the scheduling.
 #include "exx_internal.h"
 
 #include <algorithm>
@@ -337,8 +343,8 @@ __global__ __launch_bounds__(BLOCK) void k_solve(SolveArgs a)
 //              band's halo still sees p_old), store p_new, accumulate p.Ap;
 //   update     u = p, x += alpha p at load time, r -= alpha Ap at output
 //              time, accumulate r.r.
-// The final pass recomputes b - A x and the pair energy with the density
-// re-gathered from the orbitals.
+// The final pass recomputes the true residual b - A x (the pair energy is
+// k_pair_energy's).
 
 __device__ __forceinline__ void lds_barrier()
 {

@@ -2,7 +2,7 @@
 //
 // The paper (Sec. III.C, Step IV) starts each pair's CG from a guess (the
 // previous MD step's potential, extrapolated) and points to better guesses
-// as the way to fewer iterations (Sec. VI).  Here a small convolutional
+// as the way to fewer iterations (Sec. IV.B).  Here a small convolutional
 // U-Net maps a pair's right-hand side b, averaged onto a coarse cube around
 // the pair, to the coarse solution; its output is trilinearly interpolated
 // back onto the PE sphere and used as the CG starting point.  CG then runs to

@@ -28,7 +28,7 @@ EXPORTS = ["exx_default_params", "exx_setup", "exx_pairs", "exx_solve", "exx_ene
            "exx_pair_info", "exx_debug_pair", "exx_last_error", "exx_destroy", "exx_model_init", "exx_model_train",
            "exx_model_save", "exx_load_model", "exx_model_edge", "exx_model_conv", "exx_model_wgrad",
            "exx_box_origins", "exx_pair_owners", "exx_pairs_spread",
-           "exx_pair_class"]
+           "exx_pair_class", "exx_stream_rates"]
 
 
 class ExxParams(C.Structure):
@@ -102,12 +102,27 @@ def load() -> C.CDLL:
     L.exx_model_edge.restype = i32
     L.exx_model_conv.argtypes = [vp, i32, i32, vp, vp, i32, i32, vp]
     L.exx_model_wgrad.argtypes = [vp, i32, vp, vp, vp, i32, i32, vp]
+    L.exx_stream_rates.argtypes = [C.c_int, i64, i32, vp, vp, i32]
+    L.exx_stream_rates.restype = C.c_int
     for f in ["exx_setup", "exx_pairs", "exx_solve", "exx_energy_potential", "exx_stats", "exx_pair_info",
               "exx_debug_pair", "exx_model_init", "exx_model_train", "exx_model_save", "exx_load_model",
               "exx_model_conv", "exx_model_wgrad", "exx_box_origins"]:
         getattr(L, f).restype = C.c_int
     _lib = L
     return L
+
+
+def stream_rates(device: int = 0, bytes_per_array: int = 1 << 31, reps: int = 2) -> dict:
+    """Measured streaming rates (GB/s) of plain read / copy / triad / cg-mix
+    kernels on one device (exx_stream_rates)."""
+    L = load()
+    out = np.zeros(4)
+    buf = C.create_string_buffer(512)
+    st = L.exx_stream_rates(int(device), int(bytes_per_array), int(reps), _ptr(out), buf, 512)
+    if st != EXX_OK:
+        raise ExxError(st, "exx_stream_rates failed")
+    return dict(read=float(out[0]), copy=float(out[1]), triad=float(out[2]), cg=float(out[3]),
+                detail=buf.value.decode())
 
 
 def _ptr(a):

@@ -5,6 +5,7 @@ import ctypes as C
 import os
 import re
 import subprocess
+import sys
 import tempfile
 
 import pytest
@@ -177,3 +178,37 @@ def test_setup_without_gpu_reports_device_error():
         pytest.skip("a GPU is present")
     st, msg = _setup_status()
     assert st == X.EXX_EDEVICE and "device" in msg
+
+
+def test_host_allocation_failure_is_a_status():
+    """A host allocation that fails inside the library comes back through the
+    C ABI as EXX_ENOMEM with a message, never as a C++ exception (which would
+    terminate the caller): exx_setup under an address-space limit, asked for
+    a PE sphere of about 8e7 points whose tables cannot fit.  The tables are
+    built before any device call, so this runs without a GPU."""
+    import subprocess
+    code = r"""
+import ctypes as C, resource, sys
+sys.path.insert(0, %r)
+from paper_1911_10630_amd import exx as X
+L = X.load()
+p = X.ExxParams()
+L.exx_default_params(C.byref(p))
+for a in range(3):
+    p.n_grid[a] = 600
+    p.cell[a] = 600.0
+p.r_pair = 1.0
+p.r_pe[0] = p.r_pe[1] = 270.0
+p.r_me[0] = p.r_me[1] = 274.0
+vm = [int(l.split()[1]) for l in open('/proc/self/status') if l.startswith('VmSize')][0] * 1024
+resource.setrlimit(resource.RLIMIT_AS, (vm + (256 << 20), resource.RLIM_INFINITY))
+h = C.c_void_p()
+st = L.exx_setup(C.byref(p), 0, C.byref(h))
+resource.setrlimit(resource.RLIMIT_AS, (resource.RLIM_INFINITY, resource.RLIM_INFINITY))
+print(st)
+print(L.exx_last_error(None).decode())
+""" % ROOT
+    out = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr[-2000:]
+    st, msg = out.stdout.strip().splitlines()[-2:]
+    assert int(st) == X.EXX_ENOMEM and "exx_setup: host allocation failed" in msg, (st, msg)

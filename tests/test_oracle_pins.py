@@ -495,3 +495,79 @@ def test_energy_converges_with_the_subdomain_radius():
     err = [abs(e - E[-1]) for e in E[:-1]]
     assert all(a > b for a, b in zip(err, err[1:])), err
     assert err[0] > 1e-3 * abs(E[-1]) and err[-1] < 1e-7 * abs(E[-1])
+
+
+# ---------------------------------------------------------------------------
+# The explicit-pair-list leg (the benchmark's CPU baseline and the sampled
+# full-size checks run it) and the wrap of the per-pair domain radius
+# ---------------------------------------------------------------------------
+
+def test_solve_pairs_reproduces_the_whole_step_per_pair():
+    """solve_pairs on every pair of the small workload, in shuffled order and
+    with self and non-self pairs on different radii (4 A and 3.4 A), returns
+    exactly the per-pair energy, iterations, flag and residual of the whole
+    step (Steps III-V): the orbital pointer table, the class of each pair
+    and the result order all line up."""
+    wl = S.c1_small()
+    r_pe, r_me = (4.0 * S.ANG, 3.4 * S.ANG), (5.0 * S.ANG, 4.4 * S.ANG)
+    phi = S.orbitals_np(wl)
+    E, _, out = O.exx(wl.n_grid, wl.cell, wl.r_pair, r_pe, r_me, wl.orbitals.centers, phi, want_D=False)
+    perm = np.random.default_rng(7).permutation(len(out["i"]))
+    res = O.solve_pairs(wl.n_grid, wl.cell, r_pe, r_me, wl.orbitals.centers, {k: phi[k] for k in range(len(phi))},
+                        out["i"][perm], out["j"][perm], nthreads=4)
+    for key in ("e", "iters", "converged", "relres"):
+        assert np.array_equal(res[key], out[key][perm]), key
+    assert np.sum(out["i"] == out["j"]) == 16
+
+
+def test_solve_pairs_on_rounded_box_orbitals_matches_each_class():
+    """solve_pairs on FP32-rounded orbitals that live on local boxes (zero
+    outside, as the 512-water workload stores them), given only the orbitals
+    the sampled pairs touch, equals the single-pair pipeline of the class the
+    header names for each pair: [0] for self pairs, [1] for the others."""
+    wl = S.c1_boxed()
+    r_pe, r_me = (4.0 * S.ANG, 3.5 * S.ANG), (5.0 * S.ANG, 4.5 * S.ANG)
+    C = wl.orbitals.centers
+    n, box, h = np.asarray(wl.n_grid), np.asarray(wl.box), np.asarray(wl.h)
+    # box origin: the grid point nearest the centre minus half the box
+    origins = [np.mod(np.floor(np.mod(c, wl.cell[0]) / h + 0.5).astype(int) - box // 2, n) for c in C]
+    pi, pj = O.pair_list(C, wl.cell, wl.r_pair)
+    rng = np.random.default_rng(5)
+    pick = np.concatenate([rng.choice(np.nonzero(pi == pj)[0], 2, replace=False),
+                           rng.choice(np.nonzero(pi != pj)[0], 4, replace=False)])
+    orbs = sorted(set(pi[pick].tolist()) | set(pj[pick].tolist()))
+    vals = S.embed_boxes(S.orbitals_np(wl, orbs, origins=origins), [origins[k] for k in orbs], wl.n_grid)
+    vals = vals.astype(np.float32).astype(np.float64)
+    phis = dict(zip(orbs, vals))
+    assert np.count_nonzero(vals[0]) < vals[0].size            # the boxes leave zeros
+    res = O.solve_pairs(wl.n_grid, wl.cell, r_pe, r_me, C, phis, pi[pick], pj[pick], nthreads=2)
+    subs = [O.Subdomain(wl.n_grid, wl.cell, r_pe[k], r_me[k]) for k in (0, 1)]
+    for t, p in enumerate(pick):
+        i, j = int(pi[p]), int(pj[p])
+        ref = subs[0 if i == j else 1].solve_pair(phis[i], phis[j], O.pair_origin(C[i], C[j], wl.cell, wl.n_grid))
+        assert res["e"][t] == ref["e"] and res["iters"][t] == ref["iters"], (i, j)
+        assert res["relres"][t] == ref["relres"] and res["converged"][t] == ref["converged"]
+
+
+def test_pair_domain_radius_wraps_across_the_boundary():
+    """Worked by hand, L = 10, N = 20 (h = 0.5): C_i = (9.8, 2.5, 2.5) and
+    C_j = (0.3, 2.5, 2.5) are 0.5 apart through the face x = 0.  The
+    midpoint 10.05 wraps to 0.05, so the origin is grid point (0, 5, 5);
+    g - C_i is 0.2 along x only after the minimum-image wrap (-9.8 without
+    it).  With R_i = R_j = 1 the lens ball sits at C_i + 0.25 with radius
+    sqrt(1 - 0.25^2), so the radius is 0.05 + sqrt(0.9375); the self pair of
+    i needs 0.2 + R_i."""
+    cell, n = (10.0, 10.0, 10.0), (20, 20, 20)
+    ci, cj = np.array([9.8, 2.5, 2.5]), np.array([0.3, 2.5, 2.5])
+    g = O.pair_origin(ci, cj, cell, n)
+    assert list(g) == [0, 5, 5]
+    r = O.pair_domain_radius(ci, cj, 1.0, 1.0, g, cell, n, False)
+    assert abs(r - (0.05 + math.sqrt(0.9375))) < 1e-12, r
+    gs = O.pair_origin(ci, ci, cell, n)                              # 19.6 -> 20 -> 0
+    assert list(gs) == [0, 5, 5]
+    rs = O.pair_domain_radius(ci, ci, 1.0, 1.0, gs, cell, n, True)
+    assert abs(rs - 1.2) < 1e-12, rs
+    # the same pair seen from j: the lens centre is C_j - 0.25, the origin
+    # the same grid point, 0.3 - 0.25 = 0.05 from it
+    r2 = O.pair_domain_radius(cj, ci, 1.0, 1.0, g, cell, n, False)
+    assert abs(r2 - r) < 1e-12
