@@ -68,9 +68,12 @@ enum { EXX_GUESS_ZERO = 0, EXX_GUESS_PREVIOUS = 1, EXX_GUESS_EXTRAP = 2, EXX_GUE
  * EXX_PRECOND_MG: a symmetric multigrid V-cycle (one damped Jacobi step of
  * the 6th-order operator on the PE sphere before and after; 7-point
  * Laplacians on masked coarse boxes of spacing 2^l h with damped Jacobi
- * smoothing; piecewise-constant transfers); FP64 only.  The stopping rule
- * ||b - A x|| <= cg_rtol ||b|| is unchanged, so results agree with the plain
- * iteration to the CG tolerance. */
+ * smoothing; piecewise-constant transfers).  With EXX_FP64 the residual and
+ * the iterate are FP64; with EXX_FP32_REFINE the whole iteration runs in
+ * FP32 except the iterate, and the true FP64 residual b - A x replaces the
+ * recursive one each time the latter has fallen by 1e3 (inner_rtol is not
+ * used).  The stopping rule ||b - A x|| <= cg_rtol ||b|| is unchanged, so
+ * results agree with the plain iteration to the CG tolerance. */
 enum { EXX_PRECOND_NONE = 0, EXX_PRECOND_MG = 1 };
 
 typedef struct {
@@ -159,6 +162,9 @@ typedef struct {
     int64_t class_pairs[4];  /* pairs per class in the current list            */
     int64_t class_capped;    /* pairs whose Omega_ij the largest class does not
                                 cover (exx_pairs_spread; they use that class)  */
+    int32_t cg_inflight[2];  /* planes of loads in flight in the CG kernel's
+                                FP64 / FP32 passes (1 or 2)                    */
+    int32_t cg_cols32;       /* columns per thread of the FP32 passes          */
 } exx_stats_t;
 
 /* Fills *p with the paper's method defaults (n = 3, l_max = 6, FP64, zero

@@ -24,6 +24,7 @@ constexpr double kFD[4] = {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0};
 // messages live in fixed buffers so that reporting a failure never allocates
 char g_setup_error[512] = "no error";
 
+
 // Fortran NINT: nearest integer, halves away from zero.
 long nint_away(double v) { return (long)(v >= 0.0 ? std::floor(v + 0.5) : -std::floor(-v + 0.5)); }
 int mod_pos(long a, int n) { long r = a % n; return (int)(r < 0 ? r + n : r); }
@@ -51,7 +52,8 @@ struct HostClass {
     long long mg_off[MG_MAX] = {};
     long long mg_doubles = 0;   // f, e, t of every level, the dense box and its sink
     long long mg_dense_off = 0;
-    int64_t mg_cells_bytes = 0; // algorithmic bytes of one V-cycle
+    int64_t mg_cells_bytes = 0; // algorithmic bytes of one V-cycle (FP64 coarse values)
+    int64_t mg_cells_bytes32 = 0; // the same with FP32 coarse values
 };
 
 template <typename T>
@@ -138,7 +140,7 @@ struct exx_ctx {
     int graph_builds = 0, graph_launches = 0;
     double tune_ms = 0.0;    // time of the timed tuning launches
     bool tune_on_pairs = false;   // variant to be timed on the first per-pair class mix
-    CgVariant var{0, 256, 0, 0, 0, 0, 0};
+    CgVariant var{0, 256, 0, 0, 0, 0, 0, 1, 1, 0x1f};
     size_t lds_bytes = 0;
     long long slot_n = 0;
     const void *phi = nullptr;
@@ -447,6 +449,7 @@ exx_status build_mg_levels(exx_ctx *c, HostClass &k)
     k.mg_levels = 0;
     k.mg_doubles = 0;
     k.mg_cells_bytes = 0;
+    k.mg_cells_bytes32 = 0;
     while (k.mg_levels < MG_MAX) {
         const int l = k.mg_levels;
         int m[3];
@@ -480,8 +483,12 @@ exx_status build_mg_levels(exx_ctx *c, HostClass &k)
         // of the dense box, child bits, f) and the correction its POST pass
         // gathers; per level the down pass (f, bits) and the up pass (f, the
         // coarser e, bits, e)
-        if (l == 0) k.mg_cells_bytes += in * (32 + 1 + 8 + 8);
+        if (l == 0) {
+            k.mg_cells_bytes += in * (32 + 1 + 8 + 8);
+            k.mg_cells_bytes32 += in * (32 + 1 + 4 + 4);
+        }
         k.mg_cells_bytes += in * (8 + 1 + 8 + 8 + 1 + 8);
+        k.mg_cells_bytes32 += in * (4 + 1 + 4 + 4 + 1 + 4);
         if (k.d_mg_mask[l]) { (void)hipFree(k.d_mg_mask[l]); k.d_mg_mask[l] = nullptr; }
         HIPCHK(c, hipMalloc((void **)&k.d_mg_mask[l], cm.size()));
         HIPCHK(c, hipMemcpy(k.d_mg_mask[l], cm.data(), cm.size(), hipMemcpyHostToDevice));
@@ -919,7 +926,7 @@ exx_status select_variant(exx_ctx *c, const int64_t *mix = nullptr)
     for (int i = 0; i < nv; ++i) {
         const CgVariant &v = vs[i];
         if (c->prm.cg_cols < 0) { if (!v.zmarch) { flat = true; break; } continue; }
-        if (!v.zmarch) continue;
+        if (!v.zmarch || !cg_variant_applies(v, mode)) continue;
         if (c->prm.block_threads && v.block != c->prm.block_threads) continue;
         if (c->prm.cg_cols && v.cols != c->prm.cg_cols) continue;
         bool fits = true;
@@ -1013,8 +1020,6 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         return fail(nullptr, EXX_EINVAL, "unknown guess %d", p->guess);
     if (p->precond != EXX_PRECOND_NONE && p->precond != EXX_PRECOND_MG)
         return fail(nullptr, EXX_EINVAL, "unknown precond %d", p->precond);
-    if (p->precond == EXX_PRECOND_MG && p->precision != EXX_FP64)
-        return fail(nullptr, EXX_EINVAL, "precond = EXX_PRECOND_MG runs in FP64 (precision = EXX_FP64)");
     for (int a = 0; a < 3; ++a)
         if (p->box_dims[a] < 0 || p->box_dims[a] > p->n_grid[a])
             return fail(nullptr, EXX_EINVAL, "box_dims[%d] = %d outside [0, n_grid]", a, p->box_dims[a]);
@@ -1752,6 +1757,9 @@ static exx_status exx_stats_body(exx_ctx *c, exx_stats_t *st)
     st->solve_grid = c->grid;
     st->solve_block = c->block;
     st->cg_cols = c->var.zmarch ? c->var.cols : 0;
+    st->cg_inflight[0] = c->var.pf64;
+    st->cg_inflight[1] = c->var.pf32;
+    st->cg_cols32 = c->var.zmarch ? c->var.cols32 : 0;
     st->cg_bands[0] = (int)c->cls[0].bands.size() / 12;
     st->cg_bands[1] = (int)c->cls[1].bands.size() / 12;
     for (int k = 0; k < 2; ++k) {
@@ -1793,14 +1801,32 @@ static exx_status exx_stats_body(exx_ctx *c, exx_stats_t *st)
         // closing residual pass (x, b in); the pair energy reads x and the
         // two orbitals, the preparation the two orbitals (and writes b and
         // the shell potential)
-        // With the multigrid preconditioner an iteration moves 80 B per
+        // With the multigrid preconditioner an iteration moves 72 B per
         // unknown (r, x FP64; the dense residual, z, p FP32): smoothing
-        // passes 12 (r in, the dense residual out) and 20 (r twice in, z
-        // out), direction 12 (z, p in, p out), update 36 (p, x, r in, x, r
-        // out; the kernel pairs the iterate updates and moves 30 on average);
-        // plus the V-cycle's bytes per coarse cell in the domain.
-        const int64_t per_it = mg ? (int64_t)k.n_pe * 80 + k.mg_cells_bytes : (int64_t)k.n_pe * 8 * scg;
-        const int64_t cg = (int64_t)it[p] * per_it + (int64_t)k.n_pe * ((int64_t)ou[p] * 32 + 16);
+        // passes 12 (r in, the dense residual out) and 12 (r in, z out; r at
+        // the output plane is recovered from the cached coarse correction),
+        // direction 12 (z, p in, p out), update 36 (p, x, r in, x, r out; the
+        // kernel pairs the iterate updates and moves 30 on average); plus the
+        // V-cycle's bytes per coarse cell in the domain.
+        // In FP32 (FP32_REFINE) the preconditioned iteration moves 50 B per
+        // unknown: smoothing passes 8 (r in, the dense residual out) and 8
+        // (r in, z out; r at the output plane is kept in registers),
+        // direction 12, update 22 (p, r in, r out FP32; x FP64 every other
+        // iteration; the previous p every other); the V-cycle in FP32; each
+        // residual replacement 20 (x, b in, r out) and the owed step it folds
+        // into x first 20 (x in and out, p in), counted on every replacement.
+        int64_t per_it, per_outer;
+        if (mg && scg == 4) {
+            per_it = (int64_t)k.n_pe * 50 + k.mg_cells_bytes32;
+            per_outer = 40;
+        } else if (mg) {
+            per_it = (int64_t)k.n_pe * 72 + k.mg_cells_bytes;
+            per_outer = 32;
+        } else {
+            per_it = (int64_t)k.n_pe * 8 * scg;
+            per_outer = 32;
+        }
+        const int64_t cg = (int64_t)it[p] * per_it + (int64_t)k.n_pe * ((int64_t)ou[p] * per_outer + 16);
         st->cg_bytes += cg;
         st->solve_bytes += cg + (int64_t)k.n_pe * (2 * sphi + 8) + (int64_t)k.n_sh * 8 + (int64_t)k.n_pe * (8 + 2 * sphi);
         const int m = c->ij[p].x == c->ij[p].y ? 1 : 2;

@@ -241,10 +241,16 @@ struct CgVariant {
     int cols32;   // FP32 columns per thread (refinement passes)
     int halo32;   // FP32 halo columns per thread
     int wpe;      // minimum resident waves per SIMD the kernel is compiled for
+    int pf64;     // planes of loads in flight in the FP64 passes (1 or 2)
+    int pf32;     // planes of loads in flight in the FP32 passes (1 or 2)
+    int modes;    // bit mask of the kernel modes it is built for
 };
 int cg_variants(CgVariant *out, int max_n);
+// Whether a variant is built for a mode.
+bool cg_variant_applies(const CgVariant &v, int mode);
 // Kernel mode for a precision (EXX_FP64 / EXX_FP32_REFINE), whether CG
-// starts from a guess in vout, and the multigrid preconditioner.
+// starts from a guess in vout, and the multigrid preconditioner (in FP64, or
+// in FP32 with FP64 residual replacement under EXX_FP32_REFINE).
 int cg_mode(int precision, int guess, int mg);
 hipError_t cg_occupancy(const CgVariant &v, int mode, size_t lds_bytes, int *blocks_per_cu);
 hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t lds_bytes, hipStream_t s);

@@ -407,10 +407,17 @@ __device__ __forceinline__ T *sel_ptr(T *p, int a, T *sink)
     return a >= 0 ? p + a : sink;
 }
 
+// Planes of loads in flight.  A policy holds its loaded values in kSlots
+// slots: with one slot the loads of the plane the next step consumes are
+// issued one step ahead; with two, two steps ahead (the z loop is unrolled
+// by two so each slot index is a constant), which hides twice the memory
+// latency at the register cost of a second copy of the loaded values.
 template <typename R, int T, int K, int KH, class P>
 __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, double *lds, int &par, P &pol,
                                             const StencilW<R> &w, const int4 &pg, int nx, int ny, int nz)
 {
+    constexpr int PF = P::kSlots;
+    static_assert(PF == 1 || PF == 2, "one or two planes of loads in flight");
     const int tid = threadIdx.x;
     constexpr bool F32 = sizeof(R) == 4;
     const int *bd = (F32 ? g.bands32 : g.bands) + 12 * bi;
@@ -455,48 +462,51 @@ __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, double *l
         hlo[j] = (y - ya + 3) * W + (x - g.pxlo + 3);
     }
     // packed index of a column at plane z, or -1 (branch-free)
-    auto addr = [&](int z, int xr, int zr) -> int {
+    auto addr = [&](int z, int xr, int zr) __attribute__((always_inline)) -> int {
         const int zl = (zr & 0xffff) - 512, zh = (zr >> 16) - 512;
         const int zc = min(max(z, g.pzlo), g.pzlo + g.pnz - 1);
         const int idx = tbl[(zc - g.pzlo) * g.pny + (xr >> 16)] + (xr & 0xffff) - 512;
         return (unsigned)(z - zl) <= (unsigned)(zh - zl) ? idx : -1;
     };
-    auto fetch_own = [&](int zl) {
+    // slot arguments are std::integral_constant, so every index into the
+    // policy's arrays is a constant and they stay in registers
+    auto fetch_own = [&](auto sc, int zl) __attribute__((always_inline)) {
+        constexpr int s = decltype(sc)::value;
         int ad[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) ad[k] = addr(zl, cxr[k], czr[k]);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if constexpr (wants_xyz<P>::value)
-                pol.fetch_own_at(k, ad[k], (cxr[k] & 0xffff) - 512, g.pylo + (cxr[k] >> 16), zl);
+                pol.fetch_own_at(s, k, ad[k], (cxr[k] & 0xffff) - 512, g.pylo + (cxr[k] >> 16), zl);
             else
-                pol.fetch_own(k, ad[k]);
+                pol.fetch_own(s, k, ad[k]);
         }
     };
-    auto fetch_halo = [&](int z) {
+    auto fetch_halo = [&](auto sc, int z) __attribute__((always_inline)) {
+        constexpr int s = decltype(sc)::value;
         int ad[KH];
 #pragma unroll
         for (int j = 0; j < KH; ++j) ad[j] = addr(z, hxr[j], hzr[j]);
 #pragma unroll
         for (int j = 0; j < KH; ++j) {
             if constexpr (wants_xyz<P>::value)
-                pol.fetch_halo_at(j, ad[j], (hxr[j] & 0xffff) - 512, g.pylo + (hxr[j] >> 16), z);
+                pol.fetch_halo_at(s, j, ad[j], (hxr[j] & 0xffff) - 512, g.pylo + (hxr[j] >> 16), z);
             else
-                pol.fetch_halo(j, ad[j]);
+                pol.fetch_halo(s, j, ad[j]);
         }
     };
-    auto fetch_out = [&](int z) {
-        const int gz = wrap_n(pg.z + z, nz);
+    auto fetch_out = [&](auto sc, int z) __attribute__((always_inline)) {
+        constexpr int s = decltype(sc)::value;
         int ad[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) ad[k] = addr(z, cxr[k], czr[k]);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             if constexpr (wants_xyz<P>::value)
-                pol.fetch_out_at(k, ad[k], (cxr[k] & 0xffff) - 512, g.pylo + (cxr[k] >> 16), z);
+                pol.fetch_out_at(s, k, ad[k], (cxr[k] & 0xffff) - 512, g.pylo + (cxr[k] >> 16), z);
             else
-                pol.fetch_out(k, ad[k], wrap_n(pg.x + (cxr[k] & 0xffff) - 512, nx),
-                              wrap_n(pg.y + g.pylo + (cxr[k] >> 16), ny), gz);
+                pol.fetch_out(s, k, ad[k]);
         }
     };
 
@@ -505,30 +515,45 @@ __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, double *l
     for (int k = 0; k < K; ++k)
 #pragma unroll
         for (int j = 0; j < 7; ++j) q[k][j] = (R)0;
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
 #pragma unroll
     for (int j = 0; j < 3; ++j) {
-        fetch_own(zlo + j);
+        fetch_own(S0{}, zlo + j);
 #pragma unroll
-        for (int k = 0; k < K; ++k) q[k][4 + j] = pol.fin_own(k);
+        for (int k = 0; k < K; ++k) q[k][4 + j] = pol.fin_own(0, k);
     }
-    fetch_own(zlo + 3);
-    fetch_halo(zlo);
-    fetch_out(zlo);
-    for (int zo = zlo; zo <= zhi; ++zo) {
+    // in flight: own planes zlo+3 .. zlo+2+PF, halo and output planes zlo .. zlo+PF-1
+    fetch_own(S0{}, zlo + 3);
+    fetch_halo(S0{}, zlo);
+    fetch_out(S0{}, zlo);
+    if constexpr (PF == 2) {
+        fetch_own(S1{}, zlo + 4);
+        fetch_halo(S1{}, zlo + 1);
+        fetch_out(S1{}, zlo + 1);
+    }
+    // one output plane zo, from slot s (a constant after unrolling)
+    auto step = [&](auto slot, int zo) __attribute__((always_inline)) {
+        constexpr int s = decltype(slot)::value;
         R un[K], uh[KH];
 #pragma unroll
-        for (int k = 0; k < K; ++k) un[k] = pol.fin_own(k);
+        for (int k = 0; k < K; ++k) un[k] = pol.fin_own(s, k);
 #pragma unroll
-        for (int j = 0; j < KH; ++j) uh[j] = pol.fin_halo(j);
-        fetch_own(zo + 4);
-        fetch_halo(zo + 1);
+        for (int j = 0; j < KH; ++j) uh[j] = pol.fin_halo(s, j);
+        fetch_own(slot, zo + 3 + PF);
+        fetch_halo(slot, zo + PF);
 #pragma unroll
         for (int k = 0; k < K; ++k) {
 #pragma unroll
             for (int j = 0; j < 6; ++j) q[k][j] = q[k][j + 1];
             q[k][6] = un[k];
         }
-        R *buf = planes + (par & 1) * plane;
+        // the plane buffer alternates every step; the empty asm keeps the
+        // compiler from precomputing each column's stencil addresses into
+        // both buffers ahead of the loop (registers it does not have)
+        int boff = (par & 1) * plane;
+        asm volatile("" : "+v"(boff));
+        R *buf = planes + boff;
         ++par;
 #pragma unroll
         for (int k = 0; k < K; ++k) *(cok[k] ? buf + clo[k] : lsink) = q[k][3];
@@ -538,13 +563,23 @@ __device__ __forceinline__ void zmarch_band(const ClassDev &g, int bi, double *l
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const R *c = buf + clo[k];
-            R s = w.c * q[k][3];
-            s += w.z[1] * (q[k][2] + q[k][4]) + w.z[2] * (q[k][1] + q[k][5]) + w.z[3] * (q[k][0] + q[k][6]);
-            s += w.x[1] * (c[-1] + c[1]) + w.x[2] * (c[-2] + c[2]) + w.x[3] * (c[-3] + c[3]);
-            s += w.y[1] * (c[-W] + c[W]) + w.y[2] * (c[-2 * W] + c[2 * W]) + w.y[3] * (c[-3 * W] + c[3 * W]);
-            pol.output(k, q[k][3], -s);
+            R sm = w.c * q[k][3];
+            sm += w.z[1] * (q[k][2] + q[k][4]) + w.z[2] * (q[k][1] + q[k][5]) + w.z[3] * (q[k][0] + q[k][6]);
+            sm += w.x[1] * (c[-1] + c[1]) + w.x[2] * (c[-2] + c[2]) + w.x[3] * (c[-3] + c[3]);
+            sm += w.y[1] * (c[-W] + c[W]) + w.y[2] * (c[-2 * W] + c[2 * W]) + w.y[3] * (c[-3 * W] + c[3 * W]);
+            pol.output(s, k, q[k][3], -sm);
         }
-        fetch_out(zo + 1);
+        fetch_out(slot, zo + PF);
+    };
+    if constexpr (PF == 1) {
+        for (int zo = zlo; zo <= zhi; ++zo) step(S0{}, zo);
+    } else {
+        int zo = zlo;
+        for (; zo + 1 <= zhi; zo += 2) {
+            step(S0{}, zo);
+            step(S1{}, zo + 1);
+        }
+        if (zo <= zhi) step(S0{}, zo);
     }
 }
 
@@ -557,41 +592,42 @@ __device__ __forceinline__ void zmarch(const ClassDev &g, double *lds, int &par,
 }
 
 // direction pass: u = r + beta p_old, p_new <- u; sum p.Ap (and b.b when r is b)
-template <typename R, int K, int KH>
+template <typename R, int K, int KH, int S = 1>
 struct PDir {
+    static constexpr int kSlots = S;
     const R *rsrc, *pold;
     R *pnew, *sink;
     R beta;
     bool load_p, acc_bb;
     double pap = 0.0, bb = 0.0;
-    R fr[K], fp[K];
-    int fa[K];
-    R hr[KH], hp[KH];
-    int ha[KH];
-    __device__ __forceinline__ void fetch_own(int k, int a)
+    R fr[S][K], fp[S][K];
+    int fa[S][K];
+    R hr[S][KH], hp[S][KH];
+    int ha[S][KH];
+    __device__ __forceinline__ void fetch_own(int s, int k, int a)
     {
-        fa[k] = a;
-        fr[k] = raw_load(rsrc, a);
-        fp[k] = load_p ? raw_load(pold, a) : (R)0;
+        fa[s][k] = a;
+        fr[s][k] = raw_load(rsrc, a);
+        fp[s][k] = load_p ? raw_load(pold, a) : (R)0;
     }
-    __device__ __forceinline__ R fin_own(int k)
+    __device__ __forceinline__ R fin_own(int s, int k)
     {
-        const bool ok = fa[k] >= 0;
-        const R r = ok ? fr[k] : (R)0;
-        const R u = ok ? fr[k] + beta * fp[k] : (R)0;
-        *sel_ptr(pnew, fa[k], sink) = u;
+        const bool ok = fa[s][k] >= 0;
+        const R r = ok ? fr[s][k] : (R)0;
+        const R u = ok ? fr[s][k] + beta * fp[s][k] : (R)0;
+        *sel_ptr(pnew, fa[s][k], sink) = u;
         if (acc_bb) bb += (double)r * (double)r;
         return u;
     }
-    __device__ __forceinline__ void fetch_halo(int j, int a)
+    __device__ __forceinline__ void fetch_halo(int s, int j, int a)
     {
-        ha[j] = a;
-        hr[j] = raw_load(rsrc, a);
-        hp[j] = load_p ? raw_load(pold, a) : (R)0;
+        ha[s][j] = a;
+        hr[s][j] = raw_load(rsrc, a);
+        hp[s][j] = load_p ? raw_load(pold, a) : (R)0;
     }
-    __device__ __forceinline__ R fin_halo(int j) { return ha[j] >= 0 ? hr[j] + beta * hp[j] : (R)0; }
-    __device__ __forceinline__ void fetch_out(int, int, int, int, int) {}
-    __device__ __forceinline__ void output(int, R u, R Au) { pap += (double)u * (double)Au; }
+    __device__ __forceinline__ R fin_halo(int s, int j) { return ha[s][j] >= 0 ? hr[s][j] + beta * hp[s][j] : (R)0; }
+    __device__ __forceinline__ void fetch_out(int, int, int) {}
+    __device__ __forceinline__ void output(int, int, R u, R Au) { pap += (double)u * (double)Au; }
 };
 
 // update pass: u = p, r = rsrc - alpha Ap (output time), sum r.r; and the
@@ -602,8 +638,9 @@ struct PDir {
 // Pairing the iterate updates reads and writes x every other iteration:
 // 7.5 vector passes per CG iteration instead of 8.
 enum { XM_STEP = 0, XM_SKIP = 1, XM_PAIR = 2 };
-template <typename R, int K, int KH, int XM = XM_STEP>
+template <typename R, int K, int KH, int XM = XM_STEP, int S = 1>
 struct PUpd {
+    static constexpr int kSlots = S;
     const R *p, *rsrc;
     R *x, *r, *sink;
     R alpha;
@@ -611,127 +648,136 @@ struct PUpd {
     const R *q = nullptr;       // XM_PAIR: the previous direction
     R alpha2 = (R)0;
     double rr = 0.0;
-    R fp[K], fx[K], fq[K];
-    int fa[K];
-    R hp[KH];
-    int ha[KH];
-    R orr[K];
-    int oa[K];
-    __device__ __forceinline__ void fetch_own(int k, int a)
+    R fp[S][K], fx[S][K], fq[S][K];
+    int fa[S][K];
+    R hp[S][KH];
+    int ha[S][KH];
+    R orr[S][K];
+    int oa[S][K];
+    __device__ __forceinline__ void fetch_own(int s, int k, int a)
     {
-        fa[k] = a;
-        fp[k] = raw_load(p, a);
-        if constexpr (XM != XM_SKIP) fx[k] = load_x ? raw_load(x, a) : (R)0;
-        if constexpr (XM == XM_PAIR) fq[k] = raw_load(q, a);
+        fa[s][k] = a;
+        fp[s][k] = raw_load(p, a);
+        if constexpr (XM != XM_SKIP) fx[s][k] = load_x ? raw_load(x, a) : (R)0;
+        if constexpr (XM == XM_PAIR) fq[s][k] = raw_load(q, a);
     }
-    __device__ __forceinline__ R fin_own(int k)
+    __device__ __forceinline__ R fin_own(int s, int k)
     {
-        const R pv = fa[k] >= 0 ? fp[k] : (R)0;
-        if constexpr (XM == XM_STEP) *sel_ptr(x, fa[k], sink) = fx[k] + alpha * pv;
-        if constexpr (XM == XM_PAIR) *sel_ptr(x, fa[k], sink) = fx[k] + alpha2 * fq[k] + alpha * pv;
+        const R pv = fa[s][k] >= 0 ? fp[s][k] : (R)0;
+        if constexpr (XM == XM_STEP) *sel_ptr(x, fa[s][k], sink) = fx[s][k] + alpha * pv;
+        if constexpr (XM == XM_PAIR) *sel_ptr(x, fa[s][k], sink) = fx[s][k] + alpha2 * fq[s][k] + alpha * pv;
         return pv;
     }
-    __device__ __forceinline__ void fetch_halo(int j, int a)
+    __device__ __forceinline__ void fetch_halo(int s, int j, int a)
     {
-        ha[j] = a;
-        hp[j] = raw_load(p, a);
+        ha[s][j] = a;
+        hp[s][j] = raw_load(p, a);
     }
-    __device__ __forceinline__ R fin_halo(int j) { return ha[j] >= 0 ? hp[j] : (R)0; }
-    __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
+    __device__ __forceinline__ R fin_halo(int s, int j) { return ha[s][j] >= 0 ? hp[s][j] : (R)0; }
+    __device__ __forceinline__ void fetch_out(int s, int k, int a)
     {
-        oa[k] = a;
-        orr[k] = raw_load(rsrc, a);
+        oa[s][k] = a;
+        orr[s][k] = raw_load(rsrc, a);
     }
-    __device__ __forceinline__ void output(int k, R, R Au)
+    __device__ __forceinline__ void output(int s, int k, R, R Au)
     {
-        const R t = oa[k] >= 0 ? orr[k] - alpha * Au : (R)0;
-        *sel_ptr(r, oa[k], sink) = t;
+        const R t = oa[s][k] >= 0 ? orr[s][k] - alpha * Au : (R)0;
+        *sel_ptr(r, oa[s][k], sink) = t;
         rr += (double)t * (double)t;
     }
 };
 
-// FP64 residual pass: u = x (+ d), r = b - A u; sums r.r and b.b; the
-// residual is stored in RT (double, or float for refinement).  x is not
-// written here (a later band's halo still needs the old x); the caller adds
-// d to x afterwards.
-template <int K, int KH, typename DT, typename RT>
+// FP64 residual pass: u = x (+ dscale d), r = b - A u; sums r.r and b.b
+// (unscaled); the residual is stored times oscale in RT (double, or float
+// for the FP32 iterations).  x is not written here (a later band's halo
+// still needs the old x); the caller adds d to x afterwards.
+template <int K, int KH, typename DT, typename RT, int S = 1>
 struct PRes {
+    static constexpr int kSlots = S;
     const double *x;
     const DT *d;
     const double *b;
     RT *r, *sink;
     bool add_d;
     double dscale;              // u = x + dscale * d
+    double oscale = 1.0;        // stored residual = oscale (b - A u)
     double rr = 0.0, bb = 0.0;
-    double fx[K];
-    DT fd[K];
-    int fa[K];
-    double hx[KH];
-    DT hd[KH];
-    int ha[KH];
-    double ob[K];
-    int oa[K];
-    __device__ __forceinline__ void fetch_own(int k, int a)
+    double fx[S][K];
+    DT fd[S][K];
+    int fa[S][K];
+    double hx[S][KH];
+    DT hd[S][KH];
+    int ha[S][KH];
+    double ob[S][K];
+    int oa[S][K];
+    __device__ __forceinline__ void fetch_own(int s, int k, int a)
     {
-        fa[k] = a;
-        fx[k] = raw_load(x, a);
-        fd[k] = add_d ? raw_load(d, a) : (DT)0;
+        fa[s][k] = a;
+        fx[s][k] = raw_load(x, a);
+        fd[s][k] = add_d ? raw_load(d, a) : (DT)0;
     }
-    __device__ __forceinline__ double fin_own(int k) { return fa[k] >= 0 ? fx[k] + dscale * (double)fd[k] : 0.0; }
-    __device__ __forceinline__ void fetch_halo(int j, int a)
+    __device__ __forceinline__ double fin_own(int s, int k)
     {
-        ha[j] = a;
-        hx[j] = raw_load(x, a);
-        hd[j] = add_d ? raw_load(d, a) : (DT)0;
+        return fa[s][k] >= 0 ? fx[s][k] + dscale * (double)fd[s][k] : 0.0;
     }
-    __device__ __forceinline__ double fin_halo(int j) { return ha[j] >= 0 ? hx[j] + dscale * (double)hd[j] : 0.0; }
-    __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
+    __device__ __forceinline__ void fetch_halo(int s, int j, int a)
     {
-        oa[k] = a;
-        ob[k] = raw_load(b, a);
+        ha[s][j] = a;
+        hx[s][j] = raw_load(x, a);
+        hd[s][j] = add_d ? raw_load(d, a) : (DT)0;
     }
-    __device__ __forceinline__ void output(int k, double, double Au)
+    __device__ __forceinline__ double fin_halo(int s, int j)
     {
-        const bool ok = oa[k] >= 0;
-        const double bv = ok ? ob[k] : 0.0;
+        return ha[s][j] >= 0 ? hx[s][j] + dscale * (double)hd[s][j] : 0.0;
+    }
+    __device__ __forceinline__ void fetch_out(int s, int k, int a)
+    {
+        oa[s][k] = a;
+        ob[s][k] = raw_load(b, a);
+    }
+    __device__ __forceinline__ void output(int s, int k, double, double Au)
+    {
+        const bool ok = oa[s][k] >= 0;
+        const double bv = ok ? ob[s][k] : 0.0;
         const double t = ok ? bv - Au : 0.0;
-        *sel_ptr(r, oa[k], sink) = (RT)t;
+        *sel_ptr(r, oa[s][k], sink) = (RT)(t * oscale);
         rr += t * t;
         bb += bv * bv;
     }
 };
 
 // final pass: true residual b - A x
-template <int K, int KH>
+template <int K, int KH, int S = 1>
 struct PFin {
+    static constexpr int kSlots = S;
     const double *x, *b;
     double res = 0.0;
-    double fx[K];
-    int fa[K];
-    double hx[KH];
-    int ha[KH];
-    double ob[K];
-    int oa[K];
-    __device__ __forceinline__ void fetch_own(int k, int a)
+    double fx[S][K];
+    int fa[S][K];
+    double hx[S][KH];
+    int ha[S][KH];
+    double ob[S][K];
+    int oa[S][K];
+    __device__ __forceinline__ void fetch_own(int s, int k, int a)
     {
-        fa[k] = a;
-        fx[k] = raw_load(x, a);
+        fa[s][k] = a;
+        fx[s][k] = raw_load(x, a);
     }
-    __device__ __forceinline__ double fin_own(int k) { return fa[k] >= 0 ? fx[k] : 0.0; }
-    __device__ __forceinline__ void fetch_halo(int j, int a)
+    __device__ __forceinline__ double fin_own(int s, int k) { return fa[s][k] >= 0 ? fx[s][k] : 0.0; }
+    __device__ __forceinline__ void fetch_halo(int s, int j, int a)
     {
-        ha[j] = a;
-        hx[j] = raw_load(x, a);
+        ha[s][j] = a;
+        hx[s][j] = raw_load(x, a);
     }
-    __device__ __forceinline__ double fin_halo(int j) { return ha[j] >= 0 ? hx[j] : 0.0; }
-    __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
+    __device__ __forceinline__ double fin_halo(int s, int j) { return ha[s][j] >= 0 ? hx[s][j] : 0.0; }
+    __device__ __forceinline__ void fetch_out(int s, int k, int a)
     {
-        oa[k] = a;
-        ob[k] = raw_load(b, a);
+        oa[s][k] = a;
+        ob[s][k] = raw_load(b, a);
     }
-    __device__ __forceinline__ void output(int k, double, double Au)
+    __device__ __forceinline__ void output(int s, int k, double, double Au)
     {
-        const double t = oa[k] >= 0 ? ob[k] - Au : 0.0;
+        const double t = oa[s][k] >= 0 ? ob[s][k] - Au : 0.0;
         res += t * t;
     }
 };
@@ -750,13 +796,17 @@ struct PFin {
 // Jacobi sweep before and after each coarsening, several on the coarsest
 // box.  Every part is symmetric, so M is too and plain PCG applies.
 
-// Storage of the preconditioned iteration: r and x in FP64; the dense
+// Storage of the FP64 preconditioned iteration: r and x in FP64; the dense
 // residual, z and the directions p in FP32, scaled by a power of two sigma
 // (the RMS of the residual rounded down to 2^k, so scaling is exact and the
 // values stay inside the FP32 range as the residual falls).  p is rounded
 // before the direction pass applies A, and the update pass recomputes Ap from
 // the stored p, so x and r stay consistent in FP64; the rounding of z and p
 // only perturbs M, like an inexact preconditioner.
+// The FP32 form (FP32_REFINE) keeps r in FP32 too, scaled, and computes the
+// fine passes and the V-cycle in FP32; x stays FP64 and the residual is
+// replaced by the true FP64 b - A x whenever the recursive one has fallen by
+// a fixed factor, so rounding never accumulates into the result.
 __device__ __forceinline__ double pow2_scale(double rr, double n)
 {
     int e;
@@ -764,74 +814,92 @@ __device__ __forceinline__ double pow2_scale(double rr, double n)
     return ldexp(1.0, e - 1);
 }
 
-// fine passes on the z-march (each takes each point's offsets):
+// fine passes on the z-march (each takes each point's offsets), in the
+// arithmetic R of the iteration (double, or float for the FP32 form):
 //   MG_PRE:  t = r - c A r on PE, stored / sigma in the dense, even-padded
 //            PE box (the residual left by the smoothing step S r)
 //   MG_POST: u = c r + e_1(cell of the point) (S r plus the prolonged coarse
 //            correction), z = u + c (r - A u) on PE stored / sigma,
-//            rho += r . z (of the stored z)
+//            rho += r . z (of the stored z).  r at the output plane is not
+//            read again: in FP64 it is recovered as (u - e_1) / c from the
+//            cell's correction (cached), in FP32 kept in a four-plane
+//            register queue (the recovery would cancel digits FP32 lacks).
 enum { MG_PRE = 0, MG_POST = 1 };
-template <int K, int KH, int MODE>
+template <typename R, int K, int KH, int MODE, int S = 1>
 struct PMg {
+    static constexpr int kSlots = S;
     static constexpr bool kXYZ = true;
-    const double *r;                    // the vector M is applied to
-    const double *e1;                   // level-1 correction (MG_POST)
+    static constexpr bool kQueue = sizeof(R) == 4 && MODE == MG_POST;
+    const R *r;                         // the vector M is applied to
+    const R *e1;                        // level-1 correction (MG_POST)
     float *out, *sink;                  // MG_PRE: dense box; MG_POST: z (packed)
     double c, sigma, inv_sigma;
     int pxlo, pylo, pzlo;
     int dnx, dnxy;                      // dense box pitches (MG_PRE)
     int nx1, nxy1;                      // level-1 pitches (MG_POST)
     double rho = 0.0;
-    double fr[K], fe[K];
-    int fa[K];
-    double hr[KH], he[KH];
-    int ha[KH];
-    double ob[K];
-    int oa[K];
+    R fr[S][K], fe[S][K];
+    int fa[S][K];
+    R hr[S][KH], he[S][KH];
+    int ha[S][KH];
+    R oe[S][K];                         // MG_POST, FP64: e_1 at the output point
+    int oa[S][K];
+    R rq[K][4];                         // MG_POST, FP32: r at the planes zo .. zo+3
     __device__ __forceinline__ int cell(int a, int x, int y, int z) const
     {
         return a >= 0 ? ((z - pzlo) >> 1) * nxy1 + ((y - pylo) >> 1) * nx1 + ((x - pxlo) >> 1) : 0;
     }
-    __device__ __forceinline__ void fetch_own_at(int k, int a, int x, int y, int z)
+    __device__ __forceinline__ void fetch_own_at(int s, int k, int a, int x, int y, int z)
     {
-        fa[k] = a;
-        fr[k] = raw_load(r, a);
-        if constexpr (MODE == MG_POST) fe[k] = e1[cell(a, x, y, z)];
+        fa[s][k] = a;
+        fr[s][k] = raw_load(r, a);
+        if constexpr (MODE == MG_POST) fe[s][k] = e1[cell(a, x, y, z)];
     }
-    __device__ __forceinline__ double fin_own(int k)
+    __device__ __forceinline__ R fin_own(int s, int k)
     {
-        if constexpr (MODE == MG_POST) return fa[k] >= 0 ? c * fr[k] + fe[k] : 0.0;
-        return fa[k] >= 0 ? fr[k] : 0.0;
+        const bool ok = fa[s][k] >= 0;
+        if constexpr (kQueue) {
+#pragma unroll
+            for (int j = 0; j < 3; ++j) rq[k][j] = rq[k][j + 1];
+            rq[k][3] = ok ? fr[s][k] : (R)0;
+        }
+        if constexpr (MODE == MG_POST) return ok ? (R)c * fr[s][k] + fe[s][k] : (R)0;
+        return ok ? fr[s][k] : (R)0;
     }
-    __device__ __forceinline__ void fetch_halo_at(int j, int a, int x, int y, int z)
+    __device__ __forceinline__ void fetch_halo_at(int s, int j, int a, int x, int y, int z)
     {
-        ha[j] = a;
-        hr[j] = raw_load(r, a);
-        if constexpr (MODE == MG_POST) he[j] = e1[cell(a, x, y, z)];
+        ha[s][j] = a;
+        hr[s][j] = raw_load(r, a);
+        if constexpr (MODE == MG_POST) he[s][j] = e1[cell(a, x, y, z)];
     }
-    __device__ __forceinline__ double fin_halo(int j)
+    __device__ __forceinline__ R fin_halo(int s, int j)
     {
-        if constexpr (MODE == MG_POST) return ha[j] >= 0 ? c * hr[j] + he[j] : 0.0;
-        return ha[j] >= 0 ? hr[j] : 0.0;
+        if constexpr (MODE == MG_POST) return ha[s][j] >= 0 ? (R)c * hr[s][j] + he[s][j] : (R)0;
+        return ha[s][j] >= 0 ? hr[s][j] : (R)0;
     }
-    __device__ __forceinline__ void fetch_out_at(int k, int a, int x, int y, int z)
+    __device__ __forceinline__ void fetch_out_at(int s, int k, int a, int x, int y, int z)
     {
         if constexpr (MODE == MG_POST) {
-            oa[k] = a;
-            ob[k] = raw_load(r, a);
+            oa[s][k] = a;
+            if constexpr (!kQueue) oe[s][k] = e1[cell(a, x, y, z)];
         } else {
-            oa[k] = a >= 0 ? ((z - pzlo) * dnxy + (y - pylo) * dnx + (x - pxlo)) : -1;
+            oa[s][k] = a >= 0 ? ((z - pzlo) * dnxy + (y - pylo) * dnx + (x - pxlo)) : -1;
         }
     }
-    __device__ __forceinline__ void output(int k, double uu, double Au)
+    __device__ __forceinline__ void output(int s, int k, R uu, R Au)
     {
         if constexpr (MODE == MG_PRE) {
-            *sel_ptr(out, oa[k], sink) = (float)((uu - c * Au) * inv_sigma);
+            *sel_ptr(out, oa[s][k], sink) = (float)(((double)uu - c * (double)Au) * inv_sigma);
         } else {
-            const bool ok = oa[k] >= 0;
-            const float zs = (float)((uu + c * (ob[k] - Au)) * inv_sigma);
-            rho += ok ? ob[k] * ((double)zs * sigma) : 0.0;
-            *sel_ptr(out, oa[k], sink) = zs;
+            const bool ok = oa[s][k] >= 0;
+            double rv;
+            if constexpr (kQueue)
+                rv = (double)rq[k][0];
+            else
+                rv = ((double)uu - (double)oe[s][k]) / c;
+            const float zs = (float)(((double)uu + c * (rv - (double)Au)) * inv_sigma);
+            rho += ok ? rv * ((double)zs * sigma) : 0.0;
+            *sel_ptr(out, oa[s][k], sink) = zs;
         }
     }
 };
@@ -839,100 +907,106 @@ struct PMg {
 // direction pass of the preconditioned iteration: u = z + beta p_old
 // (z at scale sz, p_old at scale sp), rounded to the stored p_new (scale sz)
 // before A is applied; sums p.Ap
-template <int K, int KH>
+template <typename R, int K, int KH, int S = 1>
 struct PMgDir {
+    static constexpr int kSlots = S;
     const float *z, *pold;
     float *pnew, *sink;
     double beta, sz, sp, inv_sz;
     bool load_p;
     double pap = 0.0;
-    float fz[K], fp[K];
-    int fa[K];
-    float hz[KH], hp[KH];
-    int ha[KH];
+    float fz[S][K], fp[S][K];
+    int fa[S][K];
+    float hz[S][KH], hp[S][KH];
+    int ha[S][KH];
     __device__ __forceinline__ float round_p(float zz, float pp) const
     {
         return (float)(((double)zz * sz + beta * ((double)pp * sp)) * inv_sz);
     }
-    __device__ __forceinline__ void fetch_own(int k, int a)
+    __device__ __forceinline__ void fetch_own(int s, int k, int a)
     {
-        fa[k] = a;
-        fz[k] = raw_load(z, a);
-        fp[k] = load_p ? raw_load(pold, a) : 0.f;
+        fa[s][k] = a;
+        fz[s][k] = raw_load(z, a);
+        fp[s][k] = load_p ? raw_load(pold, a) : 0.f;
     }
-    __device__ __forceinline__ double fin_own(int k)
+    __device__ __forceinline__ R fin_own(int s, int k)
     {
-        const bool ok = fa[k] >= 0;
-        const float ps = ok ? round_p(fz[k], fp[k]) : 0.f;
-        *sel_ptr(pnew, fa[k], sink) = ps;
-        return (double)ps * sz;
+        const bool ok = fa[s][k] >= 0;
+        const float ps = ok ? round_p(fz[s][k], fp[s][k]) : 0.f;
+        *sel_ptr(pnew, fa[s][k], sink) = ps;
+        return (R)((double)ps * sz);
     }
-    __device__ __forceinline__ void fetch_halo(int j, int a)
+    __device__ __forceinline__ void fetch_halo(int s, int j, int a)
     {
-        ha[j] = a;
-        hz[j] = raw_load(z, a);
-        hp[j] = load_p ? raw_load(pold, a) : 0.f;
+        ha[s][j] = a;
+        hz[s][j] = raw_load(z, a);
+        hp[s][j] = load_p ? raw_load(pold, a) : 0.f;
     }
-    __device__ __forceinline__ double fin_halo(int j)
+    __device__ __forceinline__ R fin_halo(int s, int j)
     {
-        return ha[j] >= 0 ? (double)round_p(hz[j], hp[j]) * sz : 0.0;
+        return ha[s][j] >= 0 ? (R)((double)round_p(hz[s][j], hp[s][j]) * sz) : (R)0;
     }
-    __device__ __forceinline__ void fetch_out(int, int, int, int, int) {}
-    __device__ __forceinline__ void output(int, double u, double Au) { pap += u * Au; }
+    __device__ __forceinline__ void fetch_out(int, int, int) {}
+    __device__ __forceinline__ void output(int, int, R u, R Au) { pap += (double)u * (double)Au; }
 };
 
 // update pass of the preconditioned iteration: p = sz * stored p;
-// r = rsrc - alpha A p at output time, sums r.r; the iterate at load time by
-// mode XM as in the plain iteration (XM_PAIR adds alpha2 sq q + alpha p, q
-// the previous direction at its scale sq)
-template <int K, int KH, int XM>
+// r = rsrc - alpha A p at output time (r in R), sums r.r; the iterate
+// (FP64) at load time by mode XM as in the plain iteration, each increment
+// times xscale (XM_PAIR adds alpha2 sq q + alpha p, q the previous direction
+// at its scale sq)
+template <typename R, int K, int KH, int XM, int S = 1>
 struct PMgUpd {
+    static constexpr int kSlots = S;
     const float *p;
-    const double *rsrc;
-    double *x, *r, *sink;
+    const R *rsrc;
+    double *x;
+    R *r, *sink;
+    double *xsink;              // where invalid lanes store their x
     double alpha, sz;
     bool load_x;
     const float *q = nullptr;
     double alpha2 = 0.0, sq = 0.0;
+    double xscale = 1.0;
     double rr = 0.0;
-    float fp[K], fq[K];
-    double fx[K];
-    int fa[K];
-    float hp[KH];
-    int ha[KH];
-    double orr[K];
-    int oa[K];
-    __device__ __forceinline__ void fetch_own(int k, int a)
+    float fp[S][K], fq[S][K];
+    double fx[S][K];
+    int fa[S][K];
+    float hp[S][KH];
+    int ha[S][KH];
+    R orr[S][K];
+    int oa[S][K];
+    __device__ __forceinline__ void fetch_own(int s, int k, int a)
     {
-        fa[k] = a;
-        fp[k] = raw_load(p, a);
-        if constexpr (XM != XM_SKIP) fx[k] = load_x ? raw_load(x, a) : 0.0;
-        if constexpr (XM == XM_PAIR) fq[k] = raw_load(q, a);
+        fa[s][k] = a;
+        fp[s][k] = raw_load(p, a);
+        if constexpr (XM != XM_SKIP) fx[s][k] = load_x ? raw_load(x, a) : 0.0;
+        if constexpr (XM == XM_PAIR) fq[s][k] = raw_load(q, a);
     }
-    __device__ __forceinline__ double fin_own(int k)
+    __device__ __forceinline__ R fin_own(int s, int k)
     {
-        const double pv = fa[k] >= 0 ? (double)fp[k] * sz : 0.0;
-        if constexpr (XM == XM_STEP) *sel_ptr(x, fa[k], sink) = fx[k] + alpha * pv;
-        if constexpr (XM == XM_PAIR)
-            *sel_ptr(x, fa[k], sink) = fx[k] + alpha2 * ((double)fq[k] * sq) + alpha * pv;
-        return pv;
+        const double pv = fa[s][k] >= 0 ? (double)fp[s][k] * sz : 0.0;
+        double *xs = sel_ptr(x, fa[s][k], xsink);
+        if constexpr (XM == XM_STEP) *xs = fx[s][k] + xscale * (alpha * pv);
+        if constexpr (XM == XM_PAIR) *xs = fx[s][k] + xscale * (alpha2 * ((double)fq[s][k] * sq) + alpha * pv);
+        return (R)pv;
     }
-    __device__ __forceinline__ void fetch_halo(int j, int a)
+    __device__ __forceinline__ void fetch_halo(int s, int j, int a)
     {
-        ha[j] = a;
-        hp[j] = raw_load(p, a);
+        ha[s][j] = a;
+        hp[s][j] = raw_load(p, a);
     }
-    __device__ __forceinline__ double fin_halo(int j) { return ha[j] >= 0 ? (double)hp[j] * sz : 0.0; }
-    __device__ __forceinline__ void fetch_out(int k, int a, int, int, int)
+    __device__ __forceinline__ R fin_halo(int s, int j) { return ha[s][j] >= 0 ? (R)((double)hp[s][j] * sz) : (R)0; }
+    __device__ __forceinline__ void fetch_out(int s, int k, int a)
     {
-        oa[k] = a;
-        orr[k] = raw_load(rsrc, a);
+        oa[s][k] = a;
+        orr[s][k] = raw_load(rsrc, a);
     }
-    __device__ __forceinline__ void output(int k, double, double Au)
+    __device__ __forceinline__ void output(int s, int k, R, R Au)
     {
-        const double t = oa[k] >= 0 ? orr[k] - alpha * Au : 0.0;
-        *sel_ptr(r, oa[k], sink) = t;
-        rr += t * t;
+        const R t = oa[s][k] >= 0 ? (R)((double)orr[s][k] - alpha * (double)Au) : (R)0;
+        *sel_ptr(r, oa[s][k], sink) = t;
+        rr += (double)t * (double)t;
     }
 };
 
@@ -967,8 +1041,8 @@ struct CellWalk {
 // (stride T) at a time, evaluates body(c, x, y, z) for all U (loads of the U
 // cells in flight together), then stores the U results to out[c].  Cells
 // past the end evaluate cell 0 and store nothing.
-template <int T, int U, class F>
-__device__ __forceinline__ void mg_cells(const MgLevel &L, double *out, F body)
+template <int T, int U, typename CT, class F>
+__device__ __forceinline__ void mg_cells(const MgLevel &L, CT *out, F body)
 {
     const int n = L.nx * L.ny * L.nz;
     CellWalk w(L, T);
@@ -984,20 +1058,21 @@ __device__ __forceinline__ void mg_cells(const MgLevel &L, double *out, F body)
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (cc[u] >= 0) out[cc[u]] = v[u];
+            if (cc[u] >= 0) out[cc[u]] = (CT)v[u];
     }
 }
 
 // sum over the six neighbours of cell (x, y, z) of s_a v(neighbour), zero
 // outside the box (branch-free: a missing neighbour reads the cell itself)
-__device__ __forceinline__ double mg_nbsum(const MgLevel &L, const double *v, int c, int x, int y, int z,
+template <typename CT>
+__device__ __forceinline__ double mg_nbsum(const MgLevel &L, const CT *v, int c, int x, int y, int z,
                                            const double (&s)[3])
 {
     const int sxy = L.nx * L.ny;
     const bool xm = x > 0, xp = x + 1 < L.nx, ym = y > 0, yp = y + 1 < L.ny, zm = z > 0, zp = z + 1 < L.nz;
-    const double a0 = v[xm ? c - 1 : c], a1 = v[xp ? c + 1 : c];
-    const double b0 = v[ym ? c - L.nx : c], b1 = v[yp ? c + L.nx : c];
-    const double d0 = v[zm ? c - sxy : c], d1 = v[zp ? c + sxy : c];
+    const double a0 = (double)v[xm ? c - 1 : c], a1 = (double)v[xp ? c + 1 : c];
+    const double b0 = (double)v[ym ? c - L.nx : c], b1 = (double)v[yp ? c + L.nx : c];
+    const double d0 = (double)v[zm ? c - sxy : c], d1 = (double)v[zp ? c + sxy : c];
     return s[0] * ((xm ? a0 : 0.0) + (xp ? a1 : 0.0)) + s[1] * ((ym ? b0 : 0.0) + (yp ? b1 : 0.0)) +
            s[2] * ((zm ? d0 : 0.0) + (zp ? d1 : 0.0));
 }
@@ -1015,12 +1090,12 @@ constexpr int MG_U = 4;     // cells per thread in flight
 // from the dense PE box (stored / sigma in FP32; children outside PE hold
 // stale values and cm masks them; cells outside the domain read the box's
 // first line and yield zero)
-template <int T>
-__device__ void mg_restrict_dense(const MgLevel &L, const float *__restrict__ t, double sigma, double *__restrict__ f)
+template <int T, typename CT>
+__device__ void mg_restrict_dense(const MgLevel &L, const float *__restrict__ t, double sigma, CT *__restrict__ f)
 {
     const int dnx = 2 * L.nx, dnxy = 4 * L.nx * L.ny;
     const double w = 0.125 * sigma;
-    mg_cells<T, MG_U>(L, f, [&](int c, int x, int y, int z) -> double {
+    mg_cells<T, MG_U, CT>(L, f, [&](int c, int x, int y, int z) -> double {
         const int m = L.cm[c];
         const float *p = t + (m ? (long long)(2 * z) * dnxy + (2 * y) * dnx + 2 * x : 0);
         const float2 v0 = *reinterpret_cast<const float2 *>(p);
@@ -1039,8 +1114,8 @@ __device__ void mg_restrict_dense(const MgLevel &L, const float *__restrict__ t,
 // V-cycle on the coarse levels: e_1 ~ C f_1, the right-hand side f of each
 // level zero outside its domain.  Per level: f at off, e at off + n, t at
 // off + 2n; the result e_1 is returned.
-template <int T>
-__device__ const double *mg_vcycle(const SolveArgs &a, const MgClass &M, double *ms)
+template <int T, typename CT>
+__device__ const CT *mg_vcycle(const SolveArgs &a, const MgClass &M, CT *ms)
 {
     const int nl = M.levels;
     const double wc = a.mg_omega_c;
@@ -1049,11 +1124,11 @@ __device__ const double *mg_vcycle(const SolveArgs &a, const MgClass &M, double 
     // averaged over the children in the domain of each coarser cell
     for (int l = 0; l + 1 < nl; ++l) {
         const MgLevel L = M.lv[l], Lc = M.lv[l + 1];
-        const double *f = ms + L.off;
+        const CT *f = ms + L.off;
         double s[3];
         mg_spacing(a, l, s);
         const double wd = wc / (2.0 * (s[0] + s[1] + s[2]));
-        mg_cells<T, 2>(Lc, ms + Lc.off, [&](int C, int X, int Y, int Z) -> double {
+        mg_cells<T, 1, CT>(Lc, ms + Lc.off, [&](int C, int X, int Y, int Z) -> double {
             const int m = Lc.cm[C];
             double sum = 0.0;
 #pragma unroll
@@ -1062,7 +1137,7 @@ __device__ const double *mg_vcycle(const SolveArgs &a, const MgClass &M, double 
                 const int x = in ? 2 * X + (k & 1) : 0, y = in ? 2 * Y + ((k >> 1) & 1) : 0,
                           z = in ? 2 * Z + (k >> 2) : 0;
                 const int c = (z * L.ny + y) * L.nx + x;
-                const double t = (1.0 - wc) * f[c] + wd * mg_nbsum(L, f, c, x, y, z, s);
+                const double t = (1.0 - wc) * (double)f[c] + wd * mg_nbsum(L, f, c, x, y, z, s);
                 sum += in ? t : 0.0;
             }
             return 0.125 * sum;
@@ -1070,25 +1145,25 @@ __device__ const double *mg_vcycle(const SolveArgs &a, const MgClass &M, double 
         __syncthreads();
     }
     // coarsest: damped Jacobi sweeps from zero, e and t in turn
-    const double *ec;
+    const CT *ec;
     {
         const MgLevel L = M.lv[nl - 1];
         const int n = L.nx * L.ny * L.nz;
-        const double *f = ms + L.off;
-        double *e = ms + L.off + n, *t = e + n;
+        const CT *f = ms + L.off;
+        CT *e = ms + L.off + n, *t = e + n;
         double s[3];
         mg_spacing(a, nl - 1, s);
         const double wd = wc / (2.0 * (s[0] + s[1] + s[2]));
-        for (int c = threadIdx.x; c < n; c += T) e[c] = wd * f[c];
+        for (int c = threadIdx.x; c < n; c += T) e[c] = (CT)(wd * (double)f[c]);
         __syncthreads();
         for (int sw = 1; sw < a.mg_coarse_sweeps; ++sw) {
-            const double *eo = e;
-            mg_cells<T, 1>(L, t, [&](int c, int x, int y, int z) -> double {
-                const double v = (1.0 - wc) * eo[c] + wd * (f[c] + mg_nbsum(L, eo, c, x, y, z, s));
+            const CT *eo = e;
+            mg_cells<T, 1, CT>(L, t, [&](int c, int x, int y, int z) -> double {
+                const double v = (1.0 - wc) * (double)eo[c] + wd * ((double)f[c] + mg_nbsum(L, eo, c, x, y, z, s));
                 return L.cm[c] ? v : 0.0;
             });
             __syncthreads();
-            double *u = e; e = t; t = u;
+            CT *u = e; e = t; t = u;
         }
         ec = e;
     }
@@ -1097,19 +1172,19 @@ __device__ const double *mg_vcycle(const SolveArgs &a, const MgClass &M, double 
     for (int l = nl - 2; l >= 0; --l) {
         const MgLevel L = M.lv[l], Lc = M.lv[l + 1];
         const int n = L.nx * L.ny * L.nz;
-        const double *f = ms + L.off;
-        double *e = ms + L.off + n, *u = e + n;
+        const CT *f = ms + L.off;
+        CT *e = ms + L.off + n, *u = e + n;
         double s[3];
         mg_spacing(a, l, s);
         const double wd = wc / (2.0 * (s[0] + s[1] + s[2]));
-        const double *ecl = ec;
-        mg_cells<T, MG_U>(L, u, [&](int c, int x, int y, int z) -> double {
-            const double v = wd * f[c] + ecl[((z >> 1) * Lc.ny + (y >> 1)) * Lc.nx + (x >> 1)];
+        const CT *ecl = ec;
+        mg_cells<T, MG_U, CT>(L, u, [&](int c, int x, int y, int z) -> double {
+            const double v = wd * (double)f[c] + (double)ecl[((z >> 1) * Lc.ny + (y >> 1)) * Lc.nx + (x >> 1)];
             return L.cm[c] ? v : 0.0;
         });
         __syncthreads();
-        mg_cells<T, MG_U>(L, e, [&](int c, int x, int y, int z) -> double {
-            const double v = (1.0 - wc) * u[c] + wd * (f[c] + mg_nbsum(L, u, c, x, y, z, s));
+        mg_cells<T, MG_U, CT>(L, e, [&](int c, int x, int y, int z) -> double {
+            const double v = (1.0 - wc) * (double)u[c] + wd * ((double)f[c] + mg_nbsum(L, u, c, x, y, z, s));
             return L.cm[c] ? v : 0.0;
         });
         __syncthreads();
@@ -1121,23 +1196,30 @@ __device__ const double *mg_vcycle(const SolveArgs &a, const MgClass &M, double 
 // Kernel modes: FP64 CG from zero, FP64 CG from the guess in vout (one more
 // pass type, so more registers), FP32 CG with FP64 reliable updates (guess
 // read at run time), FP64 CG preconditioned by the multigrid V-cycle (guess
-// read at run time).
-enum { CG_FP64 = 0, CG_FP64_GUESS = 1, CG_MIXED = 2, CG_MG = 3 };
+// read at run time), and the multigrid-preconditioned iteration in FP32 with
+// FP64 residual replacement (guess read at run time).
+enum { CG_FP64 = 0, CG_FP64_GUESS = 1, CG_MIXED = 2, CG_MG = 3, CG_MG_MIXED = 4 };
 
-// One pair: FP64 CG, or FP32 CG with FP64 iterative refinement.
-template <int T, int K, int KH, int K32, int KH32, int MODE>
+// Residual replacement of the FP32 multigrid iteration: the true FP64
+// residual replaces the recursive one once the recursive norm has fallen by
+// this factor since the last replacement (or claims convergence).
+constexpr double kMgMixedDrop = 1e-3;
+
+// One pair: FP64 CG, FP32 CG with FP64 iterative refinement, or the
+// multigrid-preconditioned iteration in FP64 or FP32.  PF64 / PF32: planes of
+// loads in flight in the FP64 / FP32 passes.
+template <int T, int K, int KH, int K32, int KH32, int MODE, int PF64, int PF32>
 __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, long long slot, double *lds, double *red,
                                                int &par)
 {
     constexpr bool MIXED = MODE == CG_MIXED;
     const int tid = threadIdx.x;
     const int4 pg = a.pair_gc[pair];
-    const int2 ij = a.pair_ij[pair];
     const ClassDev g = a.cls[pg.w];
     double *x = a.vout + a.out_off[pair];
     const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
     const StencilW<double> w64 = stencil_w<double>(a);
-    const bool guess = (MIXED || MODE == CG_MG) ? a.guess != 0 : MODE == CG_FP64_GUESS;
+    const bool guess = (MIXED || MODE == CG_MG || MODE == CG_MG_MIXED) ? a.guess != 0 : MODE == CG_FP64_GUESS;
     int it = 0, conv = 0, outer = 0;
     double bb = 0.0;
 
@@ -1145,6 +1227,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         // PCG with the multigrid V-cycle as M: per slot r (FP64), then z and
         // two direction buffers (FP32, scaled); x from zero or the guess
         double *r = a.scratch + slot * 4 * a.slot_n;
+        double *rsink = r + a.slot_n - 1;
         float *zv = reinterpret_cast<float *>(r + a.slot_n);
         float *pold = zv + a.slot_n, *pnew = pold + a.slot_n;
         double *ms = a.mg_scratch + slot * a.mg_slot_n;
@@ -1157,7 +1240,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         const double *rsrc = b;
         double rr = 0.0;
         if (guess) {
-            PRes<K, KH, double, double> pr{x, x, b, r, r + a.slot_n - 1, false, 0.0};
+            PRes<K, KH, double, double, PF64> pr{x, x, b, r, rsink, false, 0.0};
             zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
             ++outer;
             rr = block_sum<T>(pr.rr, red);
@@ -1170,14 +1253,15 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         }
         // z = M rs at scale sz (stored / sz); returns rs . z
         auto precond = [&](const double *rs, double sz) -> double {
-            PMg<K, KH, MG_PRE> pre{rs, nullptr, dense, dsink, cfine, sz, 1.0 / sz, g.pxlo, g.pylo, g.pzlo,
-                                   2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny};
+            PMg<double, K, KH, MG_PRE, PF64> pre{rs, nullptr, dense, dsink, cfine, sz, 1.0 / sz, g.pxlo, g.pylo,
+                                               g.pzlo, 2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny};
             zmarch<double, T, K, KH>(g, lds, par, pre, w64, pg, a.nx, a.ny, a.nz);
             __syncthreads();                        // the dense residual of every band is written
-            mg_restrict_dense<T>(L1, dense, sz, ms + L1.off);
-            const double *e1 = mg_vcycle<T>(a, M, ms);
-            PMg<K, KH, MG_POST> post{rs, e1, zv, zv + a.slot_n - 1, cfine, sz, 1.0 / sz, g.pxlo, g.pylo, g.pzlo,
-                                     2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny};
+            mg_restrict_dense<T, double>(L1, dense, sz, ms + L1.off);
+            const double *e1 = mg_vcycle<T, double>(a, M, ms);
+            PMg<double, K, KH, MG_POST, PF64> post{rs, e1, zv, zv + a.slot_n - 1, cfine, sz, 1.0 / sz, g.pxlo,
+                                                 g.pylo, g.pzlo, 2 * L1.nx, 4 * L1.nx * L1.ny, L1.nx,
+                                                 L1.nx * L1.ny};
             zmarch<double, T, K, KH>(g, lds, par, post, w64, pg, a.nx, a.ny, a.nz);
             return block_sum<T>(post.rho, red);
         };
@@ -1193,7 +1277,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
             double rho = precond(rsrc, sz);
             double pap;
             {
-                PMgDir<K, KH> pd{zv, pold, pnew, pnew + a.slot_n - 1, 0.0, sz, sz, 1.0 / sz, false};
+                PMgDir<double, K, KH, PF64> pd{zv, pold, pnew, pnew + a.slot_n - 1, 0.0, sz, sz, 1.0 / sz, false};
                 zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
             }
@@ -1205,15 +1289,15 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
             for (;;) {
                 const double alpha = rho / pap;
                 if (!pending) {
-                    PMgUpd<K, KH, XM_SKIP> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, sp, false};
+                    PMgUpd<double, K, KH, XM_SKIP, PF64> pu{pnew, rsrc, x, r, rsink, rsink, alpha, sp, false};
                     zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
                     rr = block_sum<T>(pu.rr, red);
                     owed = alpha;
                     s_owed = sp;
                     pending = true;
                 } else {
-                    PMgUpd<K, KH, XM_PAIR> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, sp, guess || it > 1,
-                                              pold, owed, s_owed};
+                    PMgUpd<double, K, KH, XM_PAIR, PF64> pu{pnew, rsrc, x, r, rsink, rsink, alpha, sp, guess || it > 1,
+                                                          pold, owed, s_owed};
                     zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
                     rr = block_sum<T>(pu.rr, red);
                     pending = false;
@@ -1227,7 +1311,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 const double beta = rho_new / rho;
                 rho = rho_new;
                 float *t = pold; pold = pnew; pnew = t;
-                PMgDir<K, KH> pd{zv, pold, pnew, pnew + a.slot_n - 1, beta, sz, sp, 1.0 / sz, true};
+                PMgDir<double, K, KH, PF64> pd{zv, pold, pnew, pnew + a.slot_n - 1, beta, sz, sp, 1.0 / sz, true};
                 zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
                 sp = sz;
@@ -1241,13 +1325,152 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 __syncthreads();
             }
         }
+    } else if constexpr (MODE == CG_MG_MIXED) {
+        // The multigrid-preconditioned iteration in FP32: r, z and the
+        // directions in FP32 (r as r / sig, sig a power of two reset at each
+        // replacement; z and p at their own power-of-two scales), every fine
+        // pass and the V-cycle in FP32, x in FP64 (increments times sig).  The
+        // true residual b - A x, in FP64, replaces r whenever the recursive
+        // norm has fallen by kMgMixedDrop since the last replacement or
+        // claims convergence; the iteration then goes on from the replaced
+        // residual with its direction kept (rescaled to the new sig).
+        float *r32 = a.scratch32 + slot * 4 * a.slot_n;
+        float *rsink = r32 + a.slot_n - 1;
+        float *zv = r32 + a.slot_n, *pold = zv + a.slot_n, *pnew = pold + a.slot_n;
+        double *msd = a.mg_scratch + slot * a.mg_slot_n;
+        float *ms = reinterpret_cast<float *>(msd);   // coarse levels in FP32, in the FP64 region's first half
+        const MgClass &M = a.mgc[pg.w];
+        const MgLevel L1 = M.lv[0];
+        float *dense = reinterpret_cast<float *>(msd + M.dense_off);
+        float *dsink = dense + 8LL * L1.nx * L1.ny * L1.nz;
+        double *xsink = reinterpret_cast<double *>(dsink);   // 8-byte aligned spare after the dense box
+        const StencilW<float> w32 = stencil_w<float>(a);
+        const double cfine = a.mg_omega / (-w64.c);
+        const double n_el = (double)g.n_pe;
+        {
+            double s2 = 0.0;
+            for (int q = tid; q < g.n_pe; q += T) s2 += b[q] * b[q];
+            bb = block_sum<T>(s2, red);
+        }
+        const double stop = a.tol * a.tol * bb;
+        if (bb == 0.0) {
+            for (int q = tid; q < g.n_pe; q += T) x[q] = 0.0;
+            __syncthreads();
+            conv = 1;
+        } else {
+            double sig = pow2_scale(bb, n_el);
+            double rr;                              // r.r of the current residual, unscaled
+            if (guess) {
+                PRes<K, KH, double, float, PF64> pr{x, x, b, r32, rsink, false, 0.0, 1.0 / sig};
+                zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
+                ++outer;
+                rr = block_sum<T>(pr.rr, red);
+            } else {
+                const double inv = 1.0 / sig;
+                for (int q = tid; q < g.n_pe; q += T) {
+                    x[q] = 0.0;
+                    r32[q] = (float)(b[q] * inv);
+                }
+                __syncthreads();
+                rr = bb;
+            }
+            if (rr <= stop) {
+                conv = 1;
+            } else {
+                // z = M rs at scale sz (stored / sz); returns rs . z
+                auto precond = [&](double sz) -> double {
+                    PMg<float, K32, KH32, MG_PRE, PF32> pre{r32, nullptr, dense, dsink, cfine, sz, 1.0 / sz,
+                                                            g.pxlo, g.pylo, g.pzlo, 2 * L1.nx, 4 * L1.nx * L1.ny,
+                                                            L1.nx, L1.nx * L1.ny};
+                    zmarch<float, T, K32, KH32>(g, lds, par, pre, w32, pg, a.nx, a.ny, a.nz);
+                    __syncthreads();
+                    mg_restrict_dense<T, float>(L1, dense, sz, ms + L1.off);
+                    const float *e1 = mg_vcycle<T, float>(a, M, ms);
+                    PMg<float, K32, KH32, MG_POST, PF32> post{r32, e1, zv, zv + a.slot_n - 1, cfine, sz, 1.0 / sz,
+                                                              g.pxlo, g.pylo, g.pzlo, 2 * L1.nx,
+                                                              4 * L1.nx * L1.ny, L1.nx, L1.nx * L1.ny};
+                    zmarch<float, T, K32, KH32>(g, lds, par, post, w32, pg, a.nx, a.ny, a.nz);
+                    return block_sum<T>(post.rho, red);
+                };
+                double rr_s = rr / (sig * sig);     // r.r in the units of r32
+                double rr_rep = rr;                 // unscaled r.r at the last replacement
+                double sz = pow2_scale(rr_s, n_el);
+                double rho = precond(sz);
+                double pap;
+                {
+                    PMgDir<float, K32, KH32, PF32> pd{zv, pold, pnew, pnew + a.slot_n - 1, 0.0, sz, sz, 1.0 / sz,
+                                                      false};
+                    zmarch<float, T, K32, KH32>(g, lds, par, pd, w32, pg, a.nx, a.ny, a.nz);
+                    pap = block_sum<T>(pd.pap, red);
+                }
+                double sp = sz;
+                double owed = 0.0, s_owed = 0.0;
+                bool pending = false;
+                // the owed step alpha p (p in pnew at scale s_owed), into x
+                auto flush = [&]() {
+                    const double w = sig * owed * s_owed;
+                    for (int q = tid; q < g.n_pe; q += T) x[q] += w * (double)pnew[q];
+                    __syncthreads();
+                    pending = false;
+                };
+                for (;;) {
+                    const double alpha = rho / pap;
+                    if (!pending) {
+                        PMgUpd<float, K32, KH32, XM_SKIP, PF32> pu{pnew, r32, x, r32, rsink, xsink, alpha, sp, true};
+                        zmarch<float, T, K32, KH32>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
+                        rr_s = block_sum<T>(pu.rr, red);
+                        owed = alpha;
+                        s_owed = sp;
+                        pending = true;
+                    } else {
+                        PMgUpd<float, K32, KH32, XM_PAIR, PF32> pu{pnew, r32, x, r32, rsink, xsink, alpha, sp, true,
+                                                                   pold, owed, s_owed, sig};
+                        zmarch<float, T, K32, KH32>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
+                        rr_s = block_sum<T>(pu.rr, red);
+                        pending = false;
+                    }
+                    ++it;
+                    const double rr_est = rr_s * sig * sig;
+                    if (rr_est <= stop || rr_est <= kMgMixedDrop * kMgMixedDrop * rr_rep || it >= a.maxit ||
+                        !(rr_s == rr_s)) {
+                        if (pending) flush();
+                        const double sig_new = rr_est > 0.0 && rr_est == rr_est ? pow2_scale(rr_est, n_el) : sig;
+                        PRes<K, KH, double, float, PF64> pr{x, x, b, r32, rsink, false, 0.0, 1.0 / sig_new};
+                        zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
+                        ++outer;
+                        const double rr_true = block_sum<T>(pr.rr, red);
+                        if (rr_true <= stop) { conv = 1; break; }
+                        if (it >= a.maxit) break;
+                        // carry the iteration into the new units of r32
+                        const double f = sig / sig_new;
+                        sp *= f;
+                        rho *= f * f;
+                        sig = sig_new;
+                        rr_rep = rr_true;
+                        rr_s = rr_true / (sig * sig);
+                    }
+                    sz = pow2_scale(rr_s, n_el);
+                    const double rho_new = precond(sz);
+                    const double beta = rho_new / rho;
+                    rho = rho_new;
+                    float *t = pold; pold = pnew; pnew = t;
+                    PMgDir<float, K32, KH32, PF32> pd{zv, pold, pnew, pnew + a.slot_n - 1, beta, sz, sp, 1.0 / sz,
+                                                      true};
+                    zmarch<float, T, K32, KH32>(g, lds, par, pd, w32, pg, a.nx, a.ny, a.nz);
+                    pap = block_sum<T>(pd.pap, red);
+                    sp = sz;
+                }
+                if (pending) flush();
+            }
+        }
     } else if constexpr (!MIXED) {
+
         double *r = a.scratch + slot * 3 * a.slot_n;
         double *pold = r + a.slot_n, *pnew = pold + a.slot_n;
         const double *rsrc = b;
         double rr = 0.0, pap = 0.0;
         if constexpr (MODE == CG_FP64_GUESS) {
-            PRes<K, KH, double, double> pr{x, x, b, r, r + a.slot_n - 1, false, 0.0};
+            PRes<K, KH, double, double, PF64> pr{x, x, b, r, r + a.slot_n - 1, false, 0.0};
             zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
             ++outer;
             rr = block_sum<T>(pr.rr, red);
@@ -1255,7 +1478,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
             rsrc = r;
         }
         {
-            PDir<double, K, KH> pd{rsrc, pold, pnew, pnew + a.slot_n - 1, 0.0, false, !guess};
+            PDir<double, K, KH, PF64> pd{rsrc, pold, pnew, pnew + a.slot_n - 1, 0.0, false, !guess};
             zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
             pap = block_sum<T>(pd.pap, red);
             if (!guess) rr = bb = block_sum<T>(pd.bb, red);
@@ -1275,13 +1498,13 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 const double alpha = rr / pap;
                 double rn;
                 if (!pending) {
-                    PUpd<double, K, KH, XM_SKIP> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, false};
+                    PUpd<double, K, KH, XM_SKIP, PF64> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, false};
                     zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
                     rn = block_sum<T>(pu.rr, red);
                     owed = alpha;
                     pending = true;
                 } else {
-                    PUpd<double, K, KH, XM_PAIR> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, guess || it > 1, pold,
+                    PUpd<double, K, KH, XM_PAIR, PF64> pu{pnew, rsrc, x, r, r + a.slot_n - 1, alpha, guess || it > 1, pold,
                                                    owed};
                     zmarch<double, T, K, KH>(g, lds, par, pu, w64, pg, a.nx, a.ny, a.nz);
                     rn = block_sum<T>(pu.rr, red);
@@ -1294,7 +1517,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 if (rr <= stop) { conv = 1; break; }
                 if (it >= a.maxit) break;
                 double *t = pold; pold = pnew; pnew = t;
-                PDir<double, K, KH> pd{r, pold, pnew, pnew + a.slot_n - 1, beta, true, false};
+                PDir<double, K, KH, PF64> pd{r, pold, pnew, pnew + a.slot_n - 1, beta, true, false};
                 zmarch<double, T, K, KH>(g, lds, par, pd, w64, pg, a.nx, a.ny, a.nz);
                 pap = block_sum<T>(pd.pap, red);
             }
@@ -1329,7 +1552,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         bool have_d = false, first = true;
         for (;;) {
             // true residual of x (+ sigma d), in FP64
-            PRes<K, KH, float, double> pr{x, d32, b, r64, r64 + a.slot_n - 1, have_d, sigma};
+            PRes<K, KH, float, double, PF64> pr{x, d32, b, r64, r64 + a.slot_n - 1, have_d, sigma};
             zmarch<double, T, K, KH>(g, lds, par, pr, w64, pg, a.nx, a.ny, a.nz);
             ++outer;
             const double rr_true = block_sum<T>(pr.rr, red);
@@ -1366,7 +1589,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 double pap;
                 {
                     if (!first) { float *t = pold; pold = pnew; pnew = t; }
-                    PDir<float, K32, KH32> pd{r32, pold, pnew, pnew + a.slot_n - 1, (float)beta, !first, false};
+                    PDir<float, K32, KH32, PF32> pd{r32, pold, pnew, pnew + a.slot_n - 1, (float)beta, !first, false};
                     zmarch<float, T, K32, KH32>(g, lds, par, pd, w32, pg, a.nx, a.ny, a.nz);
                     pap = block_sum<T>(pd.pap, red);
                 }
@@ -1374,13 +1597,13 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
                 const float alpha = (float)(rr_s / pap);
                 double rn_s;
                 if (!pending) {
-                    PUpd<float, K32, KH32, XM_SKIP> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, false};
+                    PUpd<float, K32, KH32, XM_SKIP, PF32> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, false};
                     zmarch<float, T, K32, KH32>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
                     rn_s = block_sum<T>(pu.rr, red);
                     owed = alpha;
                     pending = true;
                 } else {
-                    PUpd<float, K32, KH32, XM_PAIR> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, have_d, pold,
+                    PUpd<float, K32, KH32, XM_PAIR, PF32> pu{pnew, r32, d32, r32, r32 + a.slot_n - 1, alpha, have_d, pold,
                                                       owed};
                     zmarch<float, T, K32, KH32>(g, lds, par, pu, w32, pg, a.nx, a.ny, a.nz);
                     rn_s = block_sum<T>(pu.rr, red);
@@ -1406,7 +1629,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
         }
     }
 
-    PFin<K, KH> pf{x, b};
+    PFin<K, KH, PF64> pf{x, b};
     zmarch<double, T, K, KH>(g, lds, par, pf, w64, pg, a.nx, a.ny, a.nz);
     const double res = block_sum<T>(pf.res, red);
     if (tid == 0) {
@@ -1418,7 +1641,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     __syncthreads();
 }
 
-template <int T, int K, int KH, int K32, int KH32, int WPE, int MODE>
+template <int T, int K, int KH, int K32, int KH32, int WPE, int MODE, int PF64, int PF32>
 __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
 {
     extern __shared__ double lds_dyn[];
@@ -1442,7 +1665,7 @@ __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
             __syncthreads();
             last_cls = cls;
         }
-        cg_zmarch_pair<T, K, KH, K32, KH32, MODE>(a, pair, blockIdx.x, lds_dyn, red, par);
+        cg_zmarch_pair<T, K, KH, K32, KH32, MODE, PF64, PF32>(a, pair, blockIdx.x, lds_dyn, red, par);
     }
 }
 
@@ -1626,12 +1849,25 @@ __global__ void k_zero_int(int *p, int n)
 // ---------------------------------------------------------------------------
 
 // (threads, FP64 columns / halo columns per thread, FP32 columns / halo
-// columns per thread, min waves per SIMD)
-#define EXX_ZM_VARIANTS(X) X(256, 4, 2, 8, 2, 2) X(512, 4, 1, 8, 1, 2) X(512, 6, 1, 8, 1, 2)
+// columns per thread, min waves per SIMD, planes of loads in flight in the
+// FP64 / FP32 passes, the modes it is built for as a bit mask over CG_*).
+// The kernel inlines every pass of its mode, and the register allocation
+// covers all of them at once: 8 FP32 columns per thread fit beside 4 FP64
+// columns in the FP32 modes only without the multigrid V-cycle, so the FP32
+// multigrid mode runs 4 FP32 columns.  Two planes in flight need a second
+// copy of every loaded value, more than a wave has beside the rest of a mode
+// (they are supported by the march, not built).
+constexpr int MODES_ALL = 0x1f;
+constexpr int MODES_BUT_MGMIX = MODES_ALL & ~(1 << 4);
+constexpr int MODES_MGMIX = 1 << 4;
+#define EXX_ZM_VARIANTS(X)                                                                                \
+    X(256, 4, 2, 8, 2, 2, 1, 1, MODES_BUT_MGMIX) X(512, 4, 1, 8, 1, 2, 1, 1, MODES_BUT_MGMIX)              \
+    X(512, 6, 1, 8, 1, 2, 1, 1, MODES_BUT_MGMIX) X(256, 4, 2, 4, 2, 2, 1, 1, MODES_MGMIX)                \
+    X(512, 4, 1, 4, 1, 2, 1, 1, MODES_MGMIX)
 
 static const CgVariant kVariants[] = {
-    {0, 256, 0, 0, 0, 0, 0},
-#define EXX_V(T, K, KH, K32, KH32, W) {1, T, K, KH, K32, KH32, W},
+    {0, 256, 0, 0, 0, 0, 0, 1, 1, MODES_ALL},
+#define EXX_V(T, K, KH, K32, KH32, W, P64, P32, MS) {1, T, K, KH, K32, KH32, W, P64, P32, MS},
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V
 };
@@ -1644,32 +1880,55 @@ int cg_variants(CgVariant *out, int max_n)
     return n;
 }
 
-template <int T, int K, int KH, int K32, int KH32, int W, int M>
+bool cg_variant_applies(const CgVariant &v, int mode) { return (v.modes >> mode) & 1; }
+
+template <int T, int K, int KH, int K32, int KH32, int W, int M, int P64, int P32, int MS>
 static hipError_t zm_occ(size_t lds, int *per_cu)
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_cg_zmarch<T, K, KH, K32, KH32, W, M>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    if (e != hipSuccess) return e;
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, k_cg_zmarch<T, K, KH, K32, KH32, W, M>, T, lds);
+    if constexpr (!((MS >> M) & 1)) {
+        return hipErrorInvalidValue;
+    } else {
+        auto *f = &k_cg_zmarch<T, K, KH, K32, KH32, W, M, P64, P32>;
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(f),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (e != hipSuccess) return e;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, f, T, lds);
+    }
 }
 
-#define EXX_MATCH(v, T, K, KH, K32, KH32, W) \
-    ((v).block == T && (v).cols == K && (v).halo == KH && (v).cols32 == K32 && (v).halo32 == KH32 && (v).wpe == W)
+template <int T, int K, int KH, int K32, int KH32, int W, int M, int P64, int P32, int MS>
+static hipError_t zm_launch(const SolveArgs &a, int grid, size_t lds, hipStream_t s)
+{
+    if constexpr (!((MS >> M) & 1)) {
+        return hipErrorInvalidValue;
+    } else {
+        hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, M, P64, P32>), dim3(grid), dim3(T), lds, s, a);
+        return hipGetLastError();
+    }
+}
+
+#define EXX_MATCH(v, T, K, KH, K32, KH32, W, P64, P32, MS)                                              \
+    ((v).block == T && (v).cols == K && (v).halo == KH && (v).cols32 == K32 && (v).halo32 == KH32 &&  \
+     (v).wpe == W && (v).pf64 == P64 && (v).pf32 == P32 && (v).modes == MS)
 
 int cg_mode(int precision, int guess, int mg)
 {
-    return mg ? CG_MG : precision ? CG_MIXED : guess ? CG_FP64_GUESS : CG_FP64;
+    return mg ? (precision ? CG_MG_MIXED : CG_MG) : precision ? CG_MIXED : guess ? CG_FP64_GUESS : CG_FP64;
 }
 
 hipError_t cg_occupancy(const CgVariant &v, int mode, size_t lds, int *blocks_per_cu)
 {
     if (!v.zmarch) return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, k_solve<256>, 256, 0);
-#define EXX_V(T, K, KH, K32, KH32, W)                                                           \
-    if (EXX_MATCH(v, T, K, KH, K32, KH32, W))                                                    \
-        return mode == CG_MG           ? zm_occ<T, K, KH, K32, KH32, W, CG_MG>(lds, blocks_per_cu)         \
-               : mode == CG_MIXED      ? zm_occ<T, K, KH, K32, KH32, W, CG_MIXED>(lds, blocks_per_cu)      \
-               : mode == CG_FP64_GUESS ? zm_occ<T, K, KH, K32, KH32, W, CG_FP64_GUESS>(lds, blocks_per_cu) \
-                                       : zm_occ<T, K, KH, K32, KH32, W, CG_FP64>(lds, blocks_per_cu);
+#define EXX_V(T, K, KH, K32, KH32, W, P64, P32, MS)                                                          \
+    if (EXX_MATCH(v, T, K, KH, K32, KH32, W, P64, P32, MS)) {                                                     \
+        switch (mode) {                                                                                       \
+        case CG_MG_MIXED: return zm_occ<T, K, KH, K32, KH32, W, CG_MG_MIXED, P64, P32, MS>(lds, blocks_per_cu);   \
+        case CG_MG: return zm_occ<T, K, KH, K32, KH32, W, CG_MG, P64, P32, MS>(lds, blocks_per_cu);               \
+        case CG_MIXED: return zm_occ<T, K, KH, K32, KH32, W, CG_MIXED, P64, P32, MS>(lds, blocks_per_cu);         \
+        case CG_FP64_GUESS: return zm_occ<T, K, KH, K32, KH32, W, CG_FP64_GUESS, P64, P32, MS>(lds, blocks_per_cu); \
+        default: return zm_occ<T, K, KH, K32, KH32, W, CG_FP64, P64, P32, MS>(lds, blocks_per_cu);                \
+        }                                                                                                     \
+    }
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V
     return hipErrorInvalidValue;
@@ -1681,18 +1940,16 @@ hipError_t launch_cg(const CgVariant &v, const SolveArgs &a, int grid, size_t ld
         hipLaunchKernelGGL(k_solve<256>, dim3(grid), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-#define EXX_V(T, K, KH, K32, KH32, W)                                                                          \
-    if (EXX_MATCH(v, T, K, KH, K32, KH32, W)) {                                                                 \
-        if (a.mg)                                                                                               \
-            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_MG>), dim3(grid), dim3(T), lds, s, a);    \
-        else if (a.precision)                                                                                   \
-            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_MIXED>), dim3(grid), dim3(T), lds, s, a); \
-        else if (a.guess)                                                                                       \
-            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_FP64_GUESS>), dim3(grid), dim3(T), lds, s, \
-                               a);                                                                              \
-        else                                                                                                    \
-            hipLaunchKernelGGL((k_cg_zmarch<T, K, KH, K32, KH32, W, CG_FP64>), dim3(grid), dim3(T), lds, s, a);  \
-        return hipGetLastError();                                                                               \
+    const int mode = cg_mode(a.precision, a.guess, a.mg);
+#define EXX_V(T, K, KH, K32, KH32, W, P64, P32, MS)                                               \
+    if (EXX_MATCH(v, T, K, KH, K32, KH32, W, P64, P32, MS)) {                                          \
+        switch (mode) {                                                                            \
+        case CG_MG_MIXED: return zm_launch<T, K, KH, K32, KH32, W, CG_MG_MIXED, P64, P32, MS>(a, grid, lds, s); \
+        case CG_MG: return zm_launch<T, K, KH, K32, KH32, W, CG_MG, P64, P32, MS>(a, grid, lds, s);    \
+        case CG_MIXED: return zm_launch<T, K, KH, K32, KH32, W, CG_MIXED, P64, P32, MS>(a, grid, lds, s); \
+        case CG_FP64_GUESS: return zm_launch<T, K, KH, K32, KH32, W, CG_FP64_GUESS, P64, P32, MS>(a, grid, lds, s); \
+        default: return zm_launch<T, K, KH, K32, KH32, W, CG_FP64, P64, P32, MS>(a, grid, lds, s);     \
+        }                                                                                          \
     }
     EXX_ZM_VARIANTS(EXX_V)
 #undef EXX_V

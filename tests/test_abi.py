@@ -124,7 +124,6 @@ def _setup_status(**over):
     (dict(n_grid=(4, 48, 48)), "n_grid"),
     (dict(box_dims=(49, 0, 0)), "box_dims"),
     (dict(precond=2), "precond"),
-    (dict(precond=1, precision=1), "precond"),
     (dict(n_classes=1), "n_classes"),
     (dict(n_classes=5), "n_classes"),
     (dict(n_classes=2, class_r_pe=(3.0, 2.0, 0, 0), class_r_me=(5.0, 4.0, 0, 0), omega_scale=3.0), "ascending"),

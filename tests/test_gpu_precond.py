@@ -176,3 +176,109 @@ def test_mg_c5_full_size_two_classes_in_waves():
     for p, r in zip(pick, refs):
         assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
     ctx.close()
+
+
+# ---------------------------------------------------------------------------
+# The multigrid-preconditioned iteration in FP32 with FP64 residual
+# replacement (precision = "fp32_refine"): it stops on the same true FP64
+# residual, so the same bars hold.
+# ---------------------------------------------------------------------------
+
+def test_mg_fp32_c1_matches_the_oracle(c1):
+    wl, phi, E, D, out = c1
+    _say("[gpu] small config, multigrid-preconditioned CG in FP32 with FP64 replacement")
+    ctx = X.Exx.from_workload(wl, precond="mg", precision="fp32_refine")
+    n = ctx.pairs(wl.orbitals.centers)
+    Eg, Dg = ctx.step(torch.from_numpy(phi).cuda())
+    info = ctx.pair_info()
+    st = ctx.stats()
+    assert n == len(out["e"])
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
+    assert abs(Eg - E) <= 1e-8 * abs(E), (Eg, E)
+    rel = np.abs(info["e"] - out["e"]) / np.abs(out["e"])
+    assert rel.max() <= 1e-8, rel.max()
+    assert gamma(D, Dg.cpu().numpy()).max() <= 1e-7
+    assert np.all(info["iters"] <= 0.5 * out["iters"]), (info["iters"], out["iters"])
+    # at least one replacement per pair beyond the first residual
+    assert st["outer_total"] >= n
+
+
+def test_mg_fp32_c1_waves_match_one_wave_and_repeat(c1):
+    wl, phi, *_ = c1
+    phit = torch.from_numpy(phi).cuda()
+    a = X.Exx.from_workload(wl, precond="mg", precision="fp32_refine", autotune=False)
+    a.pairs(wl.orbitals.centers)
+    E1, D1 = a.step(phit)
+    E1b, D1b = a.step(phit)
+    b = X.Exx.from_workload(wl, precond="mg", precision="fp32_refine", wave_pairs=9, autotune=False)
+    b.pairs(wl.orbitals.centers)
+    E2, D2 = b.step(phit)
+    assert b.stats()["n_waves"] > 1
+    assert E1b == E1 and torch.equal(D1b, D1)
+    assert E2 == E1 and torch.equal(D2, D1)
+
+
+def test_mg_fp32_c1_guess_and_zero_orbital(c1):
+    """From the previous step's potential the FP32 iteration converges at once
+    or in a few iterations; a zero orbital gives exact zero pair energies."""
+    wl, phi, E, D, out = c1
+    ctx = X.Exx.from_workload(wl, precond="mg", precision="fp32_refine", guess="previous")
+    ctx.pairs(wl.orbitals.centers)
+    phit = torch.from_numpy(phi).cuda()
+    ctx.step(phit)
+    it1 = ctx.pair_info()["iters"].mean()
+    E2, _ = ctx.step(phit)
+    info = ctx.pair_info()
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
+    assert abs(E2 - E) <= 1e-8 * abs(E)
+    assert info["iters"].mean() < 0.5 * it1
+    z = phi.copy()
+    z[3] = 0.0
+    c = X.Exx.from_workload(wl, precond="mg", precision="fp32_refine")
+    c.pairs(wl.orbitals.centers)
+    c.step(torch.from_numpy(z).cuda())
+    inf = c.pair_info()
+    touch = (inf["i"] == 3) | (inf["j"] == 3)
+    assert np.all(inf["e"][touch] == 0.0) and np.all(inf["converged"] == 1)
+
+
+def test_mg_fp32_c5_full_size_sampled_pairs():
+    """The 512-water workload with the FP32 multigrid iteration (79,753 pairs
+    in waves, two classes, FP32 orbitals on boxes): every pair converged to
+    the FP64 residual bar, the energy sum, and sampled pair energies of both
+    classes against the oracle."""
+    wl = S.c5_water512()
+    _say("[gpu] 512-water workload, multigrid-preconditioned CG in FP32 with FP64 replacement")
+    ctx = X.Exx.from_workload(wl, precond="mg", precision="fp32_refine")
+    phi = torch.empty((2048,) + tuple(reversed(wl.box)), dtype=torch.float32, device="cuda:0")
+    D = torch.empty_like(phi)
+    n = ctx.pairs(wl.orbitals.centers)
+    org = ctx.box_origins()
+    S.orbitals_torch(wl, device="cuda:0", origins=org, out=phi)
+    E, D = ctx.step(phi, D)
+    info = ctx.pair_info()
+    st = ctx.stats()
+    _say(f"[gpu] {n} pairs in {st['n_waves']} waves, mean iterations {info['iters'].mean():.1f}, "
+         f"replacements {st['outer_total'] / n:.1f} per pair, cg {st['cg_ms']:.0f} ms")
+    assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
+    assert info["iters"].mean() < 60
+    w = np.where(info["i"] == info["j"], 1.0, 2.0)
+    assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
+    self_p = np.nonzero(info["i"] == info["j"])[0]
+    other_p = np.nonzero(info["i"] != info["j"])[0]
+    pick = [int(self_p[7]), int(other_p[5]), int(other_p[-3])]
+    subs = [O.Subdomain(wl.n_grid, wl.cell, wl.r_pe[c], wl.r_me[c]) for c in (0, 1)]
+    orbs = sorted({int(info["i"][p]) for p in pick} | {int(info["j"][p]) for p in pick})
+    vals = S.orbitals_np(wl, orbs, origins=org).astype(np.float32).astype(np.float64)
+    phis = dict(zip(orbs, S.embed_boxes(vals, [org[k] for k in orbs], wl.n_grid)))
+
+    def ref(p):
+        i, j = int(info["i"][p]), int(info["j"][p])
+        return subs[0 if i == j else 1].solve_pair(phis[i], phis[j], info["origin"][p])
+
+    _say(f"[gpu] oracle on sampled pairs {pick}")
+    with cf.ThreadPoolExecutor(len(pick)) as ex:
+        refs = list(ex.map(ref, pick))
+    for p, r in zip(pick, refs):
+        assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
+    ctx.close()
