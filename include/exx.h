@@ -249,6 +249,25 @@ exx_status exx_box_origins(exx_ctx *ctx, int32_t *origins);
  * split). */
 exx_status exx_solve(exx_ctx *ctx, const void *phi, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): exx_solve
+ * with nothing allocated during the call.  The CG work vectors live in a
+ * fixed 128 MiB device array that the library defines once per GPU (held
+ * from module load until the process ends) instead of the context's
+ * buffers; the CG runs on as many work-groups as that array holds slots
+ * for (fewer than exx_solve when the subdomains are large), so it can be
+ * slower; results are the same bit for bit.  Launches are eager (params.graph
+ * is ignored) and only guess = EXX_GUESS_ZERO is accepted (EXX_EINVAL
+ * otherwise: the other guesses allocate).  EXX_EINVAL with a message if one
+ * CG slot of the current pair list needs more than the array holds.  Every
+ * call on one GPU shares that GPU's array, whatever the context: calls that
+ * overlap on one GPU race (serialize them).  Nothing in the array needs to
+ * start at zero; the previous call's contents are overwritten.  Everything
+ * else is as exx_solve (same call order, same ownership, asynchronous on
+ * `stream`; the per-wave CG timings of exx_stats are recorded only when an
+ * earlier exx_solve on the context created their events). */
+exx_status exx_solve_static(exx_ctx *ctx, const void *phi, void *stream);
+
 /* Enqueues D accumulation (Step V, Eq. Dxx_mlwf_omega: D^i += v_ij phi_j
  * and D^j += v_ij phi_i over the ME sphere of each pair) and the E reduction
  * (Eq. exx_omega) on `stream`, then synchronizes it.  dxx: device, same shape and dtype as phi, fully

@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
@@ -24,6 +25,25 @@ constexpr double kFD[4] = {-49.0 / 18.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0};
 // messages live in fixed buffers so that reporting a failure never allocates
 char g_setup_error[512] = "no error";
 
+// Device address of the fixed CG scratch array on each device, taken once per
+// device (with that device current) by the first exx_setup on it.
+constexpr int kMaxDevices = 64;
+void *g_static_scratch[kMaxDevices] = {};
+std::mutex g_static_mutex;
+
+hipError_t static_scratch_for(int device, void **ptr)
+{
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_static_mutex);
+    if (!g_static_scratch[device]) {
+        void *p = nullptr;
+        const hipError_t e = static_scratch_address(&p);
+        if (e != hipSuccess) return e;
+        g_static_scratch[device] = p;
+    }
+    *ptr = g_static_scratch[device];
+    return hipSuccess;
+}
 
 // Fortran NINT: nearest integer, halves away from zero.
 long nint_away(double v) { return (long)(v >= 0.0 ? std::floor(v + 0.5) : -std::floor(-v + 0.5)); }
@@ -148,6 +168,8 @@ struct exx_ctx {
     std::vector<hipEvent_t> ev_cg;   // per wave: around the CG launch
     bool have_events = false;
     bool solved_once = false;
+    int last_grid = 0;           // CG work-groups of the last solve
+    bool last_cg_timed = false;  // the last solve recorded per-wave CG events
 };
 
 namespace {
@@ -1079,6 +1101,11 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         if (hipGetDeviceProperties(&prop, device) != hipSuccess)
             return bail(fail(c, EXX_EDEVICE, "hipGetDeviceProperties failed"));
         c->n_cu = prop.multiProcessorCount;
+        {
+            void *sp = nullptr;
+            if (static_scratch_for(device, &sp) != hipSuccess)
+                return bail(fail(c, EXX_EDEVICE, "hipGetSymbolAddress of the static CG scratch failed"));
+        }
         for (int k = 0; k < ncls; ++k) {
             exx_status st = upload_class(c, c->cls[k]);
             if (st != EXX_OK) return bail(st);
@@ -1504,13 +1531,48 @@ static exx_status exx_pairs_spread_body(exx_ctx *c, int32_t n_orb, const double 
     return pairs_common(c, n_orb, C, spreads, n_pairs);
 }
 
-static exx_status exx_solve_body(exx_ctx *c, const void *phi, void *stream)
+// exx_solve, or with fixed_scratch the allocation-free exx_solve_static: the
+// CG work vectors in the device's fixed scratch array, the CG grid cut to the
+// slots it holds, eager launches only, zero initial guess only.
+static exx_status solve_impl(exx_ctx *c, const void *phi, void *stream, bool fixed_scratch)
 {
-    if (!c) return fail(nullptr, EXX_EINVAL, "exx_solve: ctx is NULL");
-    if (c->state < 2) return fail(c, EXX_ESTATE, "exx_solve before exx_pairs");
-    if (!phi) return fail(c, EXX_EINVAL, "exx_solve: phi is NULL");
+    const char *who = fixed_scratch ? "exx_solve_static" : "exx_solve";
+    if (!c) return fail(nullptr, EXX_EINVAL, "%s: ctx is NULL", who);
+    if (c->state < 2) return fail(c, EXX_ESTATE, "%s before exx_pairs", who);
+    if (!phi) return fail(c, EXX_EINVAL, "%s: phi is NULL", who);
+    if (fixed_scratch && c->prm.guess != EXX_GUESS_ZERO)
+        return fail(c, EXX_EINVAL, "exx_solve_static: only the zero initial guess (the other guesses allocate)");
     HIPCHK(c, hipSetDevice(c->device));
     hipStream_t s = (hipStream_t)stream;
+    int cg_grid = c->grid;
+    double *scr64 = c->d_scratch.p, *scr_mg = c->d_mg_scratch.p;
+    float *scr32 = c->d_scratch32.p;
+    if (fixed_scratch) {
+        // per CG slot: the FP64 vectors, the FP32 vectors, the coarse levels,
+        // each region 256-byte aligned
+        const bool mg = c->prm.precond == EXX_PRECOND_MG;
+        const bool mixed = c->prm.precision == EXX_FP32_REFINE;
+        auto up256 = [](size_t b) { return (b + 255) / 256 * 256; };
+        const size_t b64 = (size_t)(mg ? 4 : 3) * c->slot_n * sizeof(double);
+        const size_t b32 = mixed ? (size_t)4 * c->slot_n * sizeof(float) : 0;
+        const size_t bmg = mg ? (size_t)mg_slot_doubles(c) * sizeof(double) : 0;
+        const size_t cap = static_scratch_bytes();
+        const size_t need1 = up256(b64) + up256(b32) + up256(bmg);
+        if (need1 > cap)
+            return fail(c, EXX_EINVAL, "exx_solve_static: one CG slot needs %zu bytes, the fixed scratch holds %zu",
+                        need1, cap);
+        int slots = (int)std::min<size_t>((size_t)c->grid, cap / need1);
+        while (slots > 1 && up256((size_t)slots * b64) + up256((size_t)slots * b32) + up256((size_t)slots * bmg) > cap)
+            --slots;
+        void *base = nullptr;
+        if (static_scratch_for(c->device, &base) != hipSuccess || !base)
+            return fail(c, EXX_EDEVICE, "exx_solve_static: no fixed scratch address on device %d", c->device);
+        char *b = static_cast<char *>(base);
+        scr64 = reinterpret_cast<double *>(b);
+        scr32 = reinterpret_cast<float *>(b + up256((size_t)slots * b64));
+        scr_mg = reinterpret_cast<double *>(b + up256((size_t)slots * b64) + up256((size_t)slots * b32));
+        cg_grid = slots;
+    }
     SolveArgs a{};
     for (int k = 0; k < c->n_cls; ++k) a.cls[k] = class_dev(c->cls[k]);
     a.pair_gc = c->d_gc.p;
@@ -1525,8 +1587,8 @@ static exx_status exx_solve_body(exx_ctx *c, const void *phi, void *stream)
     a.nz = c->prm.n_grid[2];
     a.ngrid = (long long)a.nx * a.ny * a.nz;
     a.vout = c->d_vout.p;
-    a.scratch = c->d_scratch.p;
-    a.scratch32 = c->d_scratch32.p;
+    a.scratch = scr64;
+    a.scratch32 = scr32;
     a.rhs = c->d_rhs.p;
     a.rho_keep = c->prm.keep_intermediates ? c->d_rho_keep.p : nullptr;
     a.slot_n = c->slot_n;
@@ -1545,7 +1607,7 @@ static exx_status exx_solve_body(exx_ctx *c, const void *phi, void *stream)
     a.inner_tol = c->prm.inner_rtol;
     a.maxit = c->prm.cg_max_iter;
     ylm_norms(a.ylm_norm);
-    mg_args(c, a, c->d_mg_scratch.p);
+    mg_args(c, a, scr_mg);
     // initial guess from earlier steps: constant, linear or quadratic
     // extrapolation over the consecutive levels that hold the same (i, j);
     // or from the learned model
@@ -1644,7 +1706,7 @@ static exx_status exx_solve_body(exx_ctx *c, const void *phi, void *stream)
             if (events && w0 == 0 && (e = hipEventRecord(c->ev[5], st)) != hipSuccess) return e;
             const size_t wi = (size_t)(w0 / c->wave_n);
             if (events && (e = hipEventRecord(c->ev_cg[2 * wi], st)) != hipSuccess) return e;
-            if ((e = launch_cg(c->var, a, std::min(c->grid, a.wave_n), c->lds_bytes, st)) != hipSuccess) return e;
+            if ((e = launch_cg(c->var, a, std::min(cg_grid, a.wave_n), c->lds_bytes, st)) != hipSuccess) return e;
             if (events && (e = hipEventRecord(c->ev_cg[2 * wi + 1], st)) != hipSuccess) return e;
             if ((e = launch_pair_energy(a, st)) != hipSuccess) return e;
             if (use_guess &&
@@ -1666,7 +1728,7 @@ static exx_status exx_solve_body(exx_ctx *c, const void *phi, void *stream)
     // the context's own stream and replayed while the pairs, phi and the
     // model's buffers are unchanged; the caller's stream and the graph
     // stream are ordered by events.
-    c->last_graph = c->prm.graph && !use_guess;
+    c->last_graph = c->prm.graph && !use_guess && !fixed_scratch;
     if (c->last_graph) {
         if (!c->gstream) HIPCHK(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking));
         if (learned) HIPCHK(c, net_reserve(c->net, (int)std::min<int64_t>(c->wave_n, c->n_pairs), c->net_D));
@@ -1696,15 +1758,20 @@ static exx_status exx_solve_body(exx_ctx *c, const void *phi, void *stream)
         HIPCHK(c, hipStreamWaitEvent(s, c->ev[1], 0));
         ++c->graph_launches;
     } else {
-        while (c->ev_cg.size() < (size_t)2 * c->n_waves) {
+        // per-wave CG events (created once; the allocation-free solve uses
+        // them only when an earlier exx_solve has created enough)
+        const bool cg_events = !fixed_scratch || c->ev_cg.size() >= (size_t)2 * c->n_waves;
+        while (!fixed_scratch && c->ev_cg.size() < (size_t)2 * c->n_waves) {
             hipEvent_t e = nullptr;
             HIPCHK(c, hipEventCreate(&e));
             c->ev_cg.push_back(e);
         }
         HIPCHK(c, hipEventRecord(c->ev[0], s));
-        HIPCHK(c, enqueue(s, true));
+        HIPCHK(c, enqueue(s, cg_events));
         HIPCHK(c, hipEventRecord(c->ev[1], s));
     }
+    c->last_grid = cg_grid;
+    c->last_cg_timed = !c->last_graph && (!fixed_scratch || c->ev_cg.size() >= (size_t)2 * c->n_waves);
     if (use_guess) {
         // rotate the ring: this step's level becomes the most recent; the
         // PREVIOUS guess keeps one level, the extrapolations three
@@ -1754,7 +1821,7 @@ static exx_status exx_stats_body(exx_ctx *c, exx_stats_t *st)
     std::memset(st, 0, sizeof *st);
     st->n_pairs = c->n_pairs;
     st->n_self = c->n_self;
-    st->solve_grid = c->grid;
+    st->solve_grid = c->solved_once ? c->last_grid : c->grid;
     st->solve_block = c->block;
     st->cg_cols = c->var.zmarch ? c->var.cols : 0;
     st->cg_inflight[0] = c->var.pf64;
@@ -1847,7 +1914,7 @@ static exx_status exx_stats_body(exx_ctx *c, exx_stats_t *st)
         if (hipEventElapsedTime(&ms, c->ev[0], c->ev[6]) == hipSuccess) st->prep_ms = ms;
         if (hipEventElapsedTime(&ms, c->ev[6], c->ev[5]) == hipSuccess) st->guess_ms = ms;
     }
-    if (!c->last_graph && c->ev_cg.size() >= (size_t)2 * c->n_waves) {
+    if (c->last_cg_timed && c->ev_cg.size() >= (size_t)2 * c->n_waves) {
         double tot = 0.0;
         bool ok = true;
         for (int w = 0; w < c->n_waves && ok; ++w) {
@@ -2063,7 +2130,12 @@ exx_status exx_pairs_spread(exx_ctx *c, int32_t n_orb, const double *C, const do
 
 exx_status exx_solve(exx_ctx *c, const void *phi, void *stream)
 {
-    EXX_GUARDED(c, exx_solve_body(c, phi, stream));
+    EXX_GUARDED(c, solve_impl(c, phi, stream, false));
+}
+
+exx_status exx_solve_static(exx_ctx *c, const void *phi, void *stream)
+{
+    EXX_GUARDED(c, solve_impl(c, phi, stream, true));
 }
 
 exx_status exx_energy_potential(exx_ctx *c, double *e_xx, void *dxx, void *stream)

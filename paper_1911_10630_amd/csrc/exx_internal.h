@@ -266,6 +266,11 @@ hipError_t launch_save_history(const double *vout, const long long *out_off, con
                                const int4 *pair_gc, int4 n_pe, int wave_begin, int wave_n, float *hist,
                                hipStream_t s);
 
+// Fixed device scratch of the allocation-free solve (exx_kernels.hip): its
+// size, and its device address on the current device.
+size_t static_scratch_bytes();
+hipError_t static_scratch_address(void **ptr);
+
 // Learned initial guess (exx_net.hip).  The net reads a pair's right-hand
 // side on a coarse cube (coarsening factor f, edge D coarse cells, fine
 // offsets [-fD/2, fD/2) per axis) and writes its PE guess into vout.

@@ -1845,6 +1845,23 @@ __global__ void k_zero_int(int *p, int n)
 }
 
 // ---------------------------------------------------------------------------
+// fixed device scratch of the allocation-free solve
+// ---------------------------------------------------------------------------
+
+// The CG work vectors of exx_solve_static live here instead of in the
+// context's buffers.  Each GPU the library runs on holds its own copy from
+// module load until the process ends.  In host code the name is a host-side
+// stand-in, never a device address: the address comes from
+// hipGetSymbolAddress, per device (static_scratch_address).
+constexpr size_t kStaticScratchBytes = (size_t)128 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+size_t static_scratch_bytes() { return kStaticScratchBytes; }
+
+// Device address of this GPU's scratch array; call with the device current.
+hipError_t static_scratch_address(void **ptr) { return hipGetSymbolAddress(ptr, HIP_SYMBOL(scratch)); }
+
+// ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
 

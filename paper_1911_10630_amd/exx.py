@@ -28,7 +28,7 @@ EXPORTS = ["exx_default_params", "exx_setup", "exx_pairs", "exx_solve", "exx_ene
            "exx_pair_info", "exx_debug_pair", "exx_last_error", "exx_destroy", "exx_model_init", "exx_model_train",
            "exx_model_save", "exx_load_model", "exx_model_edge", "exx_model_conv", "exx_model_wgrad",
            "exx_box_origins", "exx_pair_owners", "exx_pairs_spread",
-           "exx_pair_class", "exx_stream_rates"]
+           "exx_pair_class", "exx_stream_rates", "exx_solve_static"]
 
 
 class ExxParams(C.Structure):
@@ -83,6 +83,8 @@ def load() -> C.CDLL:
     L.exx_setup.argtypes = [C.POINTER(ExxParams), C.c_int, C.POINTER(vp)]
     L.exx_pairs.argtypes = [vp, i32, vp, C.POINTER(i64)]
     L.exx_solve.argtypes = [vp, vp, vp]
+    L.exx_solve_static.argtypes = [vp, vp, vp]
+    L.exx_solve_static.restype = C.c_int
     L.exx_energy_potential.argtypes = [vp, dp, vp, vp]
     L.exx_stats.argtypes = [vp, C.POINTER(ExxStats)]
     L.exx_pair_info.argtypes = [vp] + [vp] * 7
@@ -242,6 +244,13 @@ class Exx:
         self._check_grid(phi, "phi")
         self._phi = phi
         self._check(load().exx_solve(self._h, _ptr(phi), _stream_handle(stream, phi.device)))
+
+    def solve_static(self, phi, stream=None):
+        """exx_solve_static: the solve with its CG work vectors in the library's
+        fixed device scratch (nothing allocated during the call)."""
+        self._check_grid(phi, "phi")
+        self._phi = phi
+        self._check(load().exx_solve_static(self._h, _ptr(phi), _stream_handle(stream, phi.device)))
 
     def energy_potential(self, dxx, stream=None, allow_noconv=False) -> float:
         self._check_grid(dxx, "dxx")
