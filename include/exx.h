@@ -24,7 +24,8 @@
  * fraction a_x (Eq. hyb); E_xx and D are returned unscaled.
  *
  * Timing fields of exx_stats are HIP-event times; in graph mode only the
- * whole solve is timed (prep_ms, cg_ms, guess_ms read -1).
+ * whole solve is timed that way (prep_ms, cg_ms, guess_ms read -1), and the
+ * CG kernel's own span is cg_clock_ms (device wall clock, either mode).
  *
  * Call order: exx_setup -> exx_pairs -> exx_solve -> exx_energy_potential
  * (then exx_pairs or exx_solve again for the next step).  Out-of-order calls
@@ -118,7 +119,8 @@ typedef struct {
      * uses the classes class_r_pe[k] / class_r_me[k] (r_pe strictly
      * ascending, r_me - r_pe >= n max(h) each) and exx_pairs_spread, which
      * puts each pair on the smallest class that covers Omega_ij (see there);
-     * r_pe / r_me are then ignored.  The learned guess needs n_classes = 0. */
+     * r_pe / r_me are then ignored.  The learned guess runs on every class
+     * with one coarse cube, sized for the largest class. */
     int32_t n_classes;
     double  class_r_pe[4], class_r_me[4];
     double  omega_scale;    /* radius of Omega_i = omega_scale * spread_i      */
@@ -165,6 +167,10 @@ typedef struct {
     int32_t cg_inflight[2];  /* planes of loads in flight in the CG kernel's
                                 FP64 / FP32 passes (1 or 2)                    */
     int32_t cg_cols32;       /* columns per thread of the FP32 passes          */
+    double  cg_clock_ms;     /* last solve: the CG launches' spans, first
+                                work-group start to last work-group end on the
+                                device wall clock, summed over waves (graph
+                                mode included); -1 if unavailable            */
 } exx_stats_t;
 
 /* Fills *p with the paper's method defaults (n = 3, l_max = 6, FP64, zero
@@ -311,9 +317,10 @@ exx_status exx_debug_pair(exx_ctx *ctx, int64_t pair, double *v_pe, double *v_sh
 exx_status exx_model_init(exx_ctx *ctx, int32_t coarsen, uint64_t seed);
 
 /* Adam training on the pairs of the last solve: input its right-hand sides,
- * target its converged potentials on ME.  Needs the last exx_solve to have
- * run in one wave (every right-hand side resident), else EXX_ESTATE.
- * epochs >= 1, 1 <= batch <= n_pairs, lr > 0.  *loss receives the mean
+ * target its converged potentials on ME.  The pairs are those still
+ * resident: every pair, or the last wave's when the solve ran in waves (the
+ * earlier waves' right-hand sides are released).  epochs >= 1,
+ * 1 <= batch <= resident pairs, lr > 0.  *loss receives the mean
  * masked squared error of the last epoch (normalized units: potential over
  * RMS(b) h^2, per coarse cell that meets ME).  epochs = 0 only evaluates
  * that error over every pair, without updating (lr ignored).  Synchronizes

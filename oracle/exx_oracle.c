@@ -529,3 +529,105 @@ int o_solve_pairs(const int n[3], const double cell[3], const double r_pe[2], co
     o_sub_free(cls[0]); o_sub_free(cls[1]);
     return nthreads;
 }
+
+/* An explicit list of pairs, each on its own subdomain class k = cls[t]
+ * (radii r_pe[k], r_me[k], k < n_cls): the per-pair subdomains of the
+ * paper's outlook (Sec. IV A), each class built by Alg. 2 as the two fixed
+ * ones are.  Returns the number of threads used, or -1. */
+int o_solve_pairs_classed(const int n[3], const double cell[3], int n_cls, const double *r_pe, const double *r_me,
+                          const double *C, const double *const *phi_ptrs, int n_list, const int *pi, const int *pj,
+                          const int *cls, double tol, int maxit, int nthreads, double *e_out, int *iters_out,
+                          int *conv_out, double *relres_out)
+{
+    if (n_cls < 1 || n_cls > 8) return -1;
+    osub *sub[8] = {NULL};
+    for (int k = 0; k < n_cls; ++k)
+        if (o_sub_build(n, cell, r_pe[k], r_me[k], &sub[k])) {
+            for (int q = 0; q < k; ++q) o_sub_free(sub[q]);
+            return -1;
+        }
+    for (int t = 0; t < n_list; ++t)
+        if (cls[t] < 0 || cls[t] >= n_cls) {
+            for (int k = 0; k < n_cls; ++k) o_sub_free(sub[k]);
+            return -1;
+        }
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#else
+    nthreads = 1;
+#endif
+#pragma omp parallel for schedule(dynamic, 1) num_threads(nthreads)
+    for (int t = 0; t < n_list; ++t) {
+        int i = pi[t], j = pj[t];
+        int gc[3];
+        o_pair_origin(C + 3 * i, C + 3 * j, cell, n, gc);
+        o_solve_pair(sub[cls[t]], phi_ptrs[i], phi_ptrs[j], gc, tol, maxit, NULL, NULL, NULL, NULL, NULL, NULL,
+                     &e_out[t], &iters_out[t], &conv_out[t], &relres_out[t]);
+    }
+    for (int k = 0; k < n_cls; ++k) o_sub_free(sub[k]);
+    return nthreads;
+}
+
+/* D^k (Eq. Dxx_mlwf_omega) over an explicit list of pairs that involve
+ * orbital k, each on its class cls[t]: the pairs are solved in parallel and
+ * their contributions v phi_other added in list order (so, for the list of
+ * every pair of k in pair order, the sum runs as the whole step's does).
+ * Dk: [Nz][Ny][Nx], overwritten.  Returns 0, or -1. */
+int o_dxx_orbital(const int n[3], const double cell[3], int n_cls, const double *r_pe, const double *r_me,
+                  const double *C, const double *const *phi_ptrs, int n_list, const int *pi, const int *pj,
+                  const int *cls, int k, double tol, int maxit, int nthreads, double *Dk)
+{
+    if (n_cls < 1 || n_cls > 8) return -1;
+    for (int t = 0; t < n_list; ++t)
+        if ((pi[t] != k && pj[t] != k) || cls[t] < 0 || cls[t] >= n_cls) return -1;
+    osub *sub[8] = {NULL};
+    int max_me = 0;
+    for (int q = 0; q < n_cls; ++q) {
+        if (o_sub_build(n, cell, r_pe[q], r_me[q], &sub[q])) {
+            for (int u = 0; u < q; ++u) o_sub_free(sub[u]);
+            return -1;
+        }
+        if (sub[q]->n_me > max_me) max_me = sub[q]->n_me;
+    }
+    size_t ngrid = (size_t)n[0] * n[1] * n[2];
+    memset(Dk, 0, sizeof(double) * ngrid);
+#ifdef _OPENMP
+    if (nthreads <= 0) nthreads = omp_get_max_threads();
+#else
+    nthreads = 1;
+#endif
+    int batch = nthreads;
+    double **xs = (double **)calloc(batch, sizeof(double *)), **vs = (double **)calloc(batch, sizeof(double *));
+    for (int t = 0; t < batch; ++t) {
+        xs[t] = (double *)malloc(sizeof(double) * max_me);
+        vs[t] = (double *)malloc(sizeof(double) * max_me);
+    }
+    for (int p0 = 0; p0 < n_list; p0 += batch) {
+        int nb = n_list - p0 < batch ? n_list - p0 : batch;
+#pragma omp parallel for schedule(static, 1) num_threads(nthreads)
+        for (int t = 0; t < nb; ++t) {
+            int p = p0 + t, i = pi[p], j = pj[p];
+            int gc[3], it, cv;
+            double e, rr;
+            o_pair_origin(C + 3 * i, C + 3 * j, cell, n, gc);
+            o_solve_pair(sub[cls[p]], phi_ptrs[i], phi_ptrs[j], gc, tol, maxit, xs[t], vs[t], NULL, NULL, NULL, NULL,
+                         &e, &it, &cv, &rr);
+        }
+        for (int t = 0; t < nb; ++t) {   /* list order */
+            int p = p0 + t, i = pi[p], j = pj[p];
+            const osub *s = sub[cls[p]];
+            int gc[3];
+            o_pair_origin(C + 3 * i, C + 3 * j, cell, n, gc);
+            const double *other = phi_ptrs[i == k ? j : i];
+            for (int q = 0; q < s->n_me; ++q) {
+                size_t g = o_gidx(s, gc, q);
+                double v = q < s->n_pe ? xs[t][q] : vs[t][q - s->n_pe];
+                Dk[g] += v * other[g];
+            }
+        }
+    }
+    for (int t = 0; t < batch; ++t) { free(xs[t]); free(vs[t]); }
+    free(xs); free(vs);
+    for (int q = 0; q < n_cls; ++q) o_sub_free(sub[q]);
+    return 0;
+}

@@ -70,6 +70,12 @@ def lib():
         L.o_solve_pairs.restype = C.c_int
         L.o_solve_pairs.argtypes = [_ip, _dp, _dp, _dp, _dp, C.c_void_p, C.c_int, _ip, _ip, C.c_double,
                                     C.c_int, C.c_int, _dp, _ip, _ip, _dp]
+        L.o_solve_pairs_classed.restype = C.c_int
+        L.o_solve_pairs_classed.argtypes = [_ip, _dp, C.c_int, _dp, _dp, _dp, C.c_void_p, C.c_int, _ip, _ip, _ip,
+                                            C.c_double, C.c_int, C.c_int, _dp, _ip, _ip, _dp]
+        L.o_dxx_orbital.restype = C.c_int
+        L.o_dxx_orbital.argtypes = [_ip, _dp, C.c_int, _dp, _dp, _dp, C.c_void_p, C.c_int, _ip, _ip, _ip, C.c_int,
+                                    C.c_double, C.c_int, C.c_int, _dp]
         _lib = L
     return _lib
 
@@ -318,6 +324,55 @@ def solve_pairs(n, cell, r_pe, r_me, centers, phi_by_orbital: dict, pi: Sequence
     if used < 0:
         raise ValueError("o_solve_pairs failed")
     return dict(e=e, iters=it, converged=cv, relres=rr, threads=used)
+
+
+def _phi_table(centers, phi_by_orbital):
+    Cc = np.ascontiguousarray(centers, np.float64)
+    keep = {k: np.ascontiguousarray(v, np.float64) for k, v in phi_by_orbital.items()}
+    ptrs = (C.c_void_p * Cc.shape[0])()
+    for k, v in keep.items():
+        ptrs[k] = v.ctypes.data
+    return Cc, keep, ptrs
+
+
+def solve_pairs_classed(n, cell, classes, centers, phi_by_orbital: dict, pi, pj, cls, tol=1e-10, maxit=100000,
+                        nthreads=0):
+    """Solve an explicit pair list with each pair on its own subdomain class:
+    classes = [(r_pe, r_me), ...], cls[t] the class of pair t (the per-pair
+    subdomains of Sec. IV A)."""
+    L = lib()
+    Cc, keep, ptrs = _phi_table(centers, phi_by_orbital)
+    pi = np.ascontiguousarray(pi, np.int32)
+    pj = np.ascontiguousarray(pj, np.int32)
+    cls = np.ascontiguousarray(cls, np.int32)
+    m = len(pi)
+    rpe = np.ascontiguousarray([c[0] for c in classes], np.float64)
+    rme = np.ascontiguousarray([c[1] for c in classes], np.float64)
+    e, it, cv, rr = np.zeros(m), np.zeros(m, np.int32), np.zeros(m, np.int32), np.zeros(m)
+    used = L.o_solve_pairs_classed(_i3(n), _d3(cell), len(classes), rpe, rme, Cc.ravel(), ptrs, m, pi, pj, cls, tol,
+                                   maxit, nthreads, e, it, cv, rr)
+    if used < 0:
+        raise ValueError("o_solve_pairs_classed failed")
+    return dict(e=e, iters=it, converged=cv, relres=rr, threads=used)
+
+
+def dxx_orbital(n, cell, classes, centers, phi_by_orbital: dict, pi, pj, cls, k, tol=1e-10, maxit=100000,
+                nthreads=0):
+    """D^k (Eq. Dxx_mlwf_omega) on the full grid from an explicit list of the
+    pairs involving orbital k (each on class cls[t]), summed in list order."""
+    L = lib()
+    Cc, keep, ptrs = _phi_table(centers, phi_by_orbital)
+    pi = np.ascontiguousarray(pi, np.int32)
+    pj = np.ascontiguousarray(pj, np.int32)
+    cls = np.ascontiguousarray(cls, np.int32)
+    rpe = np.ascontiguousarray([c[0] for c in classes], np.float64)
+    rme = np.ascontiguousarray([c[1] for c in classes], np.float64)
+    Dk = np.zeros(tuple(int(v) for v in reversed(list(n))))
+    rc = L.o_dxx_orbital(_i3(n), _d3(cell), len(classes), rpe, rme, Cc.ravel(), ptrs, len(pi), pi, pj, cls, int(k),
+                         tol, maxit, nthreads, Dk.reshape(-1))
+    if rc != 0:
+        raise ValueError("o_dxx_orbital failed")
+    return Dk
 
 
 # ---------------------------------------------------------------------------

@@ -122,6 +122,8 @@ struct exx_ctx {
     int owner_sweeps = 0;
     DevBuf<double> d_vout, d_q, d_e, d_relres, d_scratch, d_E, d_rhs, d_rho_keep;
     DevBuf<int> d_iters, d_outer, d_conv, d_counter;
+    DevBuf<unsigned long long> d_clock;   // per wave: first start, last end of its CG launch
+    int clock_khz = 0;                    // device wall-clock rate
     DevBuf<float> d_scratch32;
     DevBuf<double> d_mg_scratch;
 
@@ -146,7 +148,7 @@ struct exx_ctx {
     // learned guess
     ExxNet *net = nullptr;
     int net_D = 0;           // coarse cube edge for this context's classes
-    DevBuf<unsigned char> d_bnd[2];   // per class: PE points whose stencil leaves PE
+    DevBuf<unsigned char> d_bnd[KMAX];   // per class: PE points whose stencil leaves PE
     double guess_ms = 0.0;   // last solve: guess kernels or net inference of wave 0
 
     int block = 256, grid = 0, slots = 0, wave_n = 0, n_waves = 0;
@@ -627,8 +629,7 @@ int pe_rmax(const exx_ctx *c)
 NetPairArgs net_args(const exx_ctx *c)
 {
     NetPairArgs n{};
-    n.cls[0] = class_dev(c->cls[0]);
-    n.cls[1] = class_dev(c->cls[1]);
+    for (int k = 0; k < c->n_cls; ++k) n.cls[k] = class_dev(c->cls[k]);
     n.pair_gc = c->d_gc.p;
     n.out_off = c->d_off.p;
     n.rhs = c->d_rhs.p;
@@ -637,8 +638,7 @@ NetPairArgs net_args(const exx_ctx *c)
     n.vout = c->d_vout.p;
     n.h2 = std::cbrt(c->h[0] * c->h[1] * c->h[2]);
     n.h2 *= n.h2;
-    n.bnd[0] = c->d_bnd[0].p;
-    n.bnd[1] = c->d_bnd[1].p;
+    for (int k = 0; k < c->n_cls; ++k) n.bnd[k] = c->d_bnd[k].p;
     return n;
 }
 
@@ -1052,8 +1052,6 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
     if (p->n_classes != 0 && (p->n_classes < 2 || p->n_classes > EXX_MAX_CLASSES))
         return fail(nullptr, EXX_EINVAL, "n_classes = %d: 0 or 2..%d", p->n_classes, EXX_MAX_CLASSES);
     const bool classed = p->n_classes >= 2;
-    if (classed && p->guess == EXX_GUESS_LEARNED)
-        return fail(nullptr, EXX_EINVAL, "the learned guess needs n_classes = 0 (two classes)");
     if (classed && !(p->omega_scale > 0.0 && std::isfinite(p->omega_scale)))
         return fail(nullptr, EXX_EINVAL, "omega_scale must be positive");
     const int ncls = classed ? p->n_classes : 2;
@@ -1101,6 +1099,8 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out)
         if (hipGetDeviceProperties(&prop, device) != hipSuccess)
             return bail(fail(c, EXX_EDEVICE, "hipGetDeviceProperties failed"));
         c->n_cu = prop.multiProcessorCount;
+        if (hipDeviceGetAttribute(&c->clock_khz, hipDeviceAttributeWallClockRate, device) != hipSuccess)
+            c->clock_khz = 0;
         {
             void *sp = nullptr;
             if (static_scratch_for(device, &sp) != hipSuccess)
@@ -1496,6 +1496,7 @@ exx_status pairs_common(exx_ctx *c, int32_t n_orb, const double *C, const double
         } else {
             dev_free(c->d_queue);
         }
+        if ((st = dev_reserve(c, c->d_clock, (size_t)2 * ((c->n_pairs + w - 1) / w))) != EXX_OK) return st;
         if ((st = dev_reserve(c, c->d_vout, (size_t)vmax)) != EXX_OK) return st;
         if ((st = dev_reserve(c, c->d_rhs, (size_t)w * c->slot_n)) != EXX_OK) return st;
         if (w < c->n_pairs) {
@@ -1702,9 +1703,10 @@ static exx_status solve_impl(exx_ctx *c, const void *phi, void *stream, bool fix
                 na.wave_begin = a.wave_begin;
                 if ((e = net_infer(c->net, na, a.wave_n, c->net_D, nullptr, st)) != hipSuccess) return e;
             }
-            if ((e = launch_zero_int(c->d_counter.p, 1, st)) != hipSuccess) return e;
-            if (events && w0 == 0 && (e = hipEventRecord(c->ev[5], st)) != hipSuccess) return e;
             const size_t wi = (size_t)(w0 / c->wave_n);
+            a.clock = c->d_clock.p + 2 * wi;
+            if ((e = launch_wave_reset(c->d_counter.p, a.clock, st)) != hipSuccess) return e;
+            if (events && w0 == 0 && (e = hipEventRecord(c->ev[5], st)) != hipSuccess) return e;
             if (events && (e = hipEventRecord(c->ev_cg[2 * wi], st)) != hipSuccess) return e;
             if ((e = launch_cg(c->var, a, std::min(cg_grid, a.wave_n), c->lds_bytes, st)) != hipSuccess) return e;
             if (events && (e = hipEventRecord(c->ev_cg[2 * wi + 1], st)) != hipSuccess) return e;
@@ -1923,6 +1925,20 @@ static exx_status exx_stats_body(exx_ctx *c, exx_stats_t *st)
         }
         if (ok) st->cg_ms = tot;   // the persistent CG kernel alone, summed over waves
     }
+    st->cg_clock_ms = -1.0;
+    if (c->clock_khz > 0 && c->d_clock.p && c->n_waves > 0) {
+        std::vector<unsigned long long> ck((size_t)2 * c->n_waves);
+        if (hipMemcpy(ck.data(), c->d_clock.p, ck.size() * sizeof(unsigned long long), hipMemcpyDeviceToHost) ==
+            hipSuccess) {
+            double tot = 0.0;
+            bool ok = true;
+            for (int w = 0; w < c->n_waves; ++w) {
+                ok = ok && ck[2 * w + 1] >= ck[2 * w];
+                tot += (double)(ck[2 * w + 1] - ck[2 * w]);
+            }
+            if (ok) st->cg_clock_ms = tot / c->clock_khz;
+        }
+    }
     if (hipEventElapsedTime(&ms, c->ev[2], c->ev[3]) == hipSuccess) st->dxx_ms = ms;
     if (hipEventElapsedTime(&ms, c->ev[3], c->ev[4]) == hipSuccess) st->energy_ms = ms;
     // a timing that is not available (an event not recorded in this mode)
@@ -2001,7 +2017,6 @@ static exx_status exx_model_init_body(exx_ctx *c, int32_t coarsen, uint64_t seed
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_init: ctx is NULL");
     if (coarsen != 2 && coarsen != 4) return fail(c, EXX_EINVAL, "coarsen must be 2 or 4 (got %d)", coarsen);
-    if (c->prm.n_classes >= 2) return fail(c, EXX_EINVAL, "the learned guess needs n_classes = 0 (two classes)");
     HIPCHK(c, hipSetDevice(c->device));
     net_destroy(c->net);
     c->net = nullptr;
@@ -2013,7 +2028,7 @@ static exx_status exx_model_init_body(exx_ctx *c, int32_t coarsen, uint64_t seed
     }
     c->net = net;
     c->net_D = net_edge(coarsen, pe_rmax(c));
-    for (int k = 0; k < 2; ++k)
+    for (int k = 0; k < c->n_cls; ++k)
         if (!c->d_bnd[k].p) {
             exx_status st = dev_reserve(c, c->d_bnd[k], (size_t)c->cls[k].n_pe);
             if (st != EXX_OK) return st;
@@ -2026,7 +2041,6 @@ static exx_status exx_model_init_body(exx_ctx *c, int32_t coarsen, uint64_t seed
 static exx_status exx_load_model_body(exx_ctx *c, const void *weights, size_t bytes)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_load_model: ctx is NULL");
-    if (c->prm.n_classes >= 2) return fail(c, EXX_EINVAL, "the learned guess needs n_classes = 0 (two classes)");
     const int f = net_blob_coarsen(weights, bytes);
     if (f < 0)
         return fail(c, EXX_EINVAL, "exx_load_model: not a model blob of %zu bytes (got %zu)", net_model_bytes(), bytes);
@@ -2062,15 +2076,19 @@ static exx_status exx_model_train_body(exx_ctx *c, int32_t epochs, int32_t batch
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_train: ctx is NULL");
     if (!c->net) return fail(c, EXX_ESTATE, "exx_model_train: no model (exx_model_init or exx_load_model)");
     if (c->state < 3) return fail(c, EXX_ESTATE, "exx_model_train before exx_solve");
-    if (c->n_waves != 1)
-        return fail(c, EXX_ESTATE, "exx_model_train needs every right-hand side resident; the last solve ran in %d waves",
-                    c->n_waves);
-    if (epochs < 0 || batch < 1 || batch > c->n_pairs || !(lr > 0.0 || epochs == 0) || !loss)
-        return fail(c, EXX_EINVAL, "exx_model_train: need epochs >= 0, 1 <= batch <= n_pairs, lr > 0, loss");
+    // the pairs whose right-hand sides and potentials are still resident:
+    // every pair, or the last wave's when the solve ran in waves
+    const int64_t w0 = c->n_waves > 1 ? (int64_t)(c->n_waves - 1) * c->wave_n : 0;
+    const int64_t nt = c->n_pairs - w0;
+    if (epochs < 0 || batch < 1 || batch > nt || !(lr > 0.0 || epochs == 0) || !loss)
+        return fail(c, EXX_EINVAL, "exx_model_train: need epochs >= 0, 1 <= batch <= %lld (resident pairs), lr > 0, loss",
+                    (long long)nt);
     HIPCHK(c, hipSetDevice(c->device));
-    std::vector<int> pairs((size_t)c->n_pairs);
-    for (int64_t p = 0; p < c->n_pairs; ++p) pairs[p] = (int)p;
-    HIPCHK(c, net_train(c->net, net_args(c), pairs.data(), (int)c->n_pairs, c->net_D, epochs, batch, (float)lr,
+    std::vector<int> pairs((size_t)nt);
+    for (int64_t p = 0; p < nt; ++p) pairs[p] = (int)(w0 + p);
+    NetPairArgs na = net_args(c);
+    na.wave_begin = (int)w0;
+    HIPCHK(c, net_train(c->net, na, pairs.data(), (int)nt, c->net_D, epochs, batch, (float)lr,
                         (unsigned long long)seed, loss, (hipStream_t)stream));
     return EXX_OK;
 }
@@ -2228,11 +2246,12 @@ void exx_destroy(exx_ctx *c)
     net_destroy(c->net);
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->gstream) (void)hipStreamDestroy(c->gstream);
-    dev_free(c->d_bnd[0]); dev_free(c->d_bnd[1]);
+    for (auto &b : c->d_bnd) dev_free(b);
     dev_free(c->d_pC); dev_free(c->d_cell_of); dev_free(c->d_cell_start); dev_free(c->d_cell_items);
     dev_free(c->d_pcount); dev_free(c->d_pstart); dev_free(c->d_pij); dev_free(c->d_pgc);
     dev_free(c->d_mg_scratch);
     dev_free(c->d_E); dev_free(c->d_iters); dev_free(c->d_outer); dev_free(c->d_conv); dev_free(c->d_counter); dev_free(c->d_scratch32);
+    dev_free(c->d_clock);
     if (c->have_events)
         for (auto &e : c->ev)
             if (e) (void)hipEventDestroy(e);

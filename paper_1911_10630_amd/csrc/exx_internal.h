@@ -147,6 +147,8 @@ struct SolveArgs {
     int *conv_out;              // [n_pairs]
     double *relres_out;         // [n_pairs]
     int *counter;               // dynamic pair queue (wave-relative)
+    unsigned long long *clock;  // or null: {first start, last end} of the CG launch,
+                                // device wall clock (k_wave_reset initializes it)
     int wave_begin, wave_n;     // pairs [wave_begin, wave_begin + wave_n)
     int static_sched;           // 1: pair = block + k*grid, slot = block
     int guess;                  // 0 zero, 1 v already in vout (previous step)
@@ -261,6 +263,9 @@ hipError_t launch_dxx(const DxxArgs &a, int n_orb, int accumulate, hipStream_t s
 hipError_t launch_dxx_final(const DxxArgs &a, int n_orb, hipStream_t s);
 hipError_t launch_energy(const double *e, const int2 *ij, int n_pairs, double *out, hipStream_t s);
 hipError_t launch_zero_int(int *p, int n, hipStream_t s);
+// Before a CG launch: its queue counter to 0 and its clock pair to
+// {max, 0} (a kernel, so that it can be captured into a graph).
+hipError_t launch_wave_reset(int *counter, unsigned long long *clock, hipStream_t s);
 hipError_t launch_guess(const GuessArgs &a, int n_pairs, hipStream_t s);
 hipError_t launch_save_history(const double *vout, const long long *out_off, const long long *hist_off,
                                const int4 *pair_gc, int4 n_pe, int wave_begin, int wave_n, float *hist,
@@ -275,7 +280,7 @@ hipError_t static_scratch_address(void **ptr);
 // side on a coarse cube (coarsening factor f, edge D coarse cells, fine
 // offsets [-fD/2, fD/2) per axis) and writes its PE guess into vout.
 struct NetPairArgs {
-    ClassDev cls[2];
+    ClassDev cls[KMAX];         // subdomain classes (unused ones have n_pe = 0)
     const int4 *pair_gc;
     const long long *out_off;
     const double *rhs;          // right-hand sides of the wave, slot_n each
@@ -283,7 +288,7 @@ struct NetPairArgs {
     int wave_begin;
     double *vout;               // read (training targets) or written (guess)
     double h2;                  // output scale: RMS(v) ~ RMS(b) h^2
-    const unsigned char *bnd[2];// per class, per PE point: 1 if the stencil leaves PE
+    const unsigned char *bnd[KMAX];// per class, per PE point: 1 if the stencil leaves PE
 };
 
 struct ExxNet;

@@ -309,6 +309,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve(SolveArgs a)
 {
     __shared__ double red[BLOCK / 64];
     __shared__ int s_pair;
+    if (a.clock && threadIdx.x == 0) atomicMin(&a.clock[0], (unsigned long long)wall_clock64());
     for (int it = 0;; ++it) {
         int k;
         if (a.static_sched) {
@@ -322,6 +323,7 @@ __global__ __launch_bounds__(BLOCK) void k_solve(SolveArgs a)
         if (k >= a.wave_n) break;
         cg_one_pair<BLOCK>(a, a.queue ? a.queue[a.wave_begin + k] : a.wave_begin + k, blockIdx.x, red);
     }
+    if (a.clock && threadIdx.x == 0) atomicMax(&a.clock[1], (unsigned long long)wall_clock64());
 }
 
 // ---------------------------------------------------------------------------
@@ -1647,6 +1649,7 @@ __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
     extern __shared__ double lds_dyn[];
     __shared__ double red[T / 64];
     __shared__ int s_pair;
+    if (a.clock && threadIdx.x == 0) atomicMin(&a.clock[0], (unsigned long long)wall_clock64());
     int par = 0;
     int last_cls = -1;
     for (;;) {
@@ -1667,6 +1670,7 @@ __global__ __launch_bounds__(T, WPE) void k_cg_zmarch(SolveArgs a)
         }
         cg_zmarch_pair<T, K, KH, K32, KH32, MODE, PF64, PF32>(a, pair, blockIdx.x, lds_dyn, red, par);
     }
+    if (a.clock && threadIdx.x == 0) atomicMax(&a.clock[1], (unsigned long long)wall_clock64());
 }
 
 // ---------------------------------------------------------------------------
@@ -1702,6 +1706,21 @@ constexpr int DXX_BLOCK = 256;
 constexpr int DXX_PER_THREAD = 4;
 constexpr int DXX_TILE = DXX_BLOCK * DXX_PER_THREAD;
 
+// Do the cyclic index ranges [a0, a0 + alen) and [b0, b0 + blen) of Z_n meet
+// (a0, b0 in [0, n); lengths at most n)?
+__device__ __forceinline__ bool cyclic_meet(int a0, int alen, int b0, int blen, int n)
+{
+    int d1 = a0 - b0, d2 = b0 - a0;
+    d1 += d1 < 0 ? n : 0;
+    d2 += d2 < 0 ? n : 0;
+    return d1 < blen || d2 < alen;
+}
+
+// One work-group per tile of DXX_TILE consecutive points of orbital k's box.
+// A pair whose ME bounding box misses the tile's bounding box is skipped by
+// the whole work-group; a tile no pair of the wave reaches writes zeros (the
+// first wave, or D directly) or nothing (a later wave's partial sums are
+// unchanged).  Contributions are added in pair order either way.
 template <typename TO, bool ACC>
 __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
 {
@@ -1709,19 +1728,6 @@ __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
     const long long t0 = (long long)blockIdx.x * DXX_TILE;
     const OrbBox &B = a.box;
     const int4 ok_org = B.org[k];
-    double acc[DXX_PER_THREAD];
-    int gx[DXX_PER_THREAD], gy[DXX_PER_THREAD], gz[DXX_PER_THREAD];
-    bool ok[DXX_PER_THREAD];
-#pragma unroll
-    for (int e = 0; e < DXX_PER_THREAD; ++e) {
-        const long long li = t0 + e * DXX_BLOCK + threadIdx.x;
-        ok[e] = li < B.vol;
-        const long long ll = ok[e] ? li : 0;
-        gx[e] = wrap_n(ok_org.x + (int)(ll % B.bx), a.nx);
-        gy[e] = wrap_n(ok_org.y + (int)((ll / B.bx) % B.by), a.ny);
-        gz[e] = wrap_n(ok_org.z + (int)(ll / ((long long)B.bx * B.by)), a.nz);
-        acc[e] = ACC && !a.acc_first && ok[e] ? a.acc[(long long)k * B.vol + li] : 0.0;
-    }
     // this orbital's pairs inside [pair_lo, pair_hi): its list is ascending
     int lo = a.orb_ptr[k], hi = a.orb_ptr[k + 1];
     {
@@ -1732,8 +1738,60 @@ __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
         lo = l;
         hi = l2;
     }
+    // the tile's bounding box in global grid coordinates (start, length per axis)
+    const long long t1 = min(t0 + DXX_TILE, B.vol) - 1;
+    const long long bplane = (long long)B.bx * B.by;
+    const int lz0 = (int)(t0 / bplane), lz1 = (int)(t1 / bplane);
+    int ly0 = 0, ylen = B.by, lx0 = 0, xlen = B.bx;
+    if (lz0 == lz1) {
+        ly0 = (int)((t0 / B.bx) % B.by);
+        const int ly1 = (int)((t1 / B.bx) % B.by);
+        ylen = ly1 - ly0 + 1;
+        if (ly0 == ly1) {
+            lx0 = (int)(t0 % B.bx);
+            xlen = (int)(t1 % B.bx) - lx0 + 1;
+        }
+    }
+    const int zs = wrap_n(ok_org.z + lz0, a.nz), ys = wrap_n(ok_org.y + ly0, a.ny), xs = wrap_n(ok_org.x + lx0, a.nx);
+    const int zlen = lz1 - lz0 + 1;
+    auto meets = [&](int pair) -> bool {
+        const int4 pg = a.pair_gc[pair];
+        const ClassDev &g = a.cls[pg.w];
+        return cyclic_meet(zs, zlen, wrap_n(pg.z + g.mzlo, a.nz), g.mnz, a.nz) &&
+               cyclic_meet(ys, ylen, wrap_n(pg.y + g.mylo, a.ny), g.mny, a.ny) &&
+               cyclic_meet(xs, xlen, wrap_n(pg.x + g.mxlo, a.nx), g.mnx, a.nx);
+    };
+    bool any = false;
+    for (int pp = lo; pp < hi && !any; ++pp) any = meets(a.orb_pairs[pp]);
+    if (!any) {
+        if (ACC && !a.acc_first) return;
+#pragma unroll
+        for (int e = 0; e < DXX_PER_THREAD; ++e) {
+            const long long li = t0 + e * DXX_BLOCK + threadIdx.x;
+            if (li >= B.vol) continue;
+            if (ACC)
+                a.acc[(long long)k * B.vol + li] = 0.0;
+            else
+                static_cast<TO *>(a.dxx)[(long long)k * B.vol + li] = (TO)0.0;
+        }
+        return;
+    }
+    double acc[DXX_PER_THREAD];
+    int gx[DXX_PER_THREAD], gy[DXX_PER_THREAD], gz[DXX_PER_THREAD];
+    bool ok[DXX_PER_THREAD];
+#pragma unroll
+    for (int e = 0; e < DXX_PER_THREAD; ++e) {
+        const long long li = t0 + e * DXX_BLOCK + threadIdx.x;
+        ok[e] = li < B.vol;
+        const long long ll = ok[e] ? li : 0;
+        gx[e] = wrap_n(ok_org.x + (int)(ll % B.bx), a.nx);
+        gy[e] = wrap_n(ok_org.y + (int)((ll / B.bx) % B.by), a.ny);
+        gz[e] = wrap_n(ok_org.z + (int)(ll / bplane), a.nz);
+        acc[e] = ACC && !a.acc_first && ok[e] ? a.acc[(long long)k * B.vol + li] : 0.0;
+    }
     for (int pp = lo; pp < hi; ++pp) {
         const int pair = a.orb_pairs[pp];
+        if (!meets(pair)) continue;
         const int4 pg = a.pair_gc[pair];
         const int2 ij = a.pair_ij[pair];
         const int other = ij.x == k ? ij.y : ij.x;
@@ -1842,6 +1900,15 @@ __global__ void k_zero_int(int *p, int n)
 {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0;
+}
+
+__global__ void k_wave_reset(int *counter, unsigned long long *clock)
+{
+    if (threadIdx.x == 0) {
+        counter[0] = 0;
+        clock[0] = ~0ULL;
+        clock[1] = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -2026,6 +2093,12 @@ hipError_t launch_save_history(const double *vout, const long long *out_off, con
 {
     hipLaunchKernelGGL(k_save_history, dim3(wave_n), dim3(256), 0, s, vout, out_off, hist_off, pair_gc, n_pe,
                        wave_begin, hist);
+    return hipGetLastError();
+}
+
+hipError_t launch_wave_reset(int *counter, unsigned long long *clock, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_wave_reset, dim3(1), dim3(64), 0, s, counter, clock);
     return hipGetLastError();
 }
 

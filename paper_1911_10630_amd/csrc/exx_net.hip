@@ -355,7 +355,7 @@ __global__ __launch_bounds__(256) void k_net_sumsq(NetPairArgs a, const int *pai
     __shared__ double red[4];
     const int k = blockIdx.y;
     const int pair = pair_of(pairs, base, k);
-    const ClassDev &g = a.pair_gc[pair].w ? a.cls[1] : a.cls[0];
+    const ClassDev &g = a.cls[a.pair_gc[pair].w];
     const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
     double ss = 0.0;
     for (int q = blockIdx.x * 256 + threadIdx.x; q < g.n_pe; q += kScaleChunks * 256) ss += b[q] * b[q];
@@ -371,7 +371,7 @@ __global__ void k_net_scale(NetPairArgs a, const int *pairs, int base, int nb, c
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nb) return;
     const int pair = pair_of(pairs, base, k);
-    const ClassDev &g = a.pair_gc[pair].w ? a.cls[1] : a.cls[0];
+    const ClassDev &g = a.cls[a.pair_gc[pair].w];
     double tot = 0.0;
     for (int j = 0; j < kScaleChunks; ++j) tot += part[k * kScaleChunks + j];
     scale[k] = tot > 0.0 ? sqrt(tot / (double)g.n_pe) : 0.0;
@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void k_net_cells(NetPairArgs a, const int *pai
     const int k = blockIdx.y;
     const int pair = pair_of(pairs, base, k);
     const int cls = a.pair_gc[pair].w;
-    const ClassDev &g = cls ? a.cls[1] : a.cls[0];
+    const ClassDev &g = a.cls[cls];
     const unsigned char *bnd = a.bnd[cls];
     const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
     const double *x = a.vout + a.out_off[pair];
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(256) void k_net_output(NetPairArgs a, int base, int
 {
     const int k = blockIdx.y;
     const int pair = base + k;
-    const ClassDev &g = a.pair_gc[pair].w ? a.cls[1] : a.cls[0];
+    const ClassDev &g = a.cls[a.pair_gc[pair].w];
     const int q = blockIdx.x * 256 + threadIdx.x;
     if (q >= g.n_pe) return;
     double *x = a.vout + a.out_off[pair];
@@ -820,7 +820,8 @@ hipError_t net_infer(ExxNet *net, const NetPairArgs &a, int n, int D, double *ms
         const int base = a.wave_begin + b0;
         net_input(net, a, nullptr, base, nb, D, false, s);
         forward(net, nb, D, s);
-        const int npe = std::max(a.cls[0].n_pe, a.cls[1].n_pe);
+        int npe = 0;
+        for (int k = 0; k < KMAX; ++k) npe = std::max(npe, a.cls[k].n_pe);
         hipLaunchKernelGGL(k_net_output, dim3((unsigned)((npe + 255) / 256), (unsigned)nb), dim3(256), 0, s, a, base, D,
                            net->f, net->out, net->scale);
     }

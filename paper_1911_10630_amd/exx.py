@@ -56,7 +56,7 @@ class ExxStats(C.Structure):
                 ("tune_ms", C.c_double), ("graph_builds", C.c_int32), ("graph_launches", C.c_int32),
                 ("n_classes", C.c_int32), ("class_n_pe", C.c_int64 * 4), ("class_n_me", C.c_int64 * 4),
                 ("class_pairs", C.c_int64 * 4), ("class_capped", C.c_int64), ("cg_inflight", C.c_int32 * 2),
-                ("cg_cols32", C.c_int32)]
+                ("cg_cols32", C.c_int32), ("cg_clock_ms", C.c_double)]
 
 
 class ExxError(RuntimeError):

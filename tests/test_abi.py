@@ -129,8 +129,6 @@ def _setup_status(**over):
     (dict(n_classes=2, class_r_pe=(3.0, 2.0, 0, 0), class_r_me=(5.0, 4.0, 0, 0), omega_scale=3.0), "ascending"),
     (dict(n_classes=2, class_r_pe=(2.0, 3.0, 0, 0), class_r_me=(2.5, 5.0, 0, 0), omega_scale=3.0), "class_r_me[0]"),
     (dict(n_classes=2, class_r_pe=(2.0, 3.0, 0, 0), class_r_me=(4.0, 5.0, 0, 0), omega_scale=0.0), "omega_scale"),
-    (dict(n_classes=2, class_r_pe=(2.0, 3.0, 0, 0), class_r_me=(4.0, 5.0, 0, 0), omega_scale=3.0, guess=3),
-     "learned"),
 ])
 def test_setup_rejects_bad_parameters(over, needle):
     st, msg = _setup_status(**over)

@@ -1,0 +1,135 @@
+"""The 512-water configuration with everything at once: per-pair subdomain
+classes (uneven truncated subdomains), the learned initial guess, the
+multigrid-preconditioned iteration in FP32 with FP64 residual replacement,
+FP32 orbitals on local boxes, pairs in waves, over three synthetic MD steps
+(centres displaced, pair list and classes rebuilt every step).
+
+Every step: each pair converged to the FP64 residual bar, E_xx the weighted
+pair sum; on the last step, sampled pairs of several classes against the FP64
+oracle's single-pair pipeline on the class the oracle itself assigns them
+(which must be the class the GPU chose).
+"""
+import concurrent.futures as cf
+import dataclasses
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+from oracle import oracle as O  # noqa: E402
+from paper_1911_10630_amd import exx as X  # noqa: E402
+from paper_1911_10630_amd import synth as S  # noqa: E402
+
+RELRES_BAR = 1e-10 * (1 + 1e-4)
+CLASSES = [(r, r + 1.9) for r in (3.5, 4.5, 6.0, 7.56)]
+OMEGA = 5.0
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _nearest(wl, n):
+    L = np.asarray(wl.cell, float)
+    d = wl.orbitals.centers - L / 2
+    d -= L * np.round(d / L)
+    return np.sort(np.argsort(np.sum(d * d, axis=1), kind="stable")[:n])
+
+
+def _sub(wl, keep):
+    o = wl.orbitals
+    return dataclasses.replace(wl, orbitals=S.OrbitalSet(centers=o.centers[keep], kind=o.kind[keep],
+                                                          alpha=o.alpha[keep], u=o.u[keep], a=o.a[keep],
+                                                          B=o.B[keep]))
+
+
+def _classes_by_oracle(wl, spreads, pi, pj):
+    C = wl.orbitals.centers
+    out = []
+    for i, j in zip(pi, pj):
+        g = O.pair_origin(C[i], C[j], wl.cell, wl.n_grid)
+        r = O.pair_domain_radius(C[i], C[j], OMEGA * spreads[i], OMEGA * spreads[j], g, wl.cell, wl.n_grid, i == j)
+        k = 0
+        while k < len(CLASSES) and CLASSES[k][0] < r:
+            k += 1
+        out.append(min(k, len(CLASSES) - 1))
+    return out
+
+
+def test_water512_classes_learned_fp32_multigrid_md():
+    wl = S.c5_water512()
+    kw = dict(precond="mg", precision="fp32_refine", guess="learned", classes=CLASSES, omega_scale=OMEGA)
+    # a model trained on a small subsystem of another seed
+    tw = S.c5_water512(seed=9001)
+    tw = _sub(tw, _nearest(tw, 64))
+    _say("[gpu] training the learned guess on a 64-orbital subsystem of another seed")
+    tr = X.Exx.from_workload(tw, **kw)
+    tr.model_init(4, seed=11)
+    tr.pairs_spread(tw.orbitals.centers, S.spreads(tw.orbitals))
+    phi_t = torch.empty((tw.orbitals.n,) + tuple(reversed(tw.box)), dtype=torch.float32, device="cuda:0")
+    S.orbitals_torch(tw, device="cuda:0", origins=tr.box_origins(), out=phi_t)
+    tr.step(phi_t)
+    before = tr.model_loss(batch=8)
+    for ep in range(4):
+        loss = tr.model_train(epochs=1, batch=8, lr=1e-3, seed=ep)
+    assert np.isfinite(loss) and loss < before
+    blob = tr.model_save()
+    tr.close()
+    del phi_t
+
+    ctx = X.Exx.from_workload(wl, **kw)
+    ctx.load_model(blob)
+    phi = torch.empty((2048,) + tuple(reversed(wl.box)), dtype=torch.float32, device="cuda:0")
+    D = torch.empty_like(phi)
+    rng = np.random.default_rng(2718)
+    orbs = wl.orbitals
+    spreads = S.spreads(orbs)
+    for step in range(3):
+        wl_k = dataclasses.replace(wl, orbitals=orbs)
+        n = ctx.pairs_spread(orbs.centers, spreads)
+        org = ctx.box_origins()
+        S.orbitals_torch(wl_k, device="cuda:0", origins=org, out=phi)
+        E, D = ctx.step(phi, D)
+        info = ctx.pair_info()
+        st = ctx.stats()
+        _say(f"[gpu] MD step {step}: {n} pairs in {st['n_waves']} waves, classes {st['class_pairs'][:4]}, "
+             f"mean iterations {info['iters'].mean():.1f}, E {E:.12f}")
+        assert st["guess_pairs"] == n and st["n_classes"] == 4
+        assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
+        w = np.where(info["i"] == info["j"], 1.0, 2.0)
+        assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
+        if step < 2:
+            orbs = S.md_displace(orbs, wl.cell[0], rng)
+    assert st["n_waves"] > 1
+    # sampled pairs of the last step: one per class in use, and a self pair
+    cls = ctx.pair_class()
+    pick = [int(np.nonzero(info["i"] == info["j"])[0][5])]
+    for k in range(4):
+        cand = np.nonzero((cls == k) & (info["i"] != info["j"]))[0]
+        if len(cand):
+            pick.append(int(cand[len(cand) // 2]))
+    mine = _classes_by_oracle(wl_k, spreads, info["i"][pick], info["j"][pick])
+    assert mine == [int(cls[p]) for p in pick]
+    subs = [O.Subdomain(wl.n_grid, wl.cell, a, b) for a, b in CLASSES]
+    need = sorted({int(info["i"][p]) for p in pick} | {int(info["j"][p]) for p in pick})
+    vals = S.orbitals_np(wl_k, need, origins=org).astype(np.float32).astype(np.float64)
+    phis = dict(zip(need, S.embed_boxes(vals, [org[k] for k in need], wl.n_grid)))
+
+    def ref(t):
+        p = pick[t]
+        i, j = int(info["i"][p]), int(info["j"][p])
+        return subs[mine[t]].solve_pair(phis[i], phis[j], info["origin"][p])
+
+    _say(f"[gpu] oracle on sampled pairs {pick} (classes {mine})")
+    with cf.ThreadPoolExecutor(len(pick)) as ex:
+        refs = list(ex.map(ref, range(len(pick))))
+    for p, r in zip(pick, refs):
+        assert abs(info["e"][p] - r["e"]) <= 1e-8 * abs(r["e"]), (p, info["e"][p], r["e"])
+    ctx.close()

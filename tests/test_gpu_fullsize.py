@@ -190,3 +190,93 @@ def test_c5_sampled_pairs_vs_oracle(c5_run):
             sub = subs[0 if info["i"][p] == info["j"][p] else 1]
             got = ctx.debug_pair(p, sub.n_pe, sub.n_shell)
             assert np.max(np.abs(got["x"] - r["x"])) <= 1e-7 * np.max(np.abs(r["x"])), p
+
+
+# ---------------------------------------------------------------------------
+# Whole-step parity at full size: every pair energy and E_xx against the
+# oracle's own whole step (tests/golden/water64_oracle.npz, written by
+# tests/golden/make_water64_oracle.py, which calls only the oracle), and
+# whole orbitals' D^k against the oracle's D^k over all of k's pairs
+# (Eqs. exx_omega, Dxx_mlwf_omega; gamma^k as in Eq. gammaxx_i:
+# sum |D - D_ref| / sum |D_ref| over the grid).
+# ---------------------------------------------------------------------------
+
+GOLDEN_C2 = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "water64_oracle.npz")
+
+
+def _golden_c2():
+    if not __import__("os").path.exists(GOLDEN_C2):
+        pytest.skip("tests/golden/water64_oracle.npz not written yet")
+    return np.load(GOLDEN_C2, allow_pickle=False)
+
+
+def test_c2_every_pair_and_energy_vs_oracle_step(c2_run):
+    wl, ctx, n, E, D, info = c2_run
+    g = _golden_c2()
+    assert np.array_equal(g["i"], info["i"]) and np.array_equal(g["j"], info["j"])
+    assert np.all(g["converged"] == 1)
+    rel = np.abs(info["e"] - g["e"]) / np.abs(g["e"])
+    _say(f"[gpu] 64-water, all {n} pairs: max rel pair-energy difference {rel.max():.2e}, "
+         f"E {E:.12f} vs oracle {float(g['E']):.12f}")
+    assert rel.max() <= 1e-8, (int(np.argmax(rel)), rel.max())
+    assert abs(E - float(g["E"])) <= 1e-8 * abs(float(g["E"]))
+
+
+def test_c2_multigrid_every_pair_vs_oracle_step():
+    """The multigrid-preconditioned FP64 iteration stops on the same residual:
+    every pair energy and E_xx against the oracle's plain-CG step."""
+    g = _golden_c2()
+    wl = S.c2_water64()
+    _say("[gpu] 64-water workload, multigrid-preconditioned FP64, full step")
+    phi = S.orbitals_torch(wl, device="cuda:0")
+    ctx = X.Exx.from_workload(wl, precond="mg")
+    ctx.pairs(wl.orbitals.centers)
+    E, _ = ctx.step(phi)
+    info = ctx.pair_info()
+    rel = np.abs(info["e"] - g["e"]) / np.abs(g["e"])
+    _say(f"[gpu] multigrid: max rel pair-energy difference {rel.max():.2e}")
+    assert rel.max() <= 1e-8 and abs(E - float(g["E"])) <= 1e-8 * abs(float(g["E"]))
+    ctx.close()
+
+
+def _dk_oracle(wl, k, info, phis, classes):
+    sel = np.nonzero((info["i"] == k) | (info["j"] == k))[0]
+    pi, pj = info["i"][sel], info["j"][sel]
+    cls = np.where(pi == pj, 0, 1).astype(np.int32)
+    return O.dxx_orbital(wl.n_grid, wl.cell, classes, wl.orbitals.centers, phis, pi, pj, cls, k,
+                         tol=wl.cg_rtol, nthreads=16), len(sel)
+
+
+@pytest.mark.parametrize("k", [37, 200])
+def test_c2_whole_orbital_potential_vs_oracle(c2_run, k):
+    """D^k over every one of k's pairs, FP64: gamma^k <= 1e-7."""
+    wl, ctx, n, E, D, info = c2_run
+    sel = np.nonzero((info["i"] == k) | (info["j"] == k))[0]
+    orbs = sorted(set(info["i"][sel].tolist()) | set(info["j"][sel].tolist()))
+    _say(f"[gpu] oracle D^{k} over its {len(sel)} pairs ({len(orbs)} orbitals)")
+    phis = dict(zip(orbs, S.orbitals_np(wl, orbs)))
+    classes = [(wl.r_pe[0], wl.r_me[0]), (wl.r_pe[1], wl.r_me[1])]
+    Dref, npair = _dk_oracle(wl, k, info, phis, classes)
+    Dk = D[k].cpu().numpy()
+    gam = np.abs(Dk - Dref).sum() / np.abs(Dref).sum()
+    rel2 = np.linalg.norm(Dk - Dref) / np.linalg.norm(Dref)
+    _say(f"[gpu] D^{k}: gamma {gam:.2e}, relative L2 {rel2:.2e}, max abs {np.abs(Dk - Dref).max():.2e}")
+    assert gam <= 1e-7 and rel2 <= 1e-7
+
+
+def test_c5_whole_orbital_potential_vs_oracle(c5_run):
+    """The 512-water workload (FP32 orbitals and D on boxes, FP32 CG with FP64
+    refinement, waves): D^k of one orbital over every one of its pairs against
+    the oracle on the same FP32-rounded orbitals: gamma^k <= 1e-6."""
+    wl, ctx, n, org, E, D, info = c5_run
+    k = 1000
+    sel = np.nonzero((info["i"] == k) | (info["j"] == k))[0]
+    orbs = sorted(set(info["i"][sel].tolist()) | set(info["j"][sel].tolist()))
+    _say(f"[gpu] oracle D^{k} over its {len(sel)} pairs ({len(orbs)} orbitals)")
+    phis = dict(zip(orbs, _oracle_orbitals(wl, orbs, org)))
+    classes = [(wl.r_pe[0], wl.r_me[0]), (wl.r_pe[1], wl.r_me[1])]
+    Dref, _ = _dk_oracle(wl, k, info, phis, classes)
+    Dk = S.embed_boxes(D[k:k + 1].cpu().numpy().astype(np.float64), [org[k]], wl.n_grid)[0]
+    gam = np.abs(Dk - Dref).sum() / np.abs(Dref).sum()
+    _say(f"[gpu] D^{k}: gamma {gam:.2e}")
+    assert gam <= 1e-6

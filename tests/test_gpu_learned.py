@@ -267,15 +267,25 @@ def test_learned_guess_needs_a_model(c1_ref):
     assert ei.value.status == X.EXX_ESTATE
 
 
-def test_training_needs_resident_right_hand_sides(c1_ref):
+def test_training_in_waves_uses_the_last_wave(c1_ref):
+    """After a solve in waves only the last wave's right-hand sides are
+    resident: training runs on those (60 pairs in waves of 7 leave 4), a
+    batch larger than that is refused, and the loss it reports equals the
+    evaluation over the same pairs."""
     wl, phi, *_ = c1_ref
     ctx = X.Exx.from_workload(wl, wave_pairs=7)
-    ctx.model_init(2)
+    ctx.model_init(2, seed=3)
     ctx.pairs(wl.orbitals.centers)
     ctx.step(torch.from_numpy(phi).cuda())
+    assert ctx.stats()["n_waves"] == 9
     with pytest.raises(X.ExxError) as ei:
-        ctx.model_train(epochs=1, batch=4)
-    assert ei.value.status == X.EXX_ESTATE
+        ctx.model_train(epochs=1, batch=5)
+    assert ei.value.status == X.EXX_EINVAL
+    before = ctx.model_loss(batch=4)
+    for ep in range(20):
+        loss = ctx.model_train(epochs=1, batch=4, lr=1e-3, seed=ep)
+    assert np.isfinite(before) and np.isfinite(loss)
+    assert ctx.model_loss(batch=4) < before
 
 
 def test_learned_guess_in_graph_mode(c1_ref, trained):

@@ -571,3 +571,46 @@ def test_pair_domain_radius_wraps_across_the_boundary():
     # the same grid point, 0.3 - 0.25 = 0.05 from it
     r2 = O.pair_domain_radius(cj, ci, 1.0, 1.0, g, cell, n, False)
     assert abs(r2 - r) < 1e-12
+
+
+def test_solve_pairs_classed_matches_each_class_and_the_two_fixed_classes(c1_result):
+    """Each pair on its own class equals that class's single-pair pipeline bit
+    for bit; with two classes chosen self -> 0, other -> 1 it equals the
+    fixed-class explicit-list solve."""
+    wl, phi, E, D, out = c1_result
+    C = wl.orbitals.centers
+    classes = [(3.0, 5.0), (4.0, 6.0), (5.5, 7.5)]
+    rng = np.random.default_rng(21)
+    pick = rng.choice(len(out["i"]), 7, replace=False)
+    pi, pj = out["i"][pick], out["j"][pick]
+    cls = rng.integers(0, 3, len(pick)).astype(np.int32)
+    phis = {k: phi[k] for k in range(len(phi))}
+    res = O.solve_pairs_classed(wl.n_grid, wl.cell, classes, C, phis, pi, pj, cls, nthreads=4)
+    subs = [O.Subdomain(wl.n_grid, wl.cell, a, b) for a, b in classes]
+    for t in range(len(pick)):
+        i, j = int(pi[t]), int(pj[t])
+        ref = subs[cls[t]].solve_pair(phi[i], phi[j], O.pair_origin(C[i], C[j], wl.cell, wl.n_grid))
+        assert res["e"][t] == ref["e"] and res["iters"][t] == ref["iters"] and res["relres"][t] == ref["relres"]
+    two = [(wl.r_pe[0], wl.r_me[0]), (wl.r_pe[1], wl.r_me[1])]
+    c2 = np.where(pi == pj, 0, 1).astype(np.int32)
+    a = O.solve_pairs_classed(wl.n_grid, wl.cell, two, C, phis, pi, pj, c2, nthreads=4)
+    b = O.solve_pairs(wl.n_grid, wl.cell, wl.r_pe, wl.r_me, C, phis, pi, pj, nthreads=4)
+    for key in ("e", "iters", "converged", "relres"):
+        assert np.array_equal(a[key], b[key]), key
+
+
+@pytest.mark.parametrize("k", [0, 7])
+def test_dxx_orbital_equals_the_whole_step(c1_result, k):
+    """D^k from the list of k's pairs in pair order equals the whole step's
+    D^k bit for bit (same solves, same summation order), and the orbital's
+    partners' phi are the only ones it reads."""
+    wl, phi, E, D, out = c1_result
+    C = wl.orbitals.centers
+    sel = np.nonzero((out["i"] == k) | (out["j"] == k))[0]
+    pi, pj = out["i"][sel], out["j"][sel]
+    touch = sorted(set(pi.tolist()) | set(pj.tolist()))
+    two = [(wl.r_pe[0], wl.r_me[0]), (wl.r_pe[1], wl.r_me[1])]
+    cls = np.where(pi == pj, 0, 1).astype(np.int32)
+    Dk = O.dxx_orbital(wl.n_grid, wl.cell, two, C, {q: phi[q] for q in touch}, pi, pj, cls, k, nthreads=4)
+    assert np.array_equal(Dk, D[k])
+    assert len(sel) >= 3
