@@ -176,6 +176,73 @@ def two_class_reference(wl, phi, dxx, origins, E_head, args):
                 rel_diff_E_vs_headline=abs(E - E_head) / abs(E))
 
 
+def learned_full(wl, phi, dxx, spreads, classes, head, args):
+    """The headline configuration (every pair, per-pair classes, multigrid
+    PCG) with the learned initial guess, in FP64 and in FP32 with FP64
+    residual replacement (the latter beside its zero-guess run): one warm-up
+    step (graph build) and one timed step each.  The model is trained on the
+    same-size subsystem of the workload drawn with another seed, on the same
+    classes."""
+    import torch
+    from paper_1911_10630_amd import exx as X
+    from paper_1911_10630_amd import synth as S
+    dev = phi.device
+    stream = torch.cuda.current_stream(dev)
+    ckw = dict(classes=classes, omega_scale=args.omega_scale, precond="mg")
+    t0 = time.perf_counter()
+    tw = S.WORKLOADS[args.workload](seed=9001)
+    tw = subsystem(tw, nearest_orbitals(tw, args.lvp_orbitals), "-train")
+    tw.precision = "fp64"
+    tr = X.Exx.from_workload(tw, guess="learned", **ckw)
+    n_tr = tr.pairs_spread(tw.orbitals.centers, S.spreads(tw.orbitals))
+    shape = (tw.orbitals.n,) + tuple(reversed(tw.box or tw.n_grid))
+    phi_t = torch.empty(shape, dtype=phi.dtype, device=dev)
+    S.orbitals_torch(tw, device=dev, origins=tr.box_origins() if tw.box else None, out=phi_t)
+    tr.model_init(args.coarsen, seed=5)
+    tr.step(phi_t)
+    loss0 = tr.model_loss(batch=args.train_batch)
+    loss = None
+    for ep in range(args.train_epochs):
+        loss = tr.model_train(epochs=1, batch=args.train_batch, lr=args.train_lr, seed=ep)
+    blob = tr.model_save()
+    train_s = time.perf_counter() - t0
+    tr.close()
+    del phi_t
+    log(f"[bench] learned guess (classes): trained on {n_tr} pairs x {args.train_epochs} epochs in {train_s:.1f} s, "
+        f"loss {loss0:.3g} -> {loss:.3g}")
+    rows = {"mg": dict(ms_per_step=head["ms_per_step"], solves_per_s=head["solves_per_s"],
+                       iters_mean=head["iters_mean"], cg_clock_ms=head["cg_clock_ms"], E_xx=head["E_xx"],
+                       rel_diff_E_vs_mg=0.0, note="the timed headline steps")}
+    for name, kw in (("mg+learned", dict(guess="learned")), ("mg_fp32", dict(precision="fp32_refine")),
+                     ("mg_fp32+learned", dict(guess="learned", precision="fp32_refine"))):
+        w = dataclasses.replace(wl)
+        w.precision = kw.pop("precision", "fp64")
+        ctx = X.Exx.from_workload(w, graph=True, **ckw, **kw)
+        n = ctx.pairs_spread(wl.orbitals.centers, spreads)
+        if "learned" in name:
+            ctx.load_model(blob)
+        step_timed(ctx, phi, dxx, stream, 1)                     # warm-up: graph build
+        E, dt = step_timed(ctx, phi, dxx, stream, 1)
+        st = ctx.stats()
+        rows[name] = dict(ms_per_step=round(1e3 * dt, 2), solves_per_s=round(n / dt, 1),
+                          iters_mean=round(st["iters_total"] / n, 2), guess_ms=round(st["guess_ms"], 2),
+                          cg_clock_ms=round(st["cg_clock_ms"], 2), E_xx=E,
+                          rel_diff_E_vs_mg=abs(E - head["E_xx"]) / abs(head["E_xx"]))
+        ctx.close()
+        log(f"[bench] {name}: {1e3 * dt:.0f} ms, {rows[name]['iters_mean']} iterations")
+    base = rows["mg"]["ms_per_step"]
+    for r in rows.values():
+        r["speedup_vs_mg"] = round(base / r["ms_per_step"], 3)
+    return dict(config="the headline workload and classes, multigrid PCG to 1e-10, HIP graph",
+                model=dict(coarsen=args.coarsen, train_pairs=n_tr, epochs=args.train_epochs, train_s=round(train_s, 1),
+                           loss_before=loss0, loss_after=loss,
+                           train_set=f"the {args.lvp_orbitals} orbitals nearest the centre, orbital seed 9001, "
+                                     "same classes"),
+                accuracy_point="every mode stops on ||b - A x|| <= 1e-10 ||b||; |dE_xx|/|E_xx| against the "
+                               "headline is listed per mode (the bar is 1e-7)",
+                modes=rows)
+
+
 def learned_vs_plain(wl, args):
     """The learned initial guess against the zero guess, for plain and
     multigrid-preconditioned FP64 CG, on the n_sub orbitals nearest the cell
@@ -348,6 +415,9 @@ def main():
     ap.add_argument("--copy-probe-mb", type=int, default=0,
                     help="(profiling) also run a plain device copy of this many MiB, 3 times, to calibrate "
                          "the FETCH_SIZE / WRITE_SIZE counters")
+    ap.add_argument("--stream-probe", action="store_true",
+                    help="print the device's measured streaming rates (read / copy / triad / CG mix, GB/s) as one "
+                         "JSON line and exit")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -359,6 +429,10 @@ def main():
     import torch
     from paper_1911_10630_amd import exx as X
     from paper_1911_10630_amd import synth as S
+
+    if args.stream_probe:
+        print(json.dumps(X.stream_rates(0)), flush=True)
+        return
 
     if args.copy_probe_mb:
         n = args.copy_probe_mb * (1 << 20) // 8
@@ -424,6 +498,7 @@ def main():
         for entry in tr.get("entries", []):
             if (entry.get("kernel_hash") == kernel_hash() and entry.get("workload") == wl.name
                     and entry.get("precond") == args.precond and entry.get("omega_scale") == args.omega_scale
+                    and entry.get("precision", "fp64") == wl.precision
                     and entry.get("variant") == [st["solve_block"], st["cg_cols"]]):
                 # measured HBM bytes of the same launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
                 # calibrated on a device copy); FP64 iteration counts are deterministic
@@ -475,6 +550,12 @@ def main():
         if classed:
             log("[bench] two-class reference step (untimed)")
             line["two_class_reference"] = two_class_reference(wl, phi, dxx, origins, E, args)
+            if args.precond == "mg" and wl.precision == "fp64":
+                log("[bench] learned guess on the headline configuration (untimed)")
+                head = dict(ms_per_step=round(ms_per_step, 2), solves_per_s=round(value, 1),
+                            iters_mean=round(st["iters_total"] / n_pairs, 2), cg_clock_ms=round(st["cg_clock_ms"], 2),
+                            E_xx=E)
+                line["learned_full"] = learned_full(wl, phi, dxx, spreads, classes, head, args)
         log("[bench] learned vs plain on a subsystem (untimed)")
         del phi, dxx
         torch.cuda.empty_cache()

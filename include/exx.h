@@ -312,8 +312,8 @@ exx_status exx_debug_pair(exx_ctx *ctx, int64_t pair, double *v_pe, double *v_sh
  * guesses as the route to fewer CG iterations (Sec. III.C Step IV, Sec. IV.B).
  * The model lives in the context and survives exx_pairs. */
 
-/* Creates a model with random (He-normal, seeded) weights.  coarsen: 2 or 4
- * grid points per coarse cell edge, else EXX_EINVAL. */
+/* Creates a model with random (He-normal, seeded) weights.  coarsen: 2, 4
+ * or 8 grid points per coarse cell edge, else EXX_EINVAL. */
 exx_status exx_model_init(exx_ctx *ctx, int32_t coarsen, uint64_t seed);
 
 /* Adam training on the pairs of the last solve: input its right-hand sides,

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libexx_mi355x.so")
-SOURCES = ["exx_kernels.hip", "exx_net.hip", "exx_pairs.hip", "exx_stream.hip", "exx_host.cpp"]
+SOURCES = ["exx_kernels.hip", "exx_dxx.hip", "exx_net.hip", "exx_pairs.hip", "exx_stream.hip", "exx_host.cpp"]
 ARCH = os.environ.get("EXX_OFFLOAD_ARCH", "gfx950")
 
 

@@ -2016,7 +2016,8 @@ static exx_status exx_debug_pair_body(exx_ctx *c, int64_t pair, double *v_pe, do
 static exx_status exx_model_init_body(exx_ctx *c, int32_t coarsen, uint64_t seed)
 {
     if (!c) return fail(nullptr, EXX_EINVAL, "exx_model_init: ctx is NULL");
-    if (coarsen != 2 && coarsen != 4) return fail(c, EXX_EINVAL, "coarsen must be 2 or 4 (got %d)", coarsen);
+    if (coarsen != 2 && coarsen != 4 && coarsen != 8)
+        return fail(c, EXX_EINVAL, "coarsen must be 2, 4 or 8 (got %d)", coarsen);
     HIPCHK(c, hipSetDevice(c->device));
     net_destroy(c->net);
     c->net = nullptr;

@@ -82,6 +82,13 @@ __device__ __forceinline__ int sh_index(const ClassDev &g, int x, int y, int z)
 // Orbital storage: orbital k lives on the periodic box [org_k, org_k + b)
 // of the grid, layout [n_orb][bz][by][bx], x fastest; outside its box an
 // orbital is zero.  The whole grid is the box with org = 0, b = N.
+// v in [-n, 2n) wrapped into [0, n)
+__device__ __forceinline__ int wrap_n(int v, int n)
+{
+    v = v < 0 ? v + n : v;
+    return v >= n ? v - n : v;
+}
+
 struct OrbBox {
     const int4 *org;            // [n_orb] box origin (grid point)
     int bx, by, bz;
@@ -292,7 +299,7 @@ struct NetPairArgs {
 };
 
 struct ExxNet;
-// Fresh net with He-initialized weights; coarsening factor f (2 or 4).
+// Fresh net with He-initialized weights; coarsening factor f (2, 4 or 8).
 ExxNet *net_create(int f, unsigned long long seed, hipError_t *err);
 void net_destroy(ExxNet *net);
 int net_coarsen(const ExxNet *net);

@@ -1,5 +1,6 @@
 // exx_kernels.hip -- HIP kernels (gfx950) of the pair-Poisson exact-exchange
-// path of Ko et al., arXiv:1911.10630, Sec. III.C Steps III-V.
+// path of Ko et al., arXiv:1911.10630, Sec. III.C Steps III-V (the D
+// accumulation of Step V is in exx_dxx.hip).
 //
 //   k_prep        one work-group per pair: gather and pair density (Eq. l2g),
 //                 multipoles (Eq. mepole), shell potential (Eq. me) and the
@@ -12,9 +13,6 @@
 //                 spheres whose planes do not fit the LDS.
 //   k_pair_energy e_ij = h^3 sum_PE rho_ij v_ij (Eq. exx_omega), one
 //                 work-group per pair.
-//   k_dxx         owner-computes accumulation of D^k = sum_j v_kj phi_j over
-//                 the pairs of each orbital, in pair order (Eq. Dxx_mlwf_omega);
-//                 no atomics.
 //   k_energy      E_xx = -sum w_ij e_ij in pair order, one work-group.
 // Every reduction is a fixed-order work-group tree, so results are bitwise
 // reproducible whatever the scheduling.
@@ -28,12 +26,6 @@ namespace exx {
 // ---------------------------------------------------------------------------
 // helpers
 // ---------------------------------------------------------------------------
-
-__device__ __forceinline__ int wrap_n(int v, int n)
-{
-    v = v < 0 ? v + n : v;
-    return v >= n ? v - n : v;
-}
 
 // Unnormalized real regular solid harmonics U_lm(x, y, z), index l*l + l + m:
 //   U_l,+m = Pi_l^m(z, r^2) Re (x + i y)^m,  U_l,-m = Pi_l^m Im (x + i y)^m,
@@ -1699,147 +1691,6 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_pair_energy(SolveArgs a)
 }
 
 // ---------------------------------------------------------------------------
-// D accumulation: owner computes, pair order, no atomics
-// ---------------------------------------------------------------------------
-
-constexpr int DXX_BLOCK = 256;
-constexpr int DXX_PER_THREAD = 4;
-constexpr int DXX_TILE = DXX_BLOCK * DXX_PER_THREAD;
-
-// Do the cyclic index ranges [a0, a0 + alen) and [b0, b0 + blen) of Z_n meet
-// (a0, b0 in [0, n); lengths at most n)?
-__device__ __forceinline__ bool cyclic_meet(int a0, int alen, int b0, int blen, int n)
-{
-    int d1 = a0 - b0, d2 = b0 - a0;
-    d1 += d1 < 0 ? n : 0;
-    d2 += d2 < 0 ? n : 0;
-    return d1 < blen || d2 < alen;
-}
-
-// One work-group per tile of DXX_TILE consecutive points of orbital k's box.
-// A pair whose ME bounding box misses the tile's bounding box is skipped by
-// the whole work-group; a tile no pair of the wave reaches writes zeros (the
-// first wave, or D directly) or nothing (a later wave's partial sums are
-// unchanged).  Contributions are added in pair order either way.
-template <typename TO, bool ACC>
-__global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
-{
-    const int k = blockIdx.y;
-    const long long t0 = (long long)blockIdx.x * DXX_TILE;
-    const OrbBox &B = a.box;
-    const int4 ok_org = B.org[k];
-    // this orbital's pairs inside [pair_lo, pair_hi): its list is ascending
-    int lo = a.orb_ptr[k], hi = a.orb_ptr[k + 1];
-    {
-        int l = lo, r = hi;
-        while (l < r) { const int m = (l + r) >> 1; if (a.orb_pairs[m] < a.pair_lo) l = m + 1; else r = m; }
-        int l2 = l, r2 = hi;
-        while (l2 < r2) { const int m = (l2 + r2) >> 1; if (a.orb_pairs[m] < a.pair_hi) l2 = m + 1; else r2 = m; }
-        lo = l;
-        hi = l2;
-    }
-    // the tile's bounding box in global grid coordinates (start, length per axis)
-    const long long t1 = min(t0 + DXX_TILE, B.vol) - 1;
-    const long long bplane = (long long)B.bx * B.by;
-    const int lz0 = (int)(t0 / bplane), lz1 = (int)(t1 / bplane);
-    int ly0 = 0, ylen = B.by, lx0 = 0, xlen = B.bx;
-    if (lz0 == lz1) {
-        ly0 = (int)((t0 / B.bx) % B.by);
-        const int ly1 = (int)((t1 / B.bx) % B.by);
-        ylen = ly1 - ly0 + 1;
-        if (ly0 == ly1) {
-            lx0 = (int)(t0 % B.bx);
-            xlen = (int)(t1 % B.bx) - lx0 + 1;
-        }
-    }
-    const int zs = wrap_n(ok_org.z + lz0, a.nz), ys = wrap_n(ok_org.y + ly0, a.ny), xs = wrap_n(ok_org.x + lx0, a.nx);
-    const int zlen = lz1 - lz0 + 1;
-    auto meets = [&](int pair) -> bool {
-        const int4 pg = a.pair_gc[pair];
-        const ClassDev &g = a.cls[pg.w];
-        return cyclic_meet(zs, zlen, wrap_n(pg.z + g.mzlo, a.nz), g.mnz, a.nz) &&
-               cyclic_meet(ys, ylen, wrap_n(pg.y + g.mylo, a.ny), g.mny, a.ny) &&
-               cyclic_meet(xs, xlen, wrap_n(pg.x + g.mxlo, a.nx), g.mnx, a.nx);
-    };
-    bool any = false;
-    for (int pp = lo; pp < hi && !any; ++pp) any = meets(a.orb_pairs[pp]);
-    if (!any) {
-        if (ACC && !a.acc_first) return;
-#pragma unroll
-        for (int e = 0; e < DXX_PER_THREAD; ++e) {
-            const long long li = t0 + e * DXX_BLOCK + threadIdx.x;
-            if (li >= B.vol) continue;
-            if (ACC)
-                a.acc[(long long)k * B.vol + li] = 0.0;
-            else
-                static_cast<TO *>(a.dxx)[(long long)k * B.vol + li] = (TO)0.0;
-        }
-        return;
-    }
-    double acc[DXX_PER_THREAD];
-    int gx[DXX_PER_THREAD], gy[DXX_PER_THREAD], gz[DXX_PER_THREAD];
-    bool ok[DXX_PER_THREAD];
-#pragma unroll
-    for (int e = 0; e < DXX_PER_THREAD; ++e) {
-        const long long li = t0 + e * DXX_BLOCK + threadIdx.x;
-        ok[e] = li < B.vol;
-        const long long ll = ok[e] ? li : 0;
-        gx[e] = wrap_n(ok_org.x + (int)(ll % B.bx), a.nx);
-        gy[e] = wrap_n(ok_org.y + (int)((ll / B.bx) % B.by), a.ny);
-        gz[e] = wrap_n(ok_org.z + (int)(ll / bplane), a.nz);
-        acc[e] = ACC && !a.acc_first && ok[e] ? a.acc[(long long)k * B.vol + li] : 0.0;
-    }
-    for (int pp = lo; pp < hi; ++pp) {
-        const int pair = a.orb_pairs[pp];
-        if (!meets(pair)) continue;
-        const int4 pg = a.pair_gc[pair];
-        const int2 ij = a.pair_ij[pair];
-        const int other = ij.x == k ? ij.y : ij.x;
-        const ClassDev g = a.cls[pg.w];
-        const double *v = a.vout + a.out_off[pair];
-        const long long oo = (long long)other * B.vol;
-        const int4 oo_org = B.org[other];
-#pragma unroll
-        for (int e = 0; e < DXX_PER_THREAD; ++e) {
-            if (!ok[e]) continue;
-            int tx = gx[e] - pg.x - g.mxlo, ty = gy[e] - pg.y - g.mylo, tz = gz[e] - pg.z - g.mzlo;
-            tx = wrap_n(tx, a.nx);
-            ty = wrap_n(ty, a.ny);
-            tz = wrap_n(tz, a.nz);
-            if (tx >= g.mnx || ty >= g.mny || tz >= g.mnz) continue;
-            const int row = tz * g.mny + ty;
-            const int4 r0 = g.me_rows[2 * row];
-            const int4 r1 = g.me_rows[2 * row + 1];
-            const int ox = tx + g.mxlo;
-            if (ox < r1.x || ox > r1.y) continue;
-            double vv;
-            if (ox >= r0.y && ox <= r0.z)
-                vv = v[r0.x + ox - r0.y];
-            else
-                vv = v[g.n_pe + r0.w + (ox < r0.y ? ox - r1.x : (r0.y - r1.x) + (ox - r0.z - 1))];
-            acc[e] += vv * load_orb(a.phi, a.f32, B, oo, oo_org, gx[e], gy[e], gz[e], a.nx, a.ny, a.nz);
-        }
-    }
-#pragma unroll
-    for (int e = 0; e < DXX_PER_THREAD; ++e) {
-        const long long li = t0 + e * DXX_BLOCK + threadIdx.x;
-        if (!ok[e]) continue;
-        if (ACC)
-            a.acc[(long long)k * B.vol + li] = acc[e];
-        else
-            static_cast<TO *>(a.dxx)[(long long)k * B.vol + li] = (TO)acc[e];
-    }
-}
-
-// dxx = the FP64 partial sums, rounded to the orbital dtype.
-template <typename TO>
-__global__ void k_dxx_final(const double *acc, TO *dxx, long long n)
-{
-    for (long long t = blockIdx.x * (long long)blockDim.x + threadIdx.x; t < n; t += (long long)gridDim.x * blockDim.x)
-        dxx[t] = (TO)acc[t];
-}
-
-// ---------------------------------------------------------------------------
 // initial guess from earlier steps, and the history it reads
 // ---------------------------------------------------------------------------
 
@@ -2049,29 +1900,6 @@ hipError_t launch_pair_energy(const SolveArgs &a, hipStream_t s)
 hipError_t launch_prep(const SolveArgs &a, hipStream_t s)
 {
     hipLaunchKernelGGL(k_prep, dim3(a.wave_n), dim3(PREP_BLOCK), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_dxx(const DxxArgs &a, int n_orb, int accumulate, hipStream_t s)
-{
-    const dim3 grid((unsigned)((a.box.vol + DXX_TILE - 1) / DXX_TILE), (unsigned)n_orb);
-    if (accumulate)
-        hipLaunchKernelGGL((k_dxx<double, true>), grid, dim3(DXX_BLOCK), 0, s, a);
-    else if (a.f32)
-        hipLaunchKernelGGL((k_dxx<float, false>), grid, dim3(DXX_BLOCK), 0, s, a);
-    else
-        hipLaunchKernelGGL((k_dxx<double, false>), grid, dim3(DXX_BLOCK), 0, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_dxx_final(const DxxArgs &a, int n_orb, hipStream_t s)
-{
-    const long long n = (long long)n_orb * a.box.vol;
-    const dim3 grid((unsigned)std::min<long long>((n + 255) / 256, 1LL << 20));
-    if (a.f32)
-        hipLaunchKernelGGL(k_dxx_final<float>, grid, dim3(256), 0, s, a.acc, static_cast<float *>(a.dxx), n);
-    else
-        hipLaunchKernelGGL(k_dxx_final<double>, grid, dim3(256), 0, s, a.acc, static_cast<double *>(a.dxx), n);
     return hipGetLastError();
 }
 

@@ -20,8 +20,9 @@
 //   d1 = c10(cat(up d2, e1))  D     48 -> 16
 //   out = c11(d1)             D     16 -> 16 (channel 0 is the potential; no ReLU)
 // Convolutions are 3x3x3 with zero padding, computed as implicit GEMMs on the
-// 16x16x16 bf16 MFMA: M = voxels, N = output channels, K = 27 taps x input
-// channels.  The input gradient is the same kernel with tap-flipped,
+// 16x16x32 bf16 MFMA: M = voxels, N = output channels, K = taps x input
+// channels, the input tile staged in LDS once per 16-channel chunk and read
+// by all 27 taps.  The input gradient is the same kernel with tap-flipped,
 // transposed weights; the weight gradient is a second MFMA kernel whose K is
 // the voxels.  pool = 2x2x2 mean, up = nearest-neighbour 2x.
 #include "exx_internal.h"
@@ -35,7 +36,8 @@
 namespace exx {
 
 typedef unsigned short bf16_t;
-typedef short s4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
+typedef short s8_t __attribute__((ext_vector_type(8)));
 typedef float f4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ bf16_t f2bf(float f)
@@ -52,88 +54,182 @@ __device__ __forceinline__ float bf2f(bf16_t b) { return __uint_as_float(((unsig
 
 // Y[v][co] = sum_tap sum_ci X[v + off(tap)][ci] W[tap][co][ci], off(tap) =
 // (tap % 3, tap / 3 % 3, tap / 9) - 1 in (x, y, z).  N samples of D^3 voxels.
-// grid ceil(N D^3 / (64 MV)), 256 threads.  Each wave computes MV tiles of
-// 16 voxels times all NCO = Cout / 16 channel tiles: an input fragment
-// feeds NCO MFMAs and a weight fragment MV MFMAs.
+//
+// Implicit GEMM on the 16x16x32 bf16 MFMA: M = voxels, N = output channels,
+// K = 28 taps (the last one zero) x 16-channel chunks, two taps per MFMA.
+// A work-group (four waves) computes an 8 x 8 x TZ tile of one sample and
+// every output channel; per 16-channel chunk it stages the tile's input halo
+// (10 x 10 x (TZ + 2) voxels, zero outside the cube) in LDS, and all 27 taps
+// read their A fragments from there.  An M tile is a 4 x 4 (x, y) patch of
+// one plane; each wave holds MV of them times NCO = Cout / 16 channel tiles,
+// so a weight fragment feeds MV MFMAs and an input fragment NCO.
+//
+// Weights are packed per chunk and tap pair, Wk[chunk][s][co][32]: slots
+// 0..15 hold tap 2s, slots 16..31 tap 2s + 1, 16 input channels each (tap
+// 27 is zero).  Lane group g = lane / 16 supplies k slots 8g .. 8g + 7 of
+// both operands, i.e. tap 2s + g / 2 and channels 8 (g % 2) .. + 7 of the
+// chunk; the product is independent of which physical k the hardware
+// assigns to a slot, since A and B use the same slot map.
+constexpr int CT_XY = 8;                 // tile edge in x and y
+constexpr int CH_XY = CT_XY + 2;         // halo edge
+constexpr int CH_RP = 12;                // LDS row pitch (voxels): rows 8 banks apart
+constexpr int CH_PP = CH_XY * CH_RP;     // LDS plane pitch (voxels)
+
 template <int MV, int NCO, bool RELU, bool OUT_F32>
 __global__ __launch_bounds__(256) void k_conv3(const bf16_t *__restrict__ X, const bf16_t *__restrict__ W, void *Yv,
                                                int N, int D, int Cin)
 {
-    constexpr int Cout = 16 * NCO;
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-    const int m = lane & 15, kq = lane >> 4;
-    const int D3 = D * D * D, nvox = N * D3;
-    const int v0 = (blockIdx.x * 4 + wv) * 16 * MV;
-    int n[MV], z[MV], y[MV], x[MV];
-    bool aval[MV];
+    constexpr int TZ = MV, HZ = TZ + 2, Cout = 16 * NCO;
+    __shared__ uint4 tile[HZ * CH_PP * 2];   // 16 channels = two uint4 per voxel
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int nxy = (D + CT_XY - 1) / CT_XY, nzt = (D + TZ - 1) / TZ;
+    int b = blockIdx.x;
+    const int bx = b % nxy;
+    b /= nxy;
+    const int by = b % nxy;
+    b /= nxy;
+    const int bz = b % nzt;
+    const int n = b / nzt;
+    const int x0 = bx * CT_XY, y0 = by * CT_XY, z0 = bz * TZ;
+    // this lane's voxel (row m of A) in each of the wave's M tiles, in uint4 units
+    int abase[MV];
 #pragma unroll
     for (int u = 0; u < MV; ++u) {
-        const int va = v0 + 16 * u + m;
-        aval[u] = va < nvox;
-        const int vs = aval[u] ? va : 0;
-        n[u] = vs / D3;
-        const int r = vs - n[u] * D3;
-        z[u] = r / (D * D);
-        y[u] = (r / D) % D;
-        x[u] = r % D;
+        const int ut = wv * MV + u, lz = ut >> 2, p = ut & 3;
+        const int lx = (p & 1) * 4 + (m & 3), ly = (p >> 1) * 4 + (m >> 2);
+        abase[u] = ((lz + 1) * CH_PP + (ly + 1) * CH_RP + (lx + 1)) * 2 + (g & 1);
     }
     f4_t acc[MV][NCO];
 #pragma unroll
     for (int u = 0; u < MV; ++u)
 #pragma unroll
         for (int t = 0; t < NCO; ++t) acc[u][t] = (f4_t){0.f, 0.f, 0.f, 0.f};
-    for (int tap = 0; tap < 27; ++tap) {
-        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
-        const bf16_t *xp[MV];
-        bool ok[MV];
-#pragma unroll
-        for (int u = 0; u < MV; ++u) {
-            const int zz = z[u] + dz, yy = y[u] + dy, xx = x[u] + dx;
-            ok[u] = aval[u] && (unsigned)zz < (unsigned)D && (unsigned)yy < (unsigned)D && (unsigned)xx < (unsigned)D;
-            const long long vn = ok[u] ? (long long)n[u] * D3 + (zz * D + yy) * D + xx : 0;
-            xp[u] = X + vn * Cin + 4 * kq;
+    const int nch = Cin / 16;
+    for (int ch = 0; ch < nch; ++ch) {
+        if (ch) __syncthreads();   // the previous chunk's reads are done
+        for (int i = tid; i < HZ * CH_XY * CH_XY * 2; i += 256) {
+            const int h = i >> 1, half = i & 1;
+            const int hx = h % CH_XY, hy = (h / CH_XY) % CH_XY, hz = h / (CH_XY * CH_XY);
+            const int x = x0 - 1 + hx, y = y0 - 1 + hy, z = z0 - 1 + hz;
+            uint4 v = {0u, 0u, 0u, 0u};
+            if ((unsigned)x < (unsigned)D && (unsigned)y < (unsigned)D && (unsigned)z < (unsigned)D)
+                v = *reinterpret_cast<const uint4 *>(X + ((((long long)n * D + z) * D + y) * D + x) * Cin + ch * 16 +
+                                                     half * 8);
+            tile[(hz * CH_PP + hy * CH_RP + hx) * 2 + half] = v;
         }
-        const bf16_t *wp = W + ((long long)tap * Cout + m) * Cin + 4 * kq;
-        for (int cb = 0; cb < Cin; cb += 16) {
-            s4_t a[MV];
+        __syncthreads();
+        const bf16_t *wp = W + ((long long)ch * 14 * Cout + m) * 32 + g * 8;
+#pragma unroll
+        for (int s = 0; s < 14; ++s) {
+            const int tap = 2 * s + (g >> 1);
+            const int toff = tap < 27 ? ((tap / 9 - 1) * CH_PP + ((tap / 3) % 3 - 1) * CH_RP + (tap % 3 - 1)) * 2 : 0;
+            bf8_t bw[NCO];
+#pragma unroll
+            for (int t = 0; t < NCO; ++t)
+                bw[t] = __builtin_bit_cast(bf8_t, *reinterpret_cast<const uint4 *>(wp + ((long long)s * Cout + t * 16) * 32));
 #pragma unroll
             for (int u = 0; u < MV; ++u) {
-                a[u] = *reinterpret_cast<const s4_t *>(xp[u] + cb);
-                if (!ok[u]) a[u] = (s4_t){0, 0, 0, 0};
-            }
+                const bf8_t a = __builtin_bit_cast(bf8_t, tile[abase[u] + toff]);
 #pragma unroll
-            for (int t = 0; t < NCO; ++t) {
-                const s4_t b = *reinterpret_cast<const s4_t *>(wp + (long long)t * 16 * Cin + cb);
-#pragma unroll
-                for (int u = 0; u < MV; ++u)
-                    acc[u][t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[u], b, acc[u][t], 0, 0, 0);
+                for (int t = 0; t < NCO; ++t)
+                    acc[u][t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, bw[t], acc[u][t], 0, 0, 0);
             }
         }
     }
+    // row 4g + i of an M tile is voxel (x + i, y + g) of its patch
 #pragma unroll
-    for (int u = 0; u < MV; ++u)
+    for (int u = 0; u < MV; ++u) {
+        const int ut = wv * MV + u, p = ut & 3;
+        const int z = z0 + (ut >> 2), y = y0 + (p >> 1) * 4 + g;
+        if (z >= D || y >= D) continue;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            const int v = v0 + 16 * u + 4 * kq + i;
-            if (v >= nvox) continue;
+            const int x = x0 + (p & 1) * 4 + i;
+            if (x >= D) continue;
+            const long long v = (((long long)n * D + z) * D + y) * D + x;
 #pragma unroll
             for (int t = 0; t < NCO; ++t) {
                 float val = acc[u][t][i];
                 if (RELU) val = fmaxf(val, 0.f);
-                const long long o = (long long)v * Cout + t * 16 + m;
+                const long long o = v * Cout + t * 16 + m;
                 if (OUT_F32)
                     static_cast<float *>(Yv)[o] = val;
                 else
                     static_cast<bf16_t *>(Yv)[o] = f2bf(val);
             }
         }
+    }
+}
+
+// The same convolution for cubes smaller than a tile (D < CT_XY, the coarse
+// levels, where a tile would be mostly padding and a launch has few tiles).
+// grid (ceil(N D^3 / 16), Cout / 16), 256 threads: a work-group computes one
+// M tile of 16 consecutive voxels (sample-major, x fastest) times one
+// 16-channel output tile, its four waves splitting the K steps (chunk, tap
+// pair) four ways, their partial tiles summed in LDS in wave order.  The A
+// fragments come straight from global memory (these activations are small
+// and stay in L2); same packed weights and slot map as k_conv3.
+template <bool RELU, bool OUT_F32>
+__global__ __launch_bounds__(256) void k_conv3_small(const bf16_t *__restrict__ X, const bf16_t *__restrict__ W,
+                                                     void *Yv, int N, int D, int Cin, int Cout)
+{
+    __shared__ f4_t part[3][64];
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int m = lane & 15, g = lane >> 4;
+    const int D3 = D * D * D, nvox = N * D3;
+    const int va = blockIdx.x * 16 + m;
+    const bool av = va < nvox;
+    const int vs = av ? va : 0;
+    const int n = vs / D3, r = vs - n * D3;
+    const int z = r / (D * D), y = (r / D) % D, x = r % D;
+    const int co = blockIdx.y * 16 + m;
+    f4_t acc = {0.f, 0.f, 0.f, 0.f};
+    const int nk = (Cin / 16) * 14;
+    for (int kk = wv; kk < nk; kk += 4) {
+        const int ch = kk / 14, s = kk - ch * 14;
+        const int tap = 2 * s + (g >> 1);
+        const int dz = tap / 9 - 1, dy = (tap / 3) % 3 - 1, dx = tap % 3 - 1;
+        const bf8_t bw = __builtin_bit_cast(
+            bf8_t, *reinterpret_cast<const uint4 *>(W + (((long long)ch * 14 + s) * Cout + co) * 32 + g * 8));
+        const int zz = z + dz, yy = y + dy, xx = x + dx;
+        const bool ok = av && tap < 27 && (unsigned)zz < (unsigned)D && (unsigned)yy < (unsigned)D &&
+                        (unsigned)xx < (unsigned)D;
+        const long long vn = ok ? ((long long)n * D + zz) * D * D + (long long)yy * D + xx : 0;
+        uint4 raw = *reinterpret_cast<const uint4 *>(X + vn * Cin + ch * 16 + (g & 1) * 8);
+        if (!ok) raw = (uint4){0u, 0u, 0u, 0u};
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, raw), bw, acc, 0, 0, 0);
+    }
+    if (wv) part[wv - 1][lane] = acc;
+    __syncthreads();
+    if (wv) return;
+#pragma unroll
+    for (int w = 0; w < 3; ++w) acc += part[w][lane];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int v = blockIdx.x * 16 + 4 * g + i;
+        if (v >= nvox) continue;
+        float val = acc[i];
+        if (RELU) val = fmaxf(val, 0.f);
+        const long long o = (long long)v * Cout + co;
+        if (OUT_F32)
+            static_cast<float *>(Yv)[o] = val;
+        else
+            static_cast<bf16_t *>(Yv)[o] = f2bf(val);
+    }
+}
+
+// work-groups of k_conv3 for N samples of edge D
+__host__ __device__ constexpr long long conv_tiles(int N, int D, int TZ)
+{
+    return (long long)N * ((D + TZ - 1) / TZ) * ((D + CT_XY - 1) / CT_XY) * ((D + CT_XY - 1) / CT_XY);
 }
 
 // dW[tap][co][ci] += sum_v dY[v][co] X[v + off(tap)][ci].
 // grid (ceil(N D^3 / chunk), 27, (Cout / 16) (Cin / 16)), 256 threads; each
-// wave walks 16-voxel slices of the chunk with stride 64.  A wave's four
-// lane groups take four consecutive voxels each; their coordinates are
-// carried incrementally.
+// wave walks 32-voxel slices of the chunk with stride 128 on the 16x16x32
+// MFMA (K = voxels).  A wave's four lane groups take eight consecutive
+// voxels each; their coordinates are carried incrementally.
 __global__ __launch_bounds__(256) void k_conv3_wgrad(const bf16_t *__restrict__ X, const bf16_t *__restrict__ dY,
                                                      float *dW, int N, int D, int Cin, int Cout, int chunk)
 {
@@ -148,13 +244,13 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const bf16_t *__restrict__ 
     const int c0 = blockIdx.x * chunk;
     const int c1 = min(c0 + chunk, nvox);
     f4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (int vb = c0 + wv * 16; vb < c1; vb += 64) {
-        const int v = vb + 4 * kq;
+    for (int vb = c0 + wv * 32; vb < c1; vb += 128) {
+        const int v = vb + 8 * kq;
         int n = v / D3, r = v - n * D3;
         int z = r / (D * D), y = (r / D) % D, x = r % D;
-        s4_t a, b;
+        s8_t a, b;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
+        for (int i = 0; i < 8; ++i) {
             const bool ok = v + i < c1;
             const int zz = z + dz, yy = y + dy, xx = x + dx;
             const bool okn = ok && (unsigned)zz < (unsigned)D && (unsigned)yy < (unsigned)D && (unsigned)xx < (unsigned)D;
@@ -166,7 +262,8 @@ __global__ __launch_bounds__(256) void k_conv3_wgrad(const bf16_t *__restrict__ 
             b[i] = okn ? (short)bv : (short)0;
             if (++x == D) { x = 0; if (++y == D) { y = 0; if (++z == D) { z = 0; ++n; } } }
         }
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8_t, a), __builtin_bit_cast(bf8_t, b), acc, 0,
+                                                      0, 0);
     }
     // sum the four waves' tiles in LDS, then one atomic per element
 #pragma unroll
@@ -297,10 +394,10 @@ __global__ void k_loss(const float *out, const float2 *tgt, bf16_t *dout, float 
     }
 }
 
-// Adam on the FP32 master weights (gradient cleared after use), then the
-// bf16 copies read by the forward (W[tap][co][ci]) and input-gradient
-// (Wt[tap][ci][co] = W[26 - tap][co][ci]) convolutions.  lr = 0 only
-// refreshes the bf16 copies.
+// Adam on the FP32 master weights W[tap][co][ci] (gradient cleared after
+// use), then the bf16 copies packed for k_conv3: the forward one, and the
+// input-gradient one of the transposed layer (Cout inputs, Cin outputs, tap
+// 26 - tap).  lr = 0 only refreshes the bf16 copies.
 __global__ void k_adam(float *w, float *m, float *v, float *g, bf16_t *w16, bf16_t *wt16, int Cin, int Cout, float lr,
                        float b1, float b2, float c1, float c2, float eps)
 {
@@ -318,8 +415,9 @@ __global__ void k_adam(float *w, float *m, float *v, float *g, bf16_t *w16, bf16
         }
         g[t] = 0.f;
         const int ci = (int)(t % Cin), co = (int)((t / Cin) % Cout), tap = (int)(t / ((long long)Cin * Cout));
-        w16[t] = f2bf(wn);
-        wt16[((long long)(26 - tap) * Cin + ci) * Cout + co] = f2bf(wn);
+        const int tt = 26 - tap;
+        w16[((long long)(ci / 16 * 14 + tap / 2) * Cout + co) * 32 + (tap & 1) * 16 + ci % 16] = f2bf(wn);
+        wt16[((long long)(co / 16 * 14 + tt / 2) * Cin + ci) * 32 + (tt & 1) * 16 + co % 16] = f2bf(wn);
     }
 }
 
@@ -621,8 +719,12 @@ ExxNet *net_create(int f, unsigned long long seed, hipError_t *err)
         for (size_t t = 0; t < n; ++t) w[t] = (l == 0 && (int)(t % ly.cin) >= kInChannels) ? 0.f : nd(rng);
         for (float **p : {&ly.w, &ly.m, &ly.v, &ly.g})
             if ((*err = hipMalloc(p, n * sizeof(float))) != hipSuccess) return net;
-        if ((*err = hipMalloc(&ly.w16, n * sizeof(bf16_t))) != hipSuccess) return net;
-        if ((*err = hipMalloc(&ly.wt16, n * sizeof(bf16_t))) != hipSuccess) return net;
+        // packed copies: 14 tap pairs per 16-channel chunk, the 28th tap zero
+        const size_t n16 = 28ULL * ly.cin * ly.cout * sizeof(bf16_t);
+        for (bf16_t **p : {&ly.w16, &ly.wt16}) {
+            if ((*err = hipMalloc(p, n16)) != hipSuccess) return net;
+            if ((*err = hipMemset(*p, 0, n16)) != hipSuccess) return net;
+        }
         if ((*err = hipMemcpy(ly.w, w.data(), n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return net;
         for (float *p : {ly.m, ly.v, ly.g})
             if ((*err = hipMemcpy(p, zero.data(), n * sizeof(float), hipMemcpyHostToDevice)) != hipSuccess) return net;
@@ -653,14 +755,20 @@ static void conv(ExxNet *net, int l, const bf16_t *X, void *Y, int N, int D, boo
     const auto &ly = net->L[l];
     const int cin = transposed ? ly.cout : ly.cin, cout = transposed ? ly.cin : ly.cout;
     const bf16_t *W = transposed ? ly.wt16 : ly.w16;
-    const long long nvox = (long long)N * D * D * D;
-    // voxel tiles per wave: enough MFMAs per loaded fragment at few channels
+    // M tiles per wave (= tile depth): eight MFMA accumulators per wave; cubes
+    // smaller than a tile take the flat kernel
     switch (cout / 16 * 4 + (f32 ? 2 : 0) + (relu ? 1 : 0)) {
 #define EXX_CONV_CASE(NCO, RELU, F32)                                                                       \
     case NCO * 4 + (F32 ? 2 : 0) + (RELU ? 1 : 0): {                                                        \
-        constexpr int MV = NCO == 1 ? 4 : NCO == 2 ? 2 : 1;                                                 \
-        const dim3 grid((unsigned)((nvox + 64 * MV - 1) / (64 * MV)));                                      \
-        hipLaunchKernelGGL((k_conv3<MV, NCO, RELU, F32>), grid, dim3(256), 0, s, X, W, Y, N, D, cin);        \
+        constexpr int MV = NCO == 1 ? 8 : NCO == 2 ? 4 : NCO <= 4 ? 2 : 1;                                  \
+        if (D >= CT_XY) {                                                                                   \
+            const dim3 grid((unsigned)conv_tiles(N, D, MV));                                                \
+            hipLaunchKernelGGL((k_conv3<MV, NCO, RELU, F32>), grid, dim3(256), 0, s, X, W, Y, N, D, cin);    \
+        } else {                                                                                            \
+            const long long nvox = (long long)N * D * D * D;                                                \
+            const dim3 grid((unsigned)((nvox + 15) / 16), (unsigned)NCO);                                   \
+            hipLaunchKernelGGL((k_conv3_small<RELU, F32>), grid, dim3(256), 0, s, X, W, Y, N, D, cin, cout); \
+        }                                                                                                   \
         break;                                                                                              \
     }
 #define EXX_CONV_CASES(NCO) EXX_CONV_CASE(NCO, false, false) EXX_CONV_CASE(NCO, true, false) EXX_CONV_CASE(NCO, false, true)
@@ -675,7 +783,7 @@ static void conv(ExxNet *net, int l, const bf16_t *X, void *Y, int N, int D, boo
 static void wgrad(const ExxNet::Layer &ly, const bf16_t *X, const bf16_t *dY, float *dW, int N, int D, hipStream_t s)
 {
     const long long nvox = (long long)N * D * D * D;
-    const int chunk = 2048;   // 8 passes of the 4 waves over 64 voxels
+    const int chunk = 2048;   // 16 passes of the 4 waves over 128 voxels
     const dim3 grid((unsigned)((nvox + chunk - 1) / chunk), 27u, (unsigned)((ly.cout / 16) * (ly.cin / 16)));
     hipLaunchKernelGGL(k_conv3_wgrad, grid, dim3(256), 0, s, X, dY, dW, N, D, ly.cin, ly.cout, chunk);
 }
@@ -942,7 +1050,7 @@ int net_blob_coarsen(const void *host, size_t bytes)
     if (!host || bytes != net_model_bytes() || std::memcmp(host, kMagic, 8) != 0) return -1;
     int32_t hdr[2];
     std::memcpy(hdr, static_cast<const char *>(host) + 8, 8);
-    if ((hdr[0] != 2 && hdr[0] != 4) || hdr[1] != kLayers) return -1;
+    if ((hdr[0] != 2 && hdr[0] != 4 && hdr[0] != 8) || hdr[1] != kLayers) return -1;
     return hdr[0];
 }
 

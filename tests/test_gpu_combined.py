@@ -1,7 +1,7 @@
 """The 512-water configuration with everything at once: per-pair subdomain
 classes (uneven truncated subdomains), the learned initial guess, the
 multigrid-preconditioned iteration in FP32 with FP64 residual replacement,
-FP32 orbitals on local boxes, pairs in waves, over three synthetic MD steps
+FP32 orbitals on local boxes, pairs in waves, over five synthetic MD steps
 (centres displaced, pair list and classes rebuilt every step).
 
 Every step: each pair converged to the FP64 residual bar, E_xx the weighted
@@ -91,7 +91,7 @@ def test_water512_classes_learned_fp32_multigrid_md():
     rng = np.random.default_rng(2718)
     orbs = wl.orbitals
     spreads = S.spreads(orbs)
-    for step in range(3):
+    for step in range(5):
         wl_k = dataclasses.replace(wl, orbitals=orbs)
         n = ctx.pairs_spread(orbs.centers, spreads)
         org = ctx.box_origins()
@@ -105,7 +105,7 @@ def test_water512_classes_learned_fp32_multigrid_md():
         assert np.all(info["converged"] == 1) and info["relres"].max() <= RELRES_BAR
         w = np.where(info["i"] == info["j"], 1.0, 2.0)
         assert abs(E + np.sum(w * info["e"])) <= 1e-12 * abs(E)
-        if step < 2:
+        if step < 4:
             orbs = S.md_displace(orbs, wl.cell[0], rng)
     assert st["n_waves"] > 1
     # sampled pairs of the last step: one per class in use, and a self pair

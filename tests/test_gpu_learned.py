@@ -238,13 +238,15 @@ def test_learned_guess_is_deterministic(c1_ref, trained):
     assert np.array_equal(it1, ctx.pair_info()["iters"])
 
 
-def test_untrained_and_corrupt_models_still_converge(c1_ref):
+@pytest.mark.parametrize("coarsen", [4, 8])
+def test_untrained_and_corrupt_models_still_converge(c1_ref, coarsen):
     """A random model gives a poor but finite guess; non-finite weights give
     non-finite net outputs, which become a zero guess.  Both reach the same
-    result."""
+    result (at 8 grid points per coarse cell the small workload's cube is 8
+    cells wide and the net's coarsest level a single cell)."""
     wl, phi, E, D, out = c1_ref
     ctx = X.Exx.from_workload(wl)
-    ctx.model_init(4, seed=1)
+    ctx.model_init(coarsen, seed=1)
     good = ctx.model_save()
     bad = bytearray(good)
     w = np.frombuffer(bad, dtype=np.float32, offset=16)

@@ -614,3 +614,29 @@ def test_dxx_orbital_equals_the_whole_step(c1_result, k):
     Dk = O.dxx_orbital(wl.n_grid, wl.cell, two, C, {q: phi[q] for q in touch}, pi, pj, cls, k, nthreads=4)
     assert np.array_equal(Dk, D[k])
     assert len(sel) >= 3
+
+
+def test_water64_golden_file_is_the_oracle_step():
+    """tests/golden/water64_oracle.npz (the oracle's whole 64-water step, written
+    by tests/golden/make_water64_oracle.py) holds the workload's pair list in
+    the oracle's order, E_xx as the weighted sum of its pair energies
+    (Eq. exx_omega), and, re-solved here, bit for bit the oracle's per-pair
+    results on a self pair and two other pairs."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "water64_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip("golden file not written")
+    g = np.load(path, allow_pickle=False)
+    wl = S.c2_water64()
+    pi, pj = O.pair_list(wl.orbitals.centers, wl.cell, wl.r_pair)
+    assert np.array_equal(g["i"], pi) and np.array_equal(g["j"], pj)
+    w = np.where(g["i"] == g["j"], 1.0, 2.0)
+    assert abs(float(g["E"]) + np.sum(w * g["e"])) <= 1e-13 * abs(float(g["E"]))
+    assert np.all(g["converged"] == 1) and g["relres"].max() <= 1e-10 * (1 + 1e-4)
+    pick = np.array([int(np.nonzero(g["i"] == g["j"])[0][3]), 1234, 8765])
+    need = sorted(set(g["i"][pick].tolist()) | set(g["j"][pick].tolist()))
+    phis = dict(zip(need, S.orbitals_np(wl, need)))
+    res = O.solve_pairs(wl.n_grid, wl.cell, wl.r_pe, wl.r_me, wl.orbitals.centers, phis, g["i"][pick], g["j"][pick],
+                        tol=wl.cg_rtol, nthreads=3)
+    for key in ("e", "iters", "converged", "relres"):
+        assert np.array_equal(res[key], g[key][pick]), key
