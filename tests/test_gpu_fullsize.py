@@ -134,6 +134,51 @@ def _oracle_orbitals(wl, idx, origins):
     return S.embed_boxes(vals, [origins[k] for k in idx], wl.n_grid)
 
 
+# Whole-step parity at full size: every pair energy and E_xx of the 64-water
+# step against the oracle's own whole step (tests/golden/water64_oracle.npz,
+# written by tests/golden/make_water64_oracle.py, which calls only the
+# oracle; Eq. exx_omega).  Placed before the 512-water fixture, which sizes
+# its waves to the free memory.
+GOLDEN_C2 = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "water64_oracle.npz")
+
+
+def _golden_c2():
+    if not __import__("os").path.exists(GOLDEN_C2):
+        pytest.skip("tests/golden/water64_oracle.npz not written yet")
+    return np.load(GOLDEN_C2, allow_pickle=False)
+
+
+def test_c2_every_pair_and_energy_vs_oracle_step(c2_run):
+    wl, ctx, n, E, D, info = c2_run
+    g = _golden_c2()
+    assert np.array_equal(g["i"], info["i"]) and np.array_equal(g["j"], info["j"])
+    assert np.all(g["converged"] == 1)
+    rel = np.abs(info["e"] - g["e"]) / np.abs(g["e"])
+    _say(f"[gpu] 64-water, all {n} pairs: max rel pair-energy difference {rel.max():.2e}, "
+         f"E {E:.12f} vs oracle {float(g['E']):.12f}")
+    assert rel.max() <= 1e-8, (int(np.argmax(rel)), rel.max())
+    assert abs(E - float(g["E"])) <= 1e-8 * abs(float(g["E"]))
+
+
+def test_c2_multigrid_every_pair_vs_oracle_step():
+    """The multigrid-preconditioned FP64 iteration stops on the same residual:
+    every pair energy and E_xx against the oracle's plain-CG step."""
+    g = _golden_c2()
+    wl = S.c2_water64()
+    _say("[gpu] 64-water workload, multigrid-preconditioned FP64, full step")
+    # runs before the 512-water fixture, whose waves are sized to the free memory
+    torch.cuda.empty_cache()
+    phi = S.orbitals_torch(wl, device="cuda:0")
+    ctx = X.Exx.from_workload(wl, precond="mg")
+    ctx.pairs(wl.orbitals.centers)
+    E, _ = ctx.step(phi)
+    info = ctx.pair_info()
+    rel = np.abs(info["e"] - g["e"]) / np.abs(g["e"])
+    _say(f"[gpu] multigrid: max rel pair-energy difference {rel.max():.2e}")
+    assert rel.max() <= 1e-8 and abs(E - float(g["E"])) <= 1e-8 * abs(float(g["E"]))
+    ctx.close()
+
+
 @pytest.fixture(scope="module")
 def c5_run():
     wl = S.c5_water512()
@@ -193,51 +238,10 @@ def test_c5_sampled_pairs_vs_oracle(c5_run):
 
 
 # ---------------------------------------------------------------------------
-# Whole-step parity at full size: every pair energy and E_xx against the
-# oracle's own whole step (tests/golden/water64_oracle.npz, written by
-# tests/golden/make_water64_oracle.py, which calls only the oracle), and
-# whole orbitals' D^k against the oracle's D^k over all of k's pairs
-# (Eqs. exx_omega, Dxx_mlwf_omega; gamma^k as in Eq. gammaxx_i:
+# Whole orbitals at full size: D^k against the oracle's D^k over all of k's
+# pairs (Eq. Dxx_mlwf_omega; gamma^k as in Eq. gammaxx_i:
 # sum |D - D_ref| / sum |D_ref| over the grid).
 # ---------------------------------------------------------------------------
-
-GOLDEN_C2 = __import__("os").path.join(__import__("os").path.dirname(__file__), "golden", "water64_oracle.npz")
-
-
-def _golden_c2():
-    if not __import__("os").path.exists(GOLDEN_C2):
-        pytest.skip("tests/golden/water64_oracle.npz not written yet")
-    return np.load(GOLDEN_C2, allow_pickle=False)
-
-
-def test_c2_every_pair_and_energy_vs_oracle_step(c2_run):
-    wl, ctx, n, E, D, info = c2_run
-    g = _golden_c2()
-    assert np.array_equal(g["i"], info["i"]) and np.array_equal(g["j"], info["j"])
-    assert np.all(g["converged"] == 1)
-    rel = np.abs(info["e"] - g["e"]) / np.abs(g["e"])
-    _say(f"[gpu] 64-water, all {n} pairs: max rel pair-energy difference {rel.max():.2e}, "
-         f"E {E:.12f} vs oracle {float(g['E']):.12f}")
-    assert rel.max() <= 1e-8, (int(np.argmax(rel)), rel.max())
-    assert abs(E - float(g["E"])) <= 1e-8 * abs(float(g["E"]))
-
-
-def test_c2_multigrid_every_pair_vs_oracle_step():
-    """The multigrid-preconditioned FP64 iteration stops on the same residual:
-    every pair energy and E_xx against the oracle's plain-CG step."""
-    g = _golden_c2()
-    wl = S.c2_water64()
-    _say("[gpu] 64-water workload, multigrid-preconditioned FP64, full step")
-    phi = S.orbitals_torch(wl, device="cuda:0")
-    ctx = X.Exx.from_workload(wl, precond="mg")
-    ctx.pairs(wl.orbitals.centers)
-    E, _ = ctx.step(phi)
-    info = ctx.pair_info()
-    rel = np.abs(info["e"] - g["e"]) / np.abs(g["e"])
-    _say(f"[gpu] multigrid: max rel pair-energy difference {rel.max():.2e}")
-    assert rel.max() <= 1e-8 and abs(E - float(g["E"])) <= 1e-8 * abs(float(g["E"]))
-    ctx.close()
-
 
 def _dk_oracle(wl, k, info, phis, classes):
     sel = np.nonzero((info["i"] == k) | (info["j"] == k))[0]
