@@ -47,6 +47,20 @@ def kernel_hash() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
+def host_cpu() -> str:
+    """CPU model and logical core count of the host running the oracle."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return f"{model}, {os.cpu_count()} logical cores visible"
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -572,6 +586,7 @@ def main():
         else:
             cb, pick, res = cpu_baseline_fixed(wl, info["i"], info["j"], n_sample, threads, origins=origins)
         line["cpu_baseline"] = cb
+        line["detail"]["host_cpu"] = host_cpu()
         rel = np.abs(pinfo["e"][pick] - res["e"]) / np.abs(res["e"])
         line["detail"]["sample_pair_energy_max_rel_vs_oracle"] = float(rel.max())
     print(json.dumps(line), flush=True)
