@@ -549,7 +549,7 @@ def main():
                             iters_max=st["iters_max"], relres_max=st["relres_max"], n_not_converged=st["n_not_converged"],
                             pairs_build_s=round(t_pairs, 3), solve_ms=round(st["solve_ms"], 2),
                             cg_clock_ms=round(st["cg_clock_ms"], 2), cg_event_ms=round(st["cg_ms"], 2),
-                            dxx_ms=round(st["dxx_ms"], 2), energy_ms=round(st["energy_ms"], 3),
+                            dxx_in_energy_potential_ms=round(st["dxx_ms"], 2), energy_ms=round(st["energy_ms"], 3),
                             cg_bytes=st["cg_bytes"], grid=st["solve_grid"], block=st["solve_block"],
                             cg_cols=st["cg_cols"], cg_bands=st["cg_bands"], waves=st["n_waves"],
                             autotuned_variants=st["tuned"], tune_ms=round(st["tune_ms"], 1),

@@ -139,7 +139,10 @@ typedef struct {
     double  prep_ms;         /* last exx_solve: pair-preparation kernel         */
     double  cg_ms;           /* last exx_solve: persistent CG kernel, summed over
                                 waves (HIP events around each launch)          */
-    double  dxx_ms;          /* last exx_energy_potential: D kernel, HIP events */
+    double  dxx_ms;          /* last exx_energy_potential: D kernel, HIP events
+                                (pairs in waves: D is summed wave by wave inside
+                                exx_solve, and this times only the rounding of
+                                the FP64 partial sums)                         */
     double  energy_ms;       /* last exx_energy_potential: E reduction          */
     int32_t solve_grid;      /* persistent work-groups launched                 */
     int32_t solve_block;     /* threads per work-group                          */
