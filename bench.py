@@ -227,8 +227,12 @@ def learned_full(wl, phi, dxx, spreads, classes, head, args):
     rows = {"mg": dict(ms_per_step=head["ms_per_step"], solves_per_s=head["solves_per_s"],
                        iters_mean=head["iters_mean"], cg_clock_ms=head["cg_clock_ms"], E_xx=head["E_xx"],
                        rel_diff_E_vs_mg=0.0, note="the timed headline steps")}
+    variant = {"mg": tuple(head["variant"])}   # the zero-guess run's CG variant, forced on its learned twin
     for name, kw in (("mg+learned", dict(guess="learned")), ("mg_fp32", dict(precision="fp32_refine")),
                      ("mg_fp32+learned", dict(guess="learned", precision="fp32_refine"))):
+        base = name.split("+")[0]
+        if name != base and base in variant:
+            kw = dict(kw, block_threads=variant[base][0], cg_cols=variant[base][1])
         w = dataclasses.replace(wl)
         w.precision = kw.pop("precision", "fp64")
         ctx = X.Exx.from_workload(w, graph=True, **ckw, **kw)
@@ -238,10 +242,13 @@ def learned_full(wl, phi, dxx, spreads, classes, head, args):
         step_timed(ctx, phi, dxx, stream, 1)                     # warm-up: graph build
         E, dt = step_timed(ctx, phi, dxx, stream, 1)
         st = ctx.stats()
+        if name == base:
+            variant[name] = (st["solve_block"], st["cg_cols"])
         rows[name] = dict(ms_per_step=round(1e3 * dt, 2), solves_per_s=round(n / dt, 1),
                           iters_mean=round(st["iters_total"] / n, 2), guess_ms=round(st["guess_ms"], 2),
                           cg_clock_ms=round(st["cg_clock_ms"], 2), E_xx=E,
-                          rel_diff_E_vs_mg=abs(E - head["E_xx"]) / abs(head["E_xx"]))
+                          rel_diff_E_vs_mg=abs(E - head["E_xx"]) / abs(head["E_xx"]),
+                          variant=[st["solve_block"], st["cg_cols"]])
         ctx.close()
         log(f"[bench] {name}: {1e3 * dt:.0f} ms, {rows[name]['iters_mean']} iterations")
     base = rows["mg"]["ms_per_step"]
@@ -297,8 +304,12 @@ def learned_vs_plain(wl, args):
         f"loss {loss0:.3g} -> {loss:.3g}")
     rows = {}
     E_plain = None
+    variant = {}   # the zero-guess run's CG variant, forced on its learned twin
     for name, kw in (("plain", dict()), ("plain+learned", dict(guess="learned")), ("mg", dict(precond="mg")),
                      ("mg+learned", dict(precond="mg", guess="learned"))):
+        base = name.split("+")[0]
+        if name != base and base in variant:
+            kw = dict(kw, block_threads=variant[base][0], cg_cols=variant[base][1])
         ctx, n, phi = make(eval_wl, **kw)
         if "learned" in name:
             ctx.load_model(blob)
@@ -306,12 +317,15 @@ def learned_vs_plain(wl, args):
         step_timed(ctx, phi, dxx, stream, 1)                     # warm-up (first graph-free launch)
         E, dt = step_timed(ctx, phi, dxx, stream, 1)
         st = ctx.stats()
+        if name == base:
+            variant[name] = (st["solve_block"], st["cg_cols"])
         if E_plain is None:
             E_plain = E
         rows[name] = dict(ms_per_step=round(1e3 * dt, 2), solves_per_s=round(n / dt, 1),
                           iters_mean=round(st["iters_total"] / n, 2), guess_ms=round(st["guess_ms"], 2),
                           cg_clock_ms=round(st["cg_clock_ms"], 2), E_xx=E,
-                          rel_diff_E_vs_plain=abs(E - E_plain) / abs(E_plain))
+                          rel_diff_E_vs_plain=abs(E - E_plain) / abs(E_plain),
+                          variant=[st["solve_block"], st["cg_cols"]])
         ctx.close()
         del phi, dxx
     base = rows["plain"]["ms_per_step"]
@@ -568,7 +582,7 @@ def main():
                 log("[bench] learned guess on the headline configuration (untimed)")
                 head = dict(ms_per_step=round(ms_per_step, 2), solves_per_s=round(value, 1),
                             iters_mean=round(st["iters_total"] / n_pairs, 2), cg_clock_ms=round(st["cg_clock_ms"], 2),
-                            E_xx=E)
+                            E_xx=E, variant=[st["solve_block"], st["cg_cols"]])
                 line["learned_full"] = learned_full(wl, phi, dxx, spreads, classes, head, args)
         log("[bench] learned vs plain on a subsystem (untimed)")
         del phi, dxx

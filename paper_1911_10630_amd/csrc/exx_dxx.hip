@@ -3,11 +3,12 @@
 // whole ME sphere of each pair, owner computes, in pair order, no atomics.
 //
 // One work-group per compact tile of orbital k's box (DXX_TX x DXX_TY x
-// DXX_TZ points; each thread one (x, y) column of DXX_PER_THREAD points along
-// z, DXX_ZT threads per column).  The work-group walks k's pairs of the
-// current wave in pair order and skips, as a whole, every pair whose ME
-// bounding box misses the tile's bounding box; a compact tile meets few of
-// the pairs, and of a pair it meets most points lie in the ME box.  Each point adds the contributions of
+// DXX_TZ points; each thread a run of DXX_PER_THREAD consecutive x points of
+// one row, so one lookup of the pair's ME row table serves the run).  The
+// work-group walks k's pairs of the current wave in pair order and skips, as
+// a whole, every pair whose ME bounding box misses the tile's bounding box; a
+// compact tile meets few of the pairs, and of a pair it meets most points lie
+// in the ME box.  Each point adds the contributions of
 // the pairs whose ME sphere holds it in pair order, so the sum is the same
 // FP64 sum whatever the tiling.  With the pairs in waves the sums are carried
 // across waves in FP64 partial sums and rounded once at the end.
@@ -17,11 +18,11 @@
 
 namespace exx {
 
-// 16 x 8 x 8 points; 32 x 8 x 4 (rows of whole 128-byte lines of an FP32
-// orbital) fetches a quarter fewer bytes but ran 6 % slower
-constexpr int DXX_TX = 16, DXX_TY = 8, DXX_ZT = 2, DXX_PER_THREAD = 4;
-constexpr int DXX_BLOCK = DXX_TX * DXX_TY * DXX_ZT;
-constexpr int DXX_TZ = DXX_ZT * DXX_PER_THREAD;
+// 32 x 8 x 8 points, runs of 8: the fastest of the shapes timed on the
+// 512-water step (runs of 4, 8 or 16 in x; 32 x 4 x 16 and 32 x 16 x 4;
+// columns of 4 points along z in 16 x 8 x 8 and 32 x 8 x 4 tiles)
+constexpr int DXX_TX = 32, DXX_TY = 8, DXX_TZ = 8, DXX_PER_THREAD = 8;
+constexpr int DXX_BLOCK = DXX_TX / DXX_PER_THREAD * DXX_TY * DXX_TZ;
 
 // Do the cyclic index ranges [a0, a0 + alen) and [b0, b0 + blen) of Z_n meet
 // (a0, b0 in [0, n); lengths at most n)?
@@ -65,18 +66,19 @@ __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
                cyclic_meet(ys, ylen, wrap_n(pg.y + g.mylo, a.ny), g.mny, a.ny) &&
                cyclic_meet(xs, xlen, wrap_n(pg.x + g.mxlo, a.nx), g.mnx, a.nx);
     };
-    // this thread's column (x, y) and its points z = bz0 + zz + DXX_ZT e
-    const int lx = bx0 + (threadIdx.x % DXX_TX), ly = by0 + (threadIdx.x / DXX_TX) % DXX_TY;
-    const int zz = threadIdx.x / (DXX_TX * DXX_TY);
-    const bool col = lx < B.bx && ly < B.by;
+    // this thread's run of DXX_PER_THREAD consecutive x points at (y, z)
+    constexpr int QX = DXX_TX / DXX_PER_THREAD;
+    const int lx0 = bx0 + DXX_PER_THREAD * (threadIdx.x % QX);
+    const int ly = by0 + (threadIdx.x / QX) % DXX_TY, lz = bz0 + threadIdx.x / (QX * DXX_TY);
+    const bool row_ok = ly < B.by && lz < B.bz;
     bool any = false;
     for (int pp = lo; pp < hi && !any; ++pp) any = meets(a.orb_pairs[pp]);
     if (!any) {
         if (ACC && !a.acc_first) return;
 #pragma unroll
         for (int e = 0; e < DXX_PER_THREAD; ++e) {
-            const int lz = bz0 + zz + DXX_ZT * e;
-            if (!col || lz >= B.bz) continue;
+            const int lx = lx0 + e;
+            if (!row_ok || lx >= B.bx) continue;
             const long long li = ((long long)lz * B.by + ly) * B.bx + lx;
             if (ACC)
                 a.acc[(long long)k * B.vol + li] = 0.0;
@@ -85,17 +87,17 @@ __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
         }
         return;
     }
-    const int gx = wrap_n(ok_org.x + (col ? lx : 0), a.nx), gy = wrap_n(ok_org.y + (col ? ly : 0), a.ny);
+    const int gy = wrap_n(ok_org.y + (row_ok ? ly : 0), a.ny), gz = wrap_n(ok_org.z + (row_ok ? lz : 0), a.nz);
     double acc[DXX_PER_THREAD];
-    int gz[DXX_PER_THREAD];
+    int gx[DXX_PER_THREAD];
     bool ok[DXX_PER_THREAD];
     long long li[DXX_PER_THREAD];
 #pragma unroll
     for (int e = 0; e < DXX_PER_THREAD; ++e) {
-        const int lz = bz0 + zz + DXX_ZT * e;
-        ok[e] = col && lz < B.bz;
+        const int lx = lx0 + e;
+        ok[e] = row_ok && lx < B.bx;
         li[e] = ok[e] ? ((long long)lz * B.by + ly) * B.bx + lx : 0;
-        gz[e] = wrap_n(ok_org.z + (ok[e] ? lz : 0), a.nz);
+        gx[e] = wrap_n(ok_org.x + (ok[e] ? lx : 0), a.nx);
         acc[e] = ACC && !a.acc_first && ok[e] ? a.acc[(long long)k * B.vol + li[e]] : 0.0;
     }
     for (int pp = lo; pp < hi; ++pp) {
@@ -108,25 +110,25 @@ __global__ __launch_bounds__(DXX_BLOCK) void k_dxx(DxxArgs a)
         const double *v = a.vout + a.out_off[pair];
         const long long oo = (long long)other * B.vol;
         const int4 oo_org = B.org[other];
-        // the column's offsets in the pair's ME box (x, y shared by its points)
-        const int tx = wrap_n(gx - pg.x - g.mxlo, a.nx), ty = wrap_n(gy - pg.y - g.mylo, a.ny);
-        if (tx >= g.mnx || ty >= g.mny) continue;
-        const int ox = tx + g.mxlo;
+        // the run's row of the pair's ME box (shared by its points)
+        const int ty = wrap_n(gy - pg.y - g.mylo, a.ny), tz = wrap_n(gz - pg.z - g.mzlo, a.nz);
+        if (ty >= g.mny || tz >= g.mnz) continue;
+        const int row = tz * g.mny + ty;
+        const int4 r0 = g.me_rows[2 * row];
+        const int4 r1 = g.me_rows[2 * row + 1];
 #pragma unroll
         for (int e = 0; e < DXX_PER_THREAD; ++e) {
             if (!ok[e]) continue;
-            const int tz = wrap_n(gz[e] - pg.z - g.mzlo, a.nz);
-            if (tz >= g.mnz) continue;
-            const int row = tz * g.mny + ty;
-            const int4 r0 = g.me_rows[2 * row];
-            const int4 r1 = g.me_rows[2 * row + 1];
+            const int tx = wrap_n(gx[e] - pg.x - g.mxlo, a.nx);
+            if (tx >= g.mnx) continue;
+            const int ox = tx + g.mxlo;
             if (ox < r1.x || ox > r1.y) continue;
             double vv;
             if (ox >= r0.y && ox <= r0.z)
                 vv = v[r0.x + ox - r0.y];
             else
                 vv = v[g.n_pe + r0.w + (ox < r0.y ? ox - r1.x : (r0.y - r1.x) + (ox - r0.z - 1))];
-            acc[e] += vv * load_orb(a.phi, a.f32, B, oo, oo_org, gx, gy, gz[e], a.nx, a.ny, a.nz);
+            acc[e] += vv * load_orb(a.phi, a.f32, B, oo, oo_org, gx[e], gy, gz, a.nx, a.ny, a.nz);
         }
     }
 #pragma unroll
