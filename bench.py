@@ -527,6 +527,7 @@ def main():
             if (entry.get("kernel_hash") == kernel_hash() and entry.get("workload") == wl.name
                     and entry.get("precond") == args.precond and entry.get("omega_scale") == args.omega_scale
                     and entry.get("precision", "fp64") == wl.precision
+                    and entry.get("algorithmic_bytes_per_step") == st["cg_bytes"]
                     and entry.get("variant") == [st["solve_block"], st["cg_cols"]]):
                 # measured HBM bytes of the same launch (rocprofv3 FETCH_SIZE + WRITE_SIZE,
                 # calibrated on a device copy); FP64 iteration counts are deterministic

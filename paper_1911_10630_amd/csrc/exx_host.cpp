@@ -774,10 +774,18 @@ void mg_args(const exx_ctx *c, SolveArgs &a, double *scratch)
     a.mg_slot_n = mg_slot_doubles(c);
     // damping: the fine Jacobi step keeps M positive definite for
     // omega < 2 diag(A) / lambda_max(A) ~ 0.90 (the sixth-order stencil's
-    // largest eigenvalue is ~2.22 diag); the coarse one needs omega_c < 1
+    // largest eigenvalue is ~2.22 diag).  A coarse level contributes
+    // 2S - S L S (S = omega_c / diag L) plus a positive semidefinite term, so
+    // it stays positive definite while omega_c lambda_max(D^-1 L) < 2; the
+    // masked 7-point Laplacian with Dirichlet zero outside has
+    // lambda_max(D^-1 L) < 2, so omega_c = 1 qualifies.  One damped Jacobi step
+    // on the coarsest level: more sweeps there (a more exact coarse solve)
+    // took more PCG iterations on the water workloads (8 sweeps at
+    // omega_c = 0.9: 33.2 iterations on the 512-water step and 40.2 on the
+    // 64-water one; 1 step at omega_c = 1: 29.6 and 36.1).
     a.mg_omega = 0.8;
-    a.mg_omega_c = 0.9;
-    a.mg_coarse_sweeps = 8;
+    a.mg_omega_c = 1.0;
+    a.mg_coarse_sweeps = 1;
 }
 
 // Measured choice among the candidates: each runs kTuneIters CG iterations
