@@ -783,9 +783,16 @@ void mg_args(const exx_ctx *c, SolveArgs &a, double *scratch)
     // took more PCG iterations on the water workloads (8 sweeps at
     // omega_c = 0.9: 33.2 iterations on the 512-water step and 40.2 on the
     // 64-water one; 1 step at omega_c = 1: 29.6 and 36.1).
+    // The correction the V-cycle hands to the fine level is scaled by 0.5:
+    // with the piecewise-constant prolongation and the 7-point coarse
+    // operator the full correction overshoots (measured: 29.6 / 36.1
+    // iterations at scale 1, 27.2 / 33.1 at 0.4-0.6, 28.3 / 34.2 at 0.8,
+    // 31.7 / 37.5 at 1.2).  M stays positive definite for any positive scale
+    // (it multiplies a positive semidefinite term).
     a.mg_omega = 0.8;
     a.mg_omega_c = 1.0;
     a.mg_coarse_sweeps = 1;
+    a.mg_coarse_scale = 0.5;
 }
 
 // Measured choice among the candidates: each runs kTuneIters CG iterations

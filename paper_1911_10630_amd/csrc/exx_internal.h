@@ -175,6 +175,7 @@ struct SolveArgs {
     double mg_omega;            // damping of the fine Jacobi smoother
     double mg_omega_c;          // damping of the coarse Jacobi smoother
     int mg_coarse_sweeps;       // Jacobi sweeps on the coarsest level
+    double mg_coarse_scale;     // scale of the coarse correction reaching the fine level
 };
 
 // Initial guess of one pair from up to three earlier steps (Sec. III.C Step IV:

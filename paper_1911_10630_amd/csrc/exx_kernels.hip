@@ -1162,7 +1162,8 @@ __device__ const CT *mg_vcycle(const SolveArgs &a, const MgClass &M, CT *ms)
         ec = e;
     }
     // up: u(c) = wc d f(c) + e_coarse(parent of c) on the domain, then one
-    // damped Jacobi sweep, e(c) = (1 - wc) u(c) + wc d (f(c) + sum_a s_a u(neighbours))
+    // damped Jacobi sweep, e(c) = (1 - wc) u(c) + wc d (f(c) + sum_a s_a u(neighbours));
+    // on level 1, times the coarse-correction scale
     for (int l = nl - 2; l >= 0; --l) {
         const MgLevel L = M.lv[l], Lc = M.lv[l + 1];
         const int n = L.nx * L.ny * L.nz;
@@ -1177,8 +1178,12 @@ __device__ const CT *mg_vcycle(const SolveArgs &a, const MgClass &M, CT *ms)
             return L.cm[c] ? v : 0.0;
         });
         __syncthreads();
+        // the correction handed to the fine level (l = 0) is scaled by
+        // mg_coarse_scale, folded into the sweep's two coefficients
+        const double gsc = l == 0 ? a.mg_coarse_scale : 1.0;
+        const double a1 = gsc * (1.0 - wc), a2 = gsc * wd;
         mg_cells<T, MG_U, CT>(L, e, [&](int c, int x, int y, int z) -> double {
-            const double v = (1.0 - wc) * (double)u[c] + wd * ((double)f[c] + mg_nbsum(L, u, c, x, y, z, s));
+            const double v = a1 * (double)u[c] + a2 * ((double)f[c] + mg_nbsum(L, u, c, x, y, z, s));
             return L.cm[c] ? v : 0.0;
         });
         __syncthreads();
