@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdarg>
+#include <cstdint>
 #include <cstdio>
 #include <cstring>
 #include <mutex>
@@ -102,12 +103,13 @@ struct exx_ctx {
     std::vector<int2> ij;
     std::vector<int4> gc;
     std::vector<long long> out_off;
+    std::vector<long long> rhs_off;   // per pair: offset of its b in rhs (relative to its wave)
     std::vector<int> orb_ptr, orb_pairs;
     long long vout_n = 0;
 
     DevBuf<int2> d_ij;
     DevBuf<int4> d_gc;
-    DevBuf<long long> d_off;
+    DevBuf<long long> d_off, d_rhs_off;
     std::vector<int> queue;     // CG queue order per wave (empty: pair order)
     DevBuf<int> d_queue;
     DevBuf<int> d_orb_ptr, d_orb_pairs;
@@ -542,12 +544,6 @@ int big_class(const exx_ctx *c)
         if (c->cls[k].n_pe > c->cls[b].n_pe) b = k;
     return b;
 }
-long long max_me(const exx_ctx *c)
-{
-    long long m = 0;
-    for (int k = 0; k < c->n_cls; ++k) m = std::max(m, (long long)c->cls[k].n_pe + c->cls[k].n_sh);
-    return m;
-}
 
 ClassDev class_dev(const HostClass &k)
 {
@@ -633,7 +629,7 @@ NetPairArgs net_args(const exx_ctx *c)
     n.pair_gc = c->d_gc.p;
     n.out_off = c->d_off.p;
     n.rhs = c->d_rhs.p;
-    n.slot_n = c->slot_n;
+    n.rhs_off = c->d_rhs_off.p;
     n.wave_begin = 0;
     n.vout = c->d_vout.p;
     n.h2 = std::cbrt(c->h[0] * c->h[1] * c->h[2]);
@@ -841,12 +837,12 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms, c
     int4 *gc = (int4 *)dev((size_t)n * sizeof(int4));
     int4 *org = (int4 *)dev(sizeof(int4));
     int2 *ij = (int2 *)dev((size_t)n * sizeof(int2));
-    long long *off = (long long *)dev((size_t)n * 8);
+    long long *off = (long long *)dev((size_t)n * 8), *boff = (long long *)dev((size_t)n * 8);
     hipEvent_t ev[2] = {};
     int best = -1;
     float best_ms = 0.f;
     std::vector<float> times(cands.size(), 1e30f);
-    if (allocs.size() != (size_t)(15 + (mixed ? 1 : 0) + (mg ? 1 : 0)) || hipEventCreate(&ev[0]) != hipSuccess ||
+    if (allocs.size() != (size_t)(16 + (mixed ? 1 : 0) + (mg ? 1 : 0)) || hipEventCreate(&ev[0]) != hipSuccess ||
         hipEventCreate(&ev[1]) != hipSuccess) {
         release();
         for (auto &x : ev) if (x) (void)hipEventDestroy(x);
@@ -878,15 +874,17 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms, c
         }
     }
     std::vector<int2> hij((size_t)n, int2{0, 0});
-    std::vector<long long> hoff((size_t)n);
+    std::vector<long long> hoff((size_t)n), hboff((size_t)n);
     for (int p = 0; p < n; ++p) hoff[p] = (long long)p * per_pair;
+    for (int p = 0; p < n; ++p) hboff[p] = (long long)p * slot_n;
     bool ok = hipMemset(phi, 0, ngrid * 8) == hipSuccess &&
               hipMemset(rhs, 0x3f, (size_t)n * slot_n * 8) == hipSuccess &&    // b = 4.8e-4 everywhere
               hipMemset(vout, 0, (size_t)n * per_pair * 8) == hipSuccess &&
               hipMemcpy(gc, hgc.data(), hgc.size() * sizeof(int4), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemcpy(ij, hij.data(), hij.size() * sizeof(int2), hipMemcpyHostToDevice) == hipSuccess &&
               hipMemset(org, 0, sizeof(int4)) == hipSuccess &&
-              hipMemcpy(off, hoff.data(), hoff.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
+              hipMemcpy(off, hoff.data(), hoff.size() * 8, hipMemcpyHostToDevice) == hipSuccess &&
+              hipMemcpy(boff, hboff.data(), hboff.size() * 8, hipMemcpyHostToDevice) == hipSuccess;
     SolveArgs a{};
     a.pair_gc = gc;
     a.pair_ij = ij;
@@ -900,6 +898,7 @@ int autotune(exx_ctx *c, const std::vector<Candidate> &cands, double *tune_ms, c
     a.ngrid = (long long)ngrid;
     a.vout = vout;
     a.rhs = rhs;
+    a.rhs_off = boff;
     a.scratch = scr;
     a.scratch32 = scr32;
     a.slot_n = slot_n;
@@ -1341,6 +1340,7 @@ exx_status pairs_common(exx_ctx *c, int32_t n_orb, const double *C, const double
     for (int i = 0; i < 3 * n_orb; ++i)
         if (!std::isfinite(C[i])) return fail(c, EXX_EINVAL, "centre coordinate %d is not finite", i);
     c->out_off.clear();
+    c->rhs_off.clear();
     c->owner.clear();
     c->centers.assign(C, C + 3 * (size_t)n_orb);
     {
@@ -1451,14 +1451,29 @@ exx_status pairs_common(exx_ctx *c, int32_t n_orb, const double *C, const double
     if (mg && (st = dev_reserve(c, c->d_mg_scratch, (size_t)c->slots * mg_slot_doubles(c))) != EXX_OK)
         return st;
     // Waves of pairs: each wave holds its pairs' right-hand sides and
-    // potentials.  One wave when everything fits; otherwise D is summed wave
-    // by wave into FP64 partial sums (so the result does not depend on the
-    // split) and the waves are as large as the device allows.
+    // potentials, each pair at its own class's size.  One wave when
+    // everything fits; otherwise D is summed wave by wave into FP64 partial
+    // sums (so the result does not depend on the split) and the waves are as
+    // large as the device allows.
     {
         size_t freeb = 0, totalb = 0;
         HIPCHK(c, hipMemGetInfo(&freeb, &totalb));
-        const long long v_max = max_me(c);
-        const size_t per_pair = (size_t)(c->slot_n + v_max) * sizeof(double);
+        // a pair's b takes its n_pe rounded up to 64 elements (512-byte aligned)
+        auto rhs_len = [&](int64_t p) -> long long { return ((long long)c->cls[c->gc[p].w].n_pe + 63) / 64 * 64; };
+        std::vector<size_t> pre((size_t)c->n_pairs + 1, 0);   // bytes of pairs [0, p)
+        size_t small = SIZE_MAX;
+        for (int64_t p = 0; p < c->n_pairs; ++p) {
+            const HostClass &k = c->cls[c->gc[p].w];
+            const size_t b = (size_t)(rhs_len(p) + k.n_pe + k.n_sh) * sizeof(double);
+            pre[p + 1] = pre[p] + b;
+            small = std::min(small, b);
+        }
+        // every wave of w consecutive pairs (the last may hold fewer) within cap
+        auto fits = [&](int64_t w, size_t cap) {
+            for (int64_t w0 = 0; w0 < c->n_pairs; w0 += w)
+                if (pre[std::min<int64_t>(w0 + w, c->n_pairs)] - pre[w0] > cap) return false;
+            return true;
+        };
         const size_t have = (c->d_rhs.n + c->d_vout.n + c->d_dacc.n) * sizeof(double);
         // keep 2 GiB free, and room for the model or the guess history
         size_t keep = (size_t)2 << 30;
@@ -1471,29 +1486,41 @@ exx_status pairs_common(exx_ctx *c, int32_t n_orb, const double *C, const double
             const size_t levels = c->prm.guess == EXX_GUESS_PREVIOUS ? 2 : 4;   // kept + the one being written
             keep += levels * hist > held ? levels * hist - held : 0;
         }
-        const size_t budget = freeb + have > keep ? freeb + have - keep : 0;
+        // dev_reserve adds 1/33 to large buffers: potentials, right-hand
+        // sides and partial sums together get budget * 34/33 at most
+        const size_t budget = freeb + have > keep ? (freeb + have - keep) / 34 * 33 : 0;
         const size_t dacc = (size_t)c->n_orb * c->box_vol * sizeof(double);
         int64_t w = c->n_pairs;
-        if ((size_t)c->n_pairs * per_pair > budget)
-            w = budget > dacc ? (int64_t)((budget - dacc) / per_pair) : 0;
+        if (!fits(w, budget)) {
+            // from an upper bound down: w no larger than cap over the largest
+            // pair's bytes fits, so this ends
+            const size_t cap = budget > dacc ? budget - dacc : 0;
+            w = std::min<int64_t>(c->n_pairs - 1, (int64_t)(cap / small));
+            while (w > 0 && !fits(w, cap)) w = std::min<int64_t>(w - 1, w * 127 / 128);
+        }
         if (c->prm.wave_pairs > 0) w = std::min<int64_t>(w, c->prm.wave_pairs);
         if (c->prm.keep_intermediates) w = c->n_pairs;
         w = std::min<int64_t>(w, c->n_pairs);
         if (w < 1) return fail(c, EXX_ENOMEM, "no device memory left for a wave of pairs");
         c->wave_n = (int)w;
-        // potentials: offsets relative to the pair's wave
+        // potentials and right-hand sides: offsets relative to the pair's wave
         c->out_off.assign((size_t)c->n_pairs, 0);
-        long long vmax = 0;
+        c->rhs_off.assign((size_t)c->n_pairs, 0);
+        long long vmax = 0, bmax = 0;
         for (int64_t w0 = 0; w0 < c->n_pairs; w0 += w) {
-            long long o = 0;
+            long long o = 0, ob = 0;
             for (int64_t p = w0; p < std::min<int64_t>(w0 + w, c->n_pairs); ++p) {
                 c->out_off[p] = o;
+                c->rhs_off[p] = ob;
                 o += (long long)c->cls[c->gc[p].w].n_pe + c->cls[c->gc[p].w].n_sh;
+                ob += rhs_len(p);
             }
             vmax = std::max(vmax, o);
+            bmax = std::max(bmax, ob);
         }
         c->vout_n = vmax;
         if ((st = upload(c, c->d_off, c->out_off)) != EXX_OK) return st;
+        if ((st = upload(c, c->d_rhs_off, c->rhs_off)) != EXX_OK) return st;
         // CG queue: within each wave the pairs of the larger classes first, so
         // that the longest solves do not start last and leave a tail where
         // most of the GPU idles.  Each pair's result does not depend on when
@@ -1513,7 +1540,7 @@ exx_status pairs_common(exx_ctx *c, int32_t n_orb, const double *C, const double
         }
         if ((st = dev_reserve(c, c->d_clock, (size_t)2 * ((c->n_pairs + w - 1) / w))) != EXX_OK) return st;
         if ((st = dev_reserve(c, c->d_vout, (size_t)vmax)) != EXX_OK) return st;
-        if ((st = dev_reserve(c, c->d_rhs, (size_t)w * c->slot_n)) != EXX_OK) return st;
+        if ((st = dev_reserve(c, c->d_rhs, (size_t)bmax)) != EXX_OK) return st;
         if (w < c->n_pairs) {
             if ((st = dev_reserve(c, c->d_dacc, (size_t)c->n_orb * c->box_vol)) != EXX_OK) return st;
         } else {
@@ -1606,6 +1633,7 @@ static exx_status solve_impl(exx_ctx *c, const void *phi, void *stream, bool fix
     a.scratch = scr64;
     a.scratch32 = scr32;
     a.rhs = c->d_rhs.p;
+    a.rhs_off = c->d_rhs_off.p;
     a.rho_keep = c->prm.keep_intermediates ? c->d_rho_keep.p : nullptr;
     a.slot_n = c->slot_n;
     a.q_out = c->d_q.p;
@@ -2024,7 +2052,7 @@ static exx_status exx_debug_pair_body(exx_ctx *c, int64_t pair, double *v_pe, do
     if (v_shell) HIPCHK(c, hipMemcpy(v_shell, v + k.n_pe, (size_t)k.n_sh * 8, hipMemcpyDeviceToHost));
     if (q_lm) HIPCHK(c, hipMemcpy(q_lm, c->d_q.p + pair * NLM, NLM * 8, hipMemcpyDeviceToHost));
     if (rho) HIPCHK(c, hipMemcpy(rho, c->d_rho_keep.p + (size_t)pair * c->slot_n, (size_t)k.n_pe * 8, hipMemcpyDeviceToHost));
-    if (rhs) HIPCHK(c, hipMemcpy(rhs, c->d_rhs.p + (size_t)pair * c->slot_n, (size_t)k.n_pe * 8, hipMemcpyDeviceToHost));
+    if (rhs) HIPCHK(c, hipMemcpy(rhs, c->d_rhs.p + c->rhs_off[pair], (size_t)k.n_pe * 8, hipMemcpyDeviceToHost));
     return EXX_OK;
 }
 
@@ -2252,7 +2280,7 @@ void exx_destroy(exx_ctx *c)
     (void)hipSetDevice(c->device);
     (void)hipDeviceSynchronize();
     for (auto &k : c->cls) free_class(k);
-    dev_free(c->d_ij); dev_free(c->d_gc); dev_free(c->d_off); dev_free(c->d_queue); dev_free(c->d_orb_ptr); dev_free(c->d_orb_pairs);
+    dev_free(c->d_ij); dev_free(c->d_gc); dev_free(c->d_off); dev_free(c->d_rhs_off); dev_free(c->d_queue); dev_free(c->d_orb_ptr); dev_free(c->d_orb_pairs);
     dev_free(c->d_vout); dev_free(c->d_q); dev_free(c->d_e); dev_free(c->d_relres); dev_free(c->d_scratch);
     dev_free(c->d_rhs); dev_free(c->d_rho_keep);
     dev_free(c->d_guess); dev_free(c->d_hist_off);

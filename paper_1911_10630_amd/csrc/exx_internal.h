@@ -142,7 +142,8 @@ struct SolveArgs {
     int nx, ny, nz;
     long long ngrid;
     double *vout;               // per pair: v on PE (n_pe) then v on shell (n_sh)
-    double *rhs;                // per wave pair: right-hand side b (slot_n each)
+    double *rhs;                // per wave pair: right-hand side b (n_pe, padded)
+    const long long *rhs_off;   // [n_pairs] offset of the pair's b in rhs (relative to its wave)
     double *rho_keep;           // optional per pair: pair density (slot_n each)
     double *scratch;            // per CG slot: r, p, Ap (slot_n each)
     long long slot_n;           // elements per array (max n_pe, padded)
@@ -291,8 +292,8 @@ struct NetPairArgs {
     ClassDev cls[KMAX];         // subdomain classes (unused ones have n_pe = 0)
     const int4 *pair_gc;
     const long long *out_off;
-    const double *rhs;          // right-hand sides of the wave, slot_n each
-    long long slot_n;
+    const double *rhs;          // right-hand sides of the wave
+    const long long *rhs_off;   // [n_pairs] offset of the pair's b in rhs (relative to its wave)
     int wave_begin;
     double *vout;               // read (training targets) or written (guess)
     double h2;                  // output scale: RMS(v) ~ RMS(b) h^2

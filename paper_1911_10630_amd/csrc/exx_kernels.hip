@@ -145,7 +145,7 @@ __global__ __launch_bounds__(PREP_BLOCK) void k_prep(SolveArgs a)
     const int2 ij = a.pair_ij[pair];
     const ClassDev g = a.cls[pg.w];
     double *v_sh = a.vout + a.out_off[pair] + g.n_pe;
-    double *bv = a.rhs + (long long)blockIdx.x * a.slot_n;
+    double *bv = a.rhs + a.rhs_off[pair];
     double *keep = a.rho_keep ? a.rho_keep + (long long)pair * a.slot_n : nullptr;
     const double hx = a.h[0], hy = a.h[1], hz = a.h[2];
     const long long oi = (long long)ij.x * a.box.vol, oj = (long long)ij.y * a.box.vol;
@@ -229,7 +229,7 @@ __device__ void cg_one_pair(const SolveArgs &a, int pair, long long slot, double
     const int2 ij = a.pair_ij[pair];
     const ClassDev g = a.cls[pg.w];
     double *xv = a.vout + a.out_off[pair];
-    const double *bv = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
+    const double *bv = a.rhs + a.rhs_off[pair];
     double *r = a.scratch + slot * 3 * a.slot_n;
     double *p = r + a.slot_n;
     double *ap = p + a.slot_n;
@@ -1216,7 +1216,7 @@ __device__ __forceinline__ void cg_zmarch_pair(const SolveArgs &a, int pair, lon
     const int4 pg = a.pair_gc[pair];
     const ClassDev g = a.cls[pg.w];
     double *x = a.vout + a.out_off[pair];
-    const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
+    const double *b = a.rhs + a.rhs_off[pair];
     const StencilW<double> w64 = stencil_w<double>(a);
     const bool guess = (MIXED || MODE == CG_MG || MODE == CG_MG_MIXED) ? a.guess != 0 : MODE == CG_FP64_GUESS;
     int it = 0, conv = 0, outer = 0;

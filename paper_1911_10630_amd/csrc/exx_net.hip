@@ -454,7 +454,7 @@ __global__ __launch_bounds__(256) void k_net_sumsq(NetPairArgs a, const int *pai
     const int k = blockIdx.y;
     const int pair = pair_of(pairs, base, k);
     const ClassDev &g = a.cls[a.pair_gc[pair].w];
-    const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
+    const double *b = a.rhs + a.rhs_off[pair];
     double ss = 0.0;
     for (int q = blockIdx.x * 256 + threadIdx.x; q < g.n_pe; q += kScaleChunks * 256) ss += b[q] * b[q];
     for (int off = 32; off > 0; off >>= 1) ss += __shfl_xor(ss, off);
@@ -493,7 +493,7 @@ __global__ __launch_bounds__(256) void k_net_cells(NetPairArgs a, const int *pai
     const int cls = a.pair_gc[pair].w;
     const ClassDev &g = a.cls[cls];
     const unsigned char *bnd = a.bnd[cls];
-    const double *b = a.rhs + (long long)(pair - a.wave_begin) * a.slot_n;
+    const double *b = a.rhs + a.rhs_off[pair];
     const double *x = a.vout + a.out_off[pair];
     const double s = scale[k];
     const double inv = s > 0.0 ? 1.0 / s : 0.0;

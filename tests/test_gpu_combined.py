@@ -84,7 +84,8 @@ def test_water512_classes_learned_fp32_multigrid_md():
     tr.close()
     del phi_t
 
-    ctx = X.Exx.from_workload(wl, **kw)
+    # in waves of 30,000 pairs: the whole list would fit in one
+    ctx = X.Exx.from_workload(wl, wave_pairs=30000, **kw)
     ctx.load_model(blob)
     phi = torch.empty((2048,) + tuple(reversed(wl.box)), dtype=torch.float32, device="cuda:0")
     D = torch.empty_like(phi)
