@@ -565,6 +565,11 @@ def main():
                             pairs_build_s=round(t_pairs, 3), solve_ms=round(st["solve_ms"], 2),
                             cg_clock_ms=round(st["cg_clock_ms"], 2), cg_event_ms=round(st["cg_ms"], 2),
                             dxx_in_energy_potential_ms=round(st["dxx_ms"], 2), energy_ms=round(st["energy_ms"], 3),
+                            dxx_bytes=st["dxx_bytes"],
+                            # algorithmic rate of the D kernel; in waves D is summed inside the solve
+                            # and the timing above covers only the final rounding
+                            dxx_gbs=round(st["dxx_bytes"] / st["dxx_ms"] / 1e6, 1)
+                            if st["n_waves"] == 1 and st["dxx_ms"] > 0 else None,
                             cg_bytes=st["cg_bytes"], grid=st["solve_grid"], block=st["solve_block"],
                             cg_cols=st["cg_cols"], cg_bands=st["cg_bands"], waves=st["n_waves"],
                             autotuned_variants=st["tuned"], tune_ms=round(st["tune_ms"], 1),
