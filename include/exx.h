@@ -195,7 +195,10 @@ exx_status exx_setup(const exx_params *p, int device, exx_ctx **out);
  * through a periodic cell list and equals the plain double loop bit for bit.
  * centers: host, [n_orb][3] bohr, copied.  *n_pairs receives the pair count.
  * The pairs are split into waves sized from the device memory free at this
- * call (2 GiB kept free): allocate the orbital and D buffers before it.
+ * call (2 GiB kept free): allocate the orbital and D buffers before it.  A
+ * wave holds its pairs' right-hand sides and potentials, each at its own
+ * class's size (n_pe rounded up to 64, and n_pe + n_shell, FP64); with
+ * more than one wave D's FP64 partial sums ([n_orb][box]) are held too.
  * EXX_ENOMEM if not even one pair fits. */
 exx_status exx_pairs(exx_ctx *ctx, int32_t n_orb, const double *centers, int64_t *n_pairs);
 
